@@ -1,0 +1,153 @@
+"""Benchmark: spin-flip attempts per second of the parallel-tempering sampler on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
+
+A step is one PT cycle over the whole batch: sweeps_per_exchange Metropolis sweeps of
+every replica of every instance, the energy bookkeeping, then one replica-exchange
+step with its statistics and accumulators.  All state is resident in device memory
+when the timed region starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# MI355X: 256 compute units, 4 SIMDs x 16 lanes each (64 lanes of 32-bit integer work per
+# clock per CU), 2.4 GHz peak engine clock.
+CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
+PEAK_INT_OPS = CUS * LANES_PER_CU * CLOCK_HZ  # 3.93e13 full-rate 32-bit VALU ops/s
+MUL64_ISSUE_COST = 4  # a 32x32->64 multiply issues at quarter rate
+
+
+def ops_per_flip(avg_degree: float) -> float:
+    """Algorithmic 32-bit VALU work of one Metropolis attempt, in full-rate issue slots:
+    a quarter of a Philox4x32-10 call (10 rounds of two 32x32->64 products and two
+    three-input xors), the spatial field (a multiply-add per neighbour), the time field
+    (one add) and the table index, compare and select (five)."""
+    philox = 10 * (2 * MUL64_ISSUE_COST + 2) / 4.0
+    return philox + 2.0 * avg_degree + 1.0 + 5.0
+
+
+def workload(config: int):
+    import workloads as W
+    if config == 1:
+        insts = [W.config1()]
+        desc = "config1: N=8 3-regular, M=16, R=8, T in [0.1,2.0], Gamma=1"
+    elif config == 2:
+        insts = [W.config2()]
+        desc = "config2: N=128 6-regular, J in +-{1,2,3}, h=0, M=64, R=32, T in [0.05,3.0], Gamma=1"
+    elif config == 3:
+        insts = W.config3()
+        desc = ("config3: 512 instances, N~U[32,512], d~U{4..8}, M in {32,64,128}, "
+                "R in {16,32,64}, T in [0.1,3.0], Gamma=1")
+    elif config == 4:
+        insts = [W.config4()]
+        desc = "config4: 8x8x16 periodic cubic N=1024, J=+-1, h=0, M=256, R=64, Gamma=1.5"
+    else:
+        raise SystemExit(f"unknown config {config}")
+    return insts, desc
+
+
+def cpu_baseline(insts, seed, k, budget_s=15.0):
+    """The oracle as it stands, single-threaded on the host, on a bounded sample: whole
+    PT cycles of the first instance (index 0), as many as fit in about budget_s."""
+    import oracle
+    inst = insts[0]
+    ref = oracle.OracleChain(inst, seed, index=0)
+    t0 = time.perf_counter()
+    ref.run(k, 1)
+    one = time.perf_counter() - t0
+    cycles = max(1, int(budget_s / max(one, 1e-6)) - 1)
+    t0 = time.perf_counter()
+    ref.run(k, cycles)
+    dt = time.perf_counter() - t0
+    flips = cycles * k * inst.flips_per_sweep
+    return {"value": flips / dt, "unit": "spin-flip attempts/s", "cores": 1, "kind": "oracle",
+            "sample": f"instance 0 of the workload ({inst.name}), {cycles} cycles x {k} sweeps "
+                      f"+ exchange, {dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-replicas", type=int, default=0)
+    ap.add_argument("--block-threads", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "instances and replicas are independent between exchanges, so a multi-GPU "
+              "run would shard them, but no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_1004_0023_amd import ptqmc
+
+    torch.cuda.set_device(0)
+    insts, desc = workload(args.config)
+    k = W.sweeps_per_exchange(args.config)
+    seed = W.sampler_seed(args.config)
+    steps = args.steps if args.steps is not None else W.total_sweeps(args.config) // k
+    print(f"bench: {desc}; {steps} steps of {k} sweeps + exchange", file=sys.stderr, flush=True)
+
+    s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=ptqmc.PT_FLAG_TIMING,
+                      tile_replicas=args.tile_replicas, block_threads=args.block_threads)
+    s.run(args.warmup)
+    s.sync()
+    s.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(steps)
+    s.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    info = s.info()
+    flips_per_step = k * int(info["flips_per_sweep"])
+    value = steps * flips_per_step / elapsed
+    avg_sweep_s = info["sweep_ms"] / max(1, info["sweep_launches"]) / 1e3
+    ops_launch = 0.0
+    for inst in insts:
+        ops_launch += k * inst.flips_per_sweep * ops_per_flip(2.0 * inst.n_edges / inst.N)
+    achieved = ops_launch / avg_sweep_s / 1e12 if avg_sweep_s > 0 else 0.0
+    peak = PEAK_INT_OPS / 1e12
+    out = {
+        "metric": "spin-flip attempts/s",
+        "value": value,
+        "unit": "spin-flip attempts/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": desc, "instances": len(insts), "sweeps_per_exchange": k,
+                   "flips_per_step": flips_per_step, "tiles": info["n_tiles"],
+                   "block_threads": info["block_threads"], "lds_bytes": info["lds_bytes"],
+                   "sweep_kernel_ms": avg_sweep_s * 1e3,
+                   "exchange_kernel_ms": info["exchange_ms"] / max(1, info["exchange_launches"])},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak, "traffic": None},
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(insts, seed, k)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

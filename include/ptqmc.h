@@ -1,0 +1,198 @@
+/*
+ * ptqmc.h -- C ABI of the MI355X (gfx950) parallel-tempering quantum Monte Carlo sampler.
+ *
+ * The library runs the data-parallel hot path of parallel tempering (PT) over
+ * Suzuki-Trotter replicas of transverse-field Ising problems: Metropolis single-spin
+ * sweeps of many independent Markov chains ("replicas"), each at its own rung of a
+ * ladder, alternating with swaps between neighbouring rungs (paper, Section 2; the
+ * quantum system is represented by M coupled copies of the classical one, Section 6).
+ * Its loop is the paper's Figure 6 -- allocate, sweep k times, swap, measure, free --
+ * with every step on the GPU and the state resident in device memory between calls.
+ *
+ * Model, for one instance with N spins, M Trotter slices and R replicas:
+ *   E(s)  = sum_{edges (i,j)} J_ij s_i s_j + sum_i h_i s_i            (integer)
+ *   E_cl  = sum_k E(s^k),   C = sum_k sum_i s_i^k s_i^{(k+1) mod M}   (C = 0 if M == 1)
+ *   S_r   = b_r E_cl - K_r C   is the action of a replica at rung r; weight exp(-S_r).
+ * For a temperature ladder at transverse field Gamma: b_r = beta_r / M and
+ * K_r = -1/2 ln tanh(beta_r Gamma / M).  A rung is only the pair (b_r, K_r).
+ *
+ * Trajectory contract.  For a given (instances, seed) the sampler's trajectory is
+ * unique: spins, swap decisions, integer energies, labels and accumulators do not
+ * depend on launch shapes, tiles, encodings or the number of calls they are split over.
+ *   sweep t      : for p in slice parities (2 if M >= 2, else 1), for g in colours,
+ *                  attempt a flip at every (replica c, slice k = p mod 2, site i of colour
+ *                  g).  Field f = h_i + sum_j J_ij s_j^k, t' = s_i^{k-1} + s_i^{k+1};
+ *                  dE = -2 s f, dC = -2 s t', dS = b*dE - K*dC (FP64, no fused ops);
+ *                  flip iff u <= thr(dS), u = word (i mod 4) of
+ *                  Philox4x32-10(ctr = (k*ceil(N/4) + i/4, t, c, n), key = (lo(seed), hi(seed))).
+ *   thr(dS)      : 2^32-1 if dS <= 0, else clamp(floor(exp(-dS) * 2^32), 1, 2^32-1) - 1,
+ *                  with exp evaluated by a fixed sequence of IEEE operations.
+ *   exchange e   : pairs (r, r+1), r = e mod 2, e mod 2 + 2, ...; with x, y the replicas at
+ *                  r, r+1: D = (b_r - b_{r+1})(E_x - E_y) - (K_r - K_{r+1})(C_x - C_y);
+ *                  swap the rung labels iff u <= thr(-D), u = word 0 of
+ *                  Philox(ctr = (r, e, 0, n), key = (lo(seed), hi(seed) ^ 0x53574150)).
+ *                  Then: the replica at rung 0 labelled DOWN completes a round trip and
+ *                  becomes UP (NONE becomes UP); the replica at rung R-1 labelled UP becomes
+ *                  DOWN; per rung, E_cl, C and their squares are accumulated.
+ *   init         : s = +1 iff the top bit of word (i mod 4) of
+ *                  Philox(ctr = (k*ceil(N/4) + i/4, 0, c, n), key = (lo, hi ^ 0x494E4954)).
+ * Vertex labels are used as given: a colour-contiguous labelling makes the four sites of
+ * a Philox block share a colour class and is the fast layout.
+ *
+ * Conventions.  Every function returning int returns PT_OK (0) or a negative PT_E*
+ * code; nothing aborts or throws across this boundary.  pt_last_error() returns a
+ * thread-local message for the last failure on the calling thread.  A context is used
+ * by one host thread at a time.  All calls that launch work are asynchronous on the
+ * context's stream; pt_observables, pt_get_spins, pt_save and pt_sync synchronise it.
+ */
+#ifndef PTQMC_H
+#define PTQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PT_OK 0
+#define PT_EINVAL (-1)  /* invalid argument or instance                                  */
+#define PT_ENOMEM (-2)  /* device or host allocation failed, or workspace too small       */
+#define PT_EHIP (-3)    /* a HIP runtime call failed (the message names the call and code) */
+#define PT_ELAUNCH (-4) /* a kernel could not be launched in any fallback configuration    */
+#define PT_ESTATE (-5)  /* call not valid in the context's state (e.g. bad checkpoint)     */
+
+/* spin encodings (the trajectory is identical under every encoding) */
+#define PT_INT8 0       /* one int8 (+1/-1) per spin                                       */
+#define PT_BITPACK32 1  /* 32 replicas per uint32 word: bit (c mod 32) of word c/32 at (k, i) */
+
+/* round-trip labels */
+#define PT_LABEL_NONE 0
+#define PT_LABEL_UP 1
+#define PT_LABEL_DOWN 2
+
+/* option flags */
+#define PT_FLAG_TIMING 0x1u        /* bracket every sweep/exchange launch with HIP events   */
+#define PT_FLAG_NO_GRAPH 0x2u      /* pt_run launches eagerly instead of replaying a graph  */
+#define PT_FLAG_INJECT_LAUNCH_OOR_ONCE 0x4u /* test hook: the first sweep launch is treated
+                                             as out of resources, exercising the fallback */
+
+typedef struct pt_ctx pt_ctx;
+
+/* One problem instance and its ladder.  The caller owns every pointer (host memory)
+ * and may free it after pt_init returns: the library copies what it needs.
+ *   N >= 1 spins; M == 1 (classical) or M even >= 2 slices; R >= 2 replicas.
+ *   edges: n_edges pairs (edge_i[e], edge_j[e]) with 0 <= i < j < N, no duplicates;
+ *   edge_J[e] the coupling; h[i] the field; color[i] < n_colors a proper colouring
+ *   (no edge joins two sites of one colour).  max_i(|h_i| + sum_j |J_ij|) <= 1023.
+ *   rung_b[r], rung_K[r] finite, K > 0 when M >= 2 (ignored when M == 1); rung 0 is
+ *   the first (coldest) rung of the ladder.                                          */
+typedef struct {
+    int32_t N, M, R, n_edges, n_colors;
+    const int32_t *edge_i, *edge_j;
+    const int8_t *edge_J;
+    const int8_t *h;
+    const uint8_t *color;
+    const double *rung_b, *rung_K;
+} pt_instance;
+
+/* Sampler options.  seed keys every draw; sweeps_per_exchange (k >= 1) is the number of
+ * sweeps per pt_run cycle.  tile_replicas and block_threads override the tuner when
+ * positive (0 = choose automatically). */
+typedef struct {
+    uint64_t seed;
+    int32_t sweeps_per_exchange;
+    int32_t encoding;
+    uint32_t flags;
+    int32_t tile_replicas;
+    int32_t block_threads;
+} pt_options;
+
+/* Observables of one instance, written into caller-owned host arrays.  Any pointer may
+ * be NULL to skip that array.  Sizes: [R] unless noted. */
+typedef struct {
+    int64_t *E_cl, *C;        /* by replica slot                                      */
+    int32_t *rung_of;         /* slot -> rung                                         */
+    int32_t *replica_of;      /* rung -> slot                                         */
+    uint64_t *acc, *att;      /* [R-1] accepted / attempted swaps of pair (r, r+1)    */
+    uint64_t *roundtrips;     /* by slot                                              */
+    int8_t *label;            /* by slot                                              */
+    int64_t *sumE, *sumC, *sumE2, *sumC2; /* by rung, accumulated at every exchange   */
+    uint64_t t, e, n_acc;     /* sweeps done, exchange steps done, accumulated samples */
+} pt_obs;
+
+/* Launch and timing record of a context. */
+typedef struct {
+    int32_t n_instances, n_tiles, block_threads, lds_bytes;
+    int32_t max_tile_replicas, fallbacks, encoding, device_cus;
+    uint64_t flips_per_sweep;         /* sum over instances of R*N*M                 */
+    double sweep_ms;                  /* summed event time of timed sweep launches   */
+    int64_t sweep_launches;           /* number of timed sweep launches              */
+    double exchange_ms;
+    int64_t exchange_launches;
+} pt_info;
+
+/* Device bytes pt_init needs for these instances and options (for a caller-provided
+ * workspace).  Does not touch the GPU. */
+int pt_workspace_bytes(const pt_instance *inst, int32_t n_inst, const pt_options *opt,
+                       size_t *bytes);
+
+/* Validate the instances, build neighbour lists, colour blocks and threshold tables,
+ * place the state in device memory and draw the initial spins (then energies from
+ * scratch).  stream: a hipStream_t to run on, or NULL for a library-owned stream.
+ * workspace: device memory of at least pt_workspace_bytes() bytes that the caller keeps
+ * alive until pt_free (the library never frees it), or NULL to let the library
+ * allocate.  On error *out is NULL and nothing is leaked. */
+int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_options *opt,
+            void *stream, void *workspace, size_t workspace_bytes);
+
+/* n_sweeps >= 0 sweeps of every replica of every instance (t += n_sweeps). */
+int pt_sweep(pt_ctx *ctx, int32_t n_sweeps);
+
+/* One replica-exchange step of every instance (e += 1). */
+int pt_exchange(pt_ctx *ctx);
+
+/* n_cycles x (sweeps_per_exchange sweeps, then one exchange step). */
+int pt_run(pt_ctx *ctx, int32_t n_cycles);
+
+/* Wait for all work queued on the context's stream. */
+int pt_sync(pt_ctx *ctx);
+
+/* Copy instance inst's observables to the host (synchronising). */
+int pt_observables(pt_ctx *ctx, int32_t inst, pt_obs *out);
+
+/* Copy instance inst's spins to host int8 out[R][M][N] by replica slot (synchronising). */
+int pt_get_spins(pt_ctx *ctx, int32_t inst, int8_t *out);
+
+/* Replace instance inst's spins from host int8 in[R][M][N] (values must be +1/-1) and
+ * recompute its E_cl and C. */
+int pt_set_spins(pt_ctx *ctx, int32_t inst, const int8_t *in);
+
+/* Checkpoint: with buf == NULL, *len receives the size; otherwise the mutable state is
+ * written to buf (*len >= size).  pt_load restores it into a context created with the
+ * same instances and options; the continued run is identical to an uninterrupted one. */
+int pt_save(pt_ctx *ctx, void *buf, size_t *len);
+int pt_load(pt_ctx *ctx, const void *buf, size_t len);
+
+/* Tuning and timing record; pt_timing_reset zeroes the timing fields (synchronising). */
+int pt_get_info(pt_ctx *ctx, pt_info *out);
+int pt_timing_reset(pt_ctx *ctx);
+
+void pt_free(pt_ctx *ctx);
+const char *pt_strerror(int code);
+const char *pt_last_error(void);
+
+/* The acceptance threshold thr(dS) of the trajectory contract as the library's host code
+ * builds its tables (no GPU needed). */
+uint32_t pt_threshold(double dS);
+
+/* The same rule evaluated by the device code that decides swaps, for n values: dS and
+ * out are device pointers; runs on stream (NULL: default stream) and synchronises. */
+int pt_threshold_device(const double *dS, uint32_t *out, int32_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTQMC_H */

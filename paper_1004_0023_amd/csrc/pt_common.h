@@ -1,0 +1,157 @@
+// pt_common.h -- device layout and arithmetic shared by the library's host code and its
+// gfx950 kernels: Philox4x32-10, the deterministic exponential, the acceptance threshold,
+// and the descriptors that place every instance in the device workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace ptq {
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten rounds, each two
+// 32x32->64 products (multipliers 0xD2511F53, 0xCD9E8D57) whose high halves are xor-ed
+// with the other two words and the round key; keys advance by 0x9E3779B9, 0xBB67AE85.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+constexpr uint32_t kDomainSwap = 0x53574150u;  // 'SWAP'
+constexpr uint32_t kDomainInit = 0x494E4954u;  // 'INIT'
+
+struct Words4 {
+    uint32_t w[4];
+};
+
+__host__ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                    uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t pb = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    Words4 o;
+    o.w[0] = c0;
+    o.w[1] = c1;
+    o.w[2] = c2;
+    o.w[3] = c3;
+    return o;
+}
+
+// ------------------------------------------------------------------ exp and thresholds
+// exp(x), x <= 0, from IEEE multiply/add/floor/ldexp only (every operation separately
+// rounded; contraction is off for this file), so host and device agree bitwise:
+// Cody-Waite reduction by ln 2 split as c1 (32 significant bits, so n*c1 is exact) plus
+// c2, then the degree-12 Taylor polynomial of exp(r) in Horner form, scaled by 2^n.
+// For x < -32 the value cannot affect any 32-bit threshold and 0 is returned.
+__host__ __device__ __forceinline__ double exp_det(double x)
+{
+    const double kLog2e = 0x1.71547652b82fep+0;
+    const double kLn2Hi = 0x1.62e42feep-1;           // 2977044471 / 2^32
+    const double kLn2Lo = 0x1.a39ef35793c76p-33;     // ln 2 - kLn2Hi, rounded
+    if (!(x >= -32.0)) return 0.0;
+    const double n = floor(x * kLog2e + 0.5);
+    const double r = (x - n * kLn2Hi) - n * kLn2Lo;
+    // 1/j! for j = 12 down to 0, each the double nearest the exact rational
+    double p = 0x1.1eed8eff8d898p-29;
+    p = p * r + 0x1.ae64567f544e4p-26;
+    p = p * r + 0x1.27e4fb7789f5cp-22;
+    p = p * r + 0x1.71de3a556c734p-19;
+    p = p * r + 0x1.a01a01a01a01ap-16;
+    p = p * r + 0x1.a01a01a01a01ap-13;
+    p = p * r + 0x1.6c16c16c16c17p-10;
+    p = p * r + 0x1.1111111111111p-7;
+    p = p * r + 0x1.5555555555555p-5;
+    p = p * r + 0x1.5555555555555p-3;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)n);
+}
+
+// Metropolis min(1, exp(-dS)) as a 32-bit threshold: accept iff u <= thr.
+__host__ __device__ __forceinline__ uint32_t threshold(double dS)
+{
+    if (dS <= 0.0) return 0xFFFFFFFFu;
+    double v = floor(ldexp(exp_det(-dS), 32));
+    if (v > 4294967295.0) v = 4294967295.0;
+    if (v < 1.0) v = 1.0;
+    return (uint32_t)v - 1u;
+}
+
+// ------------------------------------------------------------------ device layout
+
+// Table of thresholds of one rung, indexed [b][f + F][tau] with b = (s > 0), f the local
+// field, tau = t'/2 + 1 in {0, 1, 2}: size 2 * (2F + 1) * 3 words.
+__host__ __device__ __forceinline__ int table_words(int F) { return 2 * (2 * F + 1) * 3; }
+
+struct InstDesc {
+    int32_t N, M, R, Npad;   // Npad = N rounded up to 4: row stride of a slice in bytes
+    int32_t Nq;              // ceil(N / 4): Philox blocks per slice
+    int32_t F;               // max |local field|
+    int32_t n_colors;
+    int32_t unit_j;          // all |J| == 1
+    int32_t rep_base;        // first global replica / rung index
+    int32_t pair_base;       // first global pair index (R - 1 pairs)
+    int32_t adj_base;        // first neighbour entry
+    int32_t site_base;       // first site (offsets have N + 1 entries at site_base + n)
+    int32_t blk_base;        // first colour-block entry
+    int32_t cls_base;        // first class offset (n_colors + 1 entries)
+    int32_t tbl_base;        // first threshold word (R tables)
+    int32_t tbl_words;       // words per rung table
+    int64_t spin_base;       // first spin byte ([R][M][Npad])
+};
+
+struct Tile {
+    int32_t inst;  // instance
+    int32_t c0;    // first replica slot
+    int32_t P;     // replicas in the tile
+    int32_t pad;
+};
+
+struct Counters {
+    uint64_t t;      // sweeps done
+    uint64_t e;      // exchange steps done
+    uint64_t n_acc;  // accumulated samples
+    uint64_t pad;
+};
+
+// Pointers into the workspace (all device addresses).
+struct DevState {
+    // immutable after init
+    const InstDesc *inst;
+    const int32_t *adj;       // neighbour entry: (j & 0xFFFF) | (J << 16)
+    const int32_t *adj_off;   // per site: first entry (N + 1 per instance)
+    const int16_t *hfield;    // per site
+    const uint32_t *blk;      // colour-block entry: (blk << 4) | mask
+    const int32_t *cls_off;   // per colour: first block entry (n_colors + 1 per instance)
+    const uint32_t *tbl;      // threshold tables
+    const double *db;         // per pair: b_r - b_{r+1}
+    const double *dK;         // per pair: K_r - K_{r+1}
+    const Tile *tiles;
+    // mutable state
+    int8_t *spins;
+    int64_t *E;       // per replica slot
+    int64_t *C;
+    int32_t *rung_of;
+    int32_t *label;
+    uint64_t *rt;
+    int32_t *replica_of;  // per rung
+    int64_t *sumE, *sumC, *sumE2, *sumC2;
+    uint64_t *acc, *att;  // per pair
+    Counters *ctr;        // per instance
+};
+
+}  // namespace ptq

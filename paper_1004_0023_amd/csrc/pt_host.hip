@@ -1,0 +1,885 @@
+// pt_host.hip -- host side of the C ABI declared in include/ptqmc.h.
+//
+// One context holds a batch of instances.  All state lives in one device workspace:
+// an immutable region (instance descriptors, neighbour lists, colour blocks, threshold
+// tables, pair constants, tiles) followed by the mutable state region (spins, energies,
+// permutation, labels, swap statistics, accumulators, counters) that pt_save/pt_load
+// copy as one block.  Every sweep and exchange runs on the device; the host only
+// launches, so a PT cycle never crosses PCIe (unlike the per-cycle copies of the
+// paper's Figure 6).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ptqmc.h"
+#include "pt_internal.h"
+
+using namespace ptq;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(PT_EHIP, std::string(what) + ": " + hipGetErrorString(e) + " (hip error " +
+                             std::to_string((int)e) + ")");
+}
+
+#define HIP_TRY(call)                                     \
+    do {                                                  \
+        hipError_t e__ = (call);                          \
+        if (e__ != hipSuccess) return hip_fail(e__, #call); \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr uint32_t kMagic = 0x51505450u;  // checkpoint tag
+constexpr uint32_t kVersion = 1;
+constexpr int kMaxField = 1023;
+
+// Host copy of everything that is uploaded once, plus the layout of the workspace.
+struct Plan {
+    std::vector<InstDesc> desc;
+    std::vector<int32_t> adj, adj_off, cls_off, rep_inst;
+    std::vector<int16_t> hfield;
+    std::vector<uint32_t> blk, tbl;
+    std::vector<double> db, dK;
+    std::vector<int32_t> n_adj, n_blk;  // per instance
+    int64_t total_reps = 0, total_pairs = 0, spin_bytes = 0;
+    uint64_t flips_per_sweep = 0;
+    // byte offsets in the workspace
+    size_t o_inst, o_adj, o_off, o_h, o_blk, o_cls, o_tbl, o_db, o_dK, o_tiles, o_repinst;
+    size_t o_state;  // start of the mutable region
+    size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
+        o_sumC2, o_acc, o_att, o_ctr;
+    size_t state_bytes, total_bytes;
+};
+
+int validate(const pt_instance &in, int idx)
+{
+    auto bad = [&](const std::string &m) {
+        return fail(PT_EINVAL, "instance " + std::to_string(idx) + ": " + m);
+    };
+    if (in.N < 1 || in.N > 65535) return bad("N must be in [1, 65535]");
+    if (in.M < 1 || (in.M > 1 && (in.M % 2))) return bad("M must be 1 or even");
+    if (in.M > 4096) return bad("M must be <= 4096");
+    if (in.R < 2) return bad("R must be >= 2");
+    if (in.n_edges < 0) return bad("n_edges < 0");
+    if (in.n_colors < 1 || in.n_colors > 256) return bad("n_colors must be in [1, 256]");
+    if (!in.h || !in.color || !in.rung_b || !in.rung_K) return bad("null array");
+    if (in.n_edges > 0 && (!in.edge_i || !in.edge_j || !in.edge_J)) return bad("null edge array");
+    for (int i = 0; i < in.N; ++i)
+        if (in.color[i] >= in.n_colors) return bad("colour out of range");
+    std::vector<int64_t> fsum(in.N);
+    for (int i = 0; i < in.N; ++i) fsum[i] = std::abs((int)in.h[i]);
+    std::vector<std::pair<int, int>> seen;
+    seen.reserve(in.n_edges);
+    for (int e = 0; e < in.n_edges; ++e) {
+        const int i = in.edge_i[e], j = in.edge_j[e];
+        if (i < 0 || j >= in.N || i >= j) return bad("edge " + std::to_string(e) + " needs 0 <= i < j < N");
+        if (in.color[i] == in.color[j]) return bad("improper colouring at edge " + std::to_string(e));
+        fsum[i] += std::abs((int)in.edge_J[e]);
+        fsum[j] += std::abs((int)in.edge_J[e]);
+        seen.emplace_back(i, j);
+    }
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return bad("duplicate edge");
+    for (int i = 0; i < in.N; ++i)
+        if (fsum[i] > kMaxField) return bad("local field bound exceeds 1023");
+    for (int r = 0; r < in.R; ++r) {
+        if (!std::isfinite(in.rung_b[r])) return bad("non-finite b");
+        if (in.M >= 2 && (!std::isfinite(in.rung_K[r]) || !(in.rung_K[r] > 0.0)))
+            return bad("K must be finite and > 0 when M >= 2");
+    }
+    return PT_OK;
+}
+
+// Threshold table of one rung: [b][f + F][tau], b = (s > 0), tau = t'/2 + 1.
+void build_table(uint32_t *out, int F, int M, double b, double K)
+{
+    const double Keff = (M >= 2) ? K : 0.0;
+    for (int bb = 0; bb < 2; ++bb) {
+        const int s = bb ? 1 : -1;
+        for (int f = -F; f <= F; ++f) {
+            for (int tau = 0; tau < 3; ++tau) {
+                const int tp = 2 * (tau - 1);
+                const int64_t dE = -2 * (int64_t)s * f;
+                const int64_t dC = -2 * (int64_t)s * tp;
+                const double dS = b * (double)dE - Keff * (double)dC;
+                out[(bb * (2 * F + 1) + (f + F)) * 3 + tau] = threshold(dS);
+            }
+        }
+    }
+}
+
+int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
+{
+    if (!inst || n_inst < 1) return fail(PT_EINVAL, "need at least one instance");
+    P = Plan();
+    int64_t rep = 0, pair = 0, adjb = 0, siteb = 0, blkb = 0, clsb = 0, tblb = 0, spinb = 0;
+    for (int n = 0; n < n_inst; ++n) {
+        int rc = validate(inst[n], n);
+        if (rc) return rc;
+        const pt_instance &in = inst[n];
+        InstDesc d{};
+        d.N = in.N;
+        d.M = in.M;
+        d.R = in.R;
+        d.Npad = (in.N + 3) & ~3;
+        d.Nq = (in.N + 3) / 4;
+        d.n_colors = in.n_colors;
+        // neighbour lists
+        std::vector<int32_t> deg(in.N + 1, 0);
+        bool unit = true;
+        for (int e = 0; e < in.n_edges; ++e) {
+            deg[in.edge_i[e] + 1]++;
+            deg[in.edge_j[e] + 1]++;
+            if (std::abs((int)in.edge_J[e]) != 1) unit = false;
+        }
+        for (int i = 0; i < in.N; ++i) deg[i + 1] += deg[i];
+        std::vector<int32_t> fill(in.N, 0), entries(2 * (size_t)in.n_edges);
+        for (int e = 0; e < in.n_edges; ++e) {
+            const int i = in.edge_i[e], j = in.edge_j[e];
+            const int32_t J = in.edge_J[e];
+            entries[deg[i] + fill[i]++] = (j & 0xFFFF) | (int32_t)((uint32_t)J << 16);
+            entries[deg[j] + fill[j]++] = (i & 0xFFFF) | (int32_t)((uint32_t)J << 16);
+        }
+        int F = 0;
+        for (int i = 0; i < in.N; ++i) {
+            int fs = std::abs((int)in.h[i]);
+            for (int e = deg[i]; e < deg[i + 1]; ++e) fs += std::abs(entries[e] >> 16);
+            F = std::max(F, fs);
+        }
+        d.F = F;
+        d.unit_j = unit ? 1 : 0;
+        // colour blocks: for colour g, every Philox block (4 consecutive labels) holding a
+        // site of colour g, with the mask of those sites
+        std::vector<int32_t> cls(in.n_colors + 1, 0);
+        std::vector<uint32_t> blocks;
+        for (int g = 0; g < in.n_colors; ++g) {
+            cls[g] = (int32_t)blocks.size();
+            for (int q = 0; q < d.Nq; ++q) {
+                uint32_t mask = 0;
+                for (int b = 0; b < 4; ++b) {
+                    const int i = 4 * q + b;
+                    if (i < in.N && in.color[i] == g) mask |= 1u << b;
+                }
+                if (mask) blocks.push_back(((uint32_t)q << 4) | mask);
+            }
+        }
+        cls[in.n_colors] = (int32_t)blocks.size();
+        d.tbl_words = table_words(F);
+        d.rep_base = (int32_t)rep;
+        d.pair_base = (int32_t)pair;
+        d.adj_base = (int32_t)adjb;
+        d.site_base = (int32_t)siteb;
+        d.blk_base = (int32_t)blkb;
+        d.cls_base = (int32_t)clsb;
+        d.tbl_base = (int32_t)tblb;
+        d.spin_base = spinb;
+        P.desc.push_back(d);
+        P.adj.insert(P.adj.end(), entries.begin(), entries.end());
+        P.adj_off.insert(P.adj_off.end(), deg.begin(), deg.end());
+        for (int i = 0; i < in.N; ++i) P.hfield.push_back(in.h[i]);
+        P.blk.insert(P.blk.end(), blocks.begin(), blocks.end());
+        P.cls_off.insert(P.cls_off.end(), cls.begin(), cls.end());
+        const size_t t0 = P.tbl.size();
+        P.tbl.resize(t0 + (size_t)in.R * d.tbl_words);
+        for (int r = 0; r < in.R; ++r)
+            build_table(P.tbl.data() + t0 + (size_t)r * d.tbl_words, F, in.M, in.rung_b[r],
+                        in.rung_K[r]);
+        for (int r = 0; r + 1 < in.R; ++r) {
+            P.db.push_back(in.rung_b[r] - in.rung_b[r + 1]);
+            P.dK.push_back(in.M >= 2 ? in.rung_K[r] - in.rung_K[r + 1] : 0.0);
+        }
+        for (int c = 0; c < in.R; ++c) P.rep_inst.push_back(n);
+        P.n_adj.push_back(2 * in.n_edges);
+        P.n_blk.push_back((int32_t)blocks.size());
+        P.flips_per_sweep += (uint64_t)in.R * in.N * in.M;
+        rep += in.R;
+        pair += in.R - 1;
+        adjb += 2 * (int64_t)in.n_edges;
+        siteb += in.N;
+        blkb += (int64_t)blocks.size();
+        clsb += in.n_colors + 1;
+        tblb += (int64_t)in.R * d.tbl_words;
+        spinb += (int64_t)align_up((size_t)in.R * in.M * d.Npad, 16);
+        if (rep > (1 << 30) || tblb > (1ll << 31) || adjb > (1ll << 31))
+            return fail(PT_EINVAL, "batch too large");
+    }
+    P.total_reps = rep;
+    P.total_pairs = pair;
+    P.spin_bytes = spinb;
+    // layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1), 256);
+        return at;
+    };
+    P.o_inst = take(P.desc.size() * sizeof(InstDesc));
+    P.o_adj = take(P.adj.size() * 4);
+    P.o_off = take(P.adj_off.size() * 4);
+    P.o_h = take(P.hfield.size() * 2);
+    P.o_blk = take(P.blk.size() * 4);
+    P.o_cls = take(P.cls_off.size() * 4);
+    P.o_tbl = take(P.tbl.size() * 4);
+    P.o_db = take(P.db.size() * 8);
+    P.o_dK = take(P.dK.size() * 8);
+    P.o_tiles = take((size_t)rep * sizeof(Tile));
+    P.o_repinst = take((size_t)rep * 4);
+    P.o_state = o;
+    P.o_spins = take((size_t)spinb);
+    P.o_E = take((size_t)rep * 8);
+    P.o_C = take((size_t)rep * 8);
+    P.o_rung = take((size_t)rep * 4);
+    P.o_label = take((size_t)rep * 4);
+    P.o_rt = take((size_t)rep * 8);
+    P.o_repof = take((size_t)rep * 4);
+    P.o_sumE = take((size_t)rep * 8);
+    P.o_sumC = take((size_t)rep * 8);
+    P.o_sumE2 = take((size_t)rep * 8);
+    P.o_sumC2 = take((size_t)rep * 8);
+    P.o_acc = take((size_t)pair * 8);
+    P.o_att = take((size_t)pair * 8);
+    P.o_ctr = take((size_t)n_inst * sizeof(Counters));
+    P.state_bytes = o - P.o_state;
+    P.total_bytes = o;
+    return PT_OK;
+}
+
+struct CkptHeader {
+    uint32_t magic, version;
+    uint64_t state_bytes;
+    uint64_t seed;
+    int32_t n_inst, encoding;
+    uint64_t flips_per_sweep;
+};
+
+}  // namespace
+
+struct pt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *ws = nullptr;
+    bool own_ws = false;
+    Plan plan;
+    DevState st{};
+    const int32_t *d_rep_inst = nullptr;
+    pt_options opt{};
+    uint32_t key_flip0 = 0, key_flip1 = 0, key_swap0 = 0, key_swap1 = 0;
+    // launch shape
+    std::vector<Tile> tiles;
+    int block_threads = 256;
+    int lds_bytes = 0;
+    int max_P = 1;
+    int lds_limit = 65536;
+    int cus = 256;
+    int fallbacks = 0;
+    bool inject_pending = false;
+    // graph of whole cycles for pt_run
+    hipGraphExec_t graph = nullptr;
+    int graph_cycles = 0;
+    // timing
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> sweep_ev, exch_ev;  // indices into ev_pool
+    size_t ev_used = 0;
+    double sweep_ms = 0, exch_ms = 0;
+    int64_t sweep_n = 0, exch_n = 0;
+};
+
+namespace {
+
+int n_inst_of(const pt_ctx *c) { return (int)c->plan.desc.size(); }
+
+// Choose tiles: P replicas of one instance per workgroup, P limited by LDS, and sized so
+// the batch yields a few workgroups per CU when it can (the paper's chain packing,
+// Section 5, stops packing once multiprocessors would go idle).
+int build_tiles(pt_ctx *c, int force_P)
+{
+    const Plan &P = c->plan;
+    // the tile list is uploaded from c->tiles: let any earlier upload finish first
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int64_t total_bytes = 0;
+    for (const auto &d : P.desc) total_bytes += (int64_t)d.R * d.M * d.Npad;
+    const int64_t target_tiles = 4ll * c->cus;
+    int64_t target_bytes = std::max<int64_t>(total_bytes / target_tiles, 4096);
+    target_bytes = std::min<int64_t>(target_bytes, 64 * 1024);
+    c->tiles.clear();
+    int lds_max = 0, maxP = 1;
+    for (int n = 0; n < (int)P.desc.size(); ++n) {
+        const InstDesc &d = P.desc[n];
+        int pmax = 0;
+        for (int p = d.R; p >= 1; --p)
+            if (sweep_tile_lds_bytes(d, P.n_adj[n], P.n_blk[n], p) <= c->lds_limit) {
+                pmax = p;
+                break;
+            }
+        if (pmax < 1)
+            return fail(PT_EINVAL, "instance " + std::to_string(n) +
+                                       ": one replica does not fit in LDS (N*M too large)");
+        int p = (int)std::max<int64_t>(1, target_bytes / ((int64_t)d.M * d.Npad));
+        if (force_P > 0) p = force_P;
+        p = std::min(p, pmax);
+        for (int c0 = 0; c0 < d.R; c0 += p) {
+            Tile t{n, c0, std::min(p, d.R - c0), 0};
+            c->tiles.push_back(t);
+            lds_max = std::max(lds_max, sweep_tile_lds_bytes(d, P.n_adj[n], P.n_blk[n], t.P));
+            maxP = std::max(maxP, t.P);
+        }
+    }
+    // largest tiles first: the device dispatches workgroups roughly in order, so the
+    // longest work starts earliest (the paper's "hardest chains first" work pool)
+    std::stable_sort(c->tiles.begin(), c->tiles.end(), [&](const Tile &a, const Tile &b) {
+        const InstDesc &da = P.desc[a.inst], &db = P.desc[b.inst];
+        return (int64_t)a.P * da.M * da.N > (int64_t)b.P * db.M * db.N;
+    });
+    c->lds_bytes = lds_max;
+    c->max_P = maxP;
+    HIP_TRY(hipMemcpyAsync(c->ws + P.o_tiles, c->tiles.data(), c->tiles.size() * sizeof(Tile),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(sweep_kernel_set_lds(c->lds_bytes));
+    return PT_OK;
+}
+
+void drop_graph(pt_ctx *c)
+{
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_cycles = 0;
+}
+
+int event_pair(pt_ctx *c, int &a, int &b)
+{
+    while (c->ev_pool.size() < c->ev_used + 2) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    a = (int)c->ev_used++;
+    b = (int)c->ev_used++;
+    return PT_OK;
+}
+
+// Accumulate the elapsed times of recorded event pairs (synchronises).
+int harvest_events(pt_ctx *c)
+{
+    if (c->ev_used == 0) return PT_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto &p : c->sweep_ev) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[p.first], c->ev_pool[p.second]));
+        c->sweep_ms += ms;
+        c->sweep_n++;
+    }
+    for (auto &p : c->exch_ev) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[p.first], c->ev_pool[p.second]));
+        c->exch_ms += ms;
+        c->exch_n++;
+    }
+    c->sweep_ev.clear();
+    c->exch_ev.clear();
+    c->ev_used = 0;
+    return PT_OK;
+}
+
+bool out_of_resources(hipError_t e)
+{
+    return e == hipErrorLaunchOutOfResources || e == hipErrorOutOfMemory ||
+           e == hipErrorInvalidConfiguration;
+}
+
+// Launch n sweeps of every tile; on a resource failure halve the tile (and, at one
+// replica per tile, the workgroup) and retry, as the paper's Figure 7 halves its chain
+// packing when a launch runs out of registers.
+int enqueue_sweep(pt_ctx *c, int n_sweeps)
+{
+    if (n_sweeps <= 0) return PT_OK;
+    const bool timing = (c->opt.flags & PT_FLAG_TIMING) != 0;
+    for (;;) {
+        SweepLaunch L{};
+        L.st = c->st;
+        L.key0 = c->key_flip0;
+        L.key1 = c->key_flip1;
+        L.n_sweeps = n_sweeps;
+        L.n_tiles = (int)c->tiles.size();
+        L.block_threads = c->block_threads;
+        L.lds_bytes = c->lds_bytes;
+        int ea = -1, eb = -1;
+        if (timing) {
+            int rc = event_pair(c, ea, eb);
+            if (rc) return rc;
+            HIP_TRY(hipEventRecord(c->ev_pool[ea], c->stream));
+        }
+        hipError_t e;
+        if (c->inject_pending) {
+            c->inject_pending = false;
+            e = hipErrorLaunchOutOfResources;
+        } else {
+            e = launch_sweep(L, c->stream);
+        }
+        if (e == hipSuccess) {
+            if (timing) {
+                HIP_TRY(hipEventRecord(c->ev_pool[eb], c->stream));
+                c->sweep_ev.emplace_back(ea, eb);
+            }
+            return PT_OK;
+        }
+        if (timing) c->ev_used -= 2;
+        if (!out_of_resources(e)) return hip_fail(e, "sweep launch");
+        (void)hipGetLastError();
+        c->fallbacks++;
+        drop_graph(c);
+        if (c->max_P > 1) {
+            int rc = build_tiles(c, std::max(1, c->max_P / 2));
+            if (rc) return rc;
+        } else if (c->block_threads > 64) {
+            c->block_threads /= 2;
+        } else {
+            return fail(PT_ELAUNCH, std::string("sweep kernel cannot be launched: ") +
+                                        hipGetErrorString(e));
+        }
+    }
+}
+
+int enqueue_exchange(pt_ctx *c, uint32_t t_add)
+{
+    const bool timing = (c->opt.flags & PT_FLAG_TIMING) != 0;
+    int ea = -1, eb = -1;
+    if (timing) {
+        int rc = event_pair(c, ea, eb);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(c->ev_pool[ea], c->stream));
+    }
+    hipError_t e = launch_exchange(c->st, n_inst_of(c), c->key_swap0, c->key_swap1, t_add,
+                                   c->stream);
+    if (e != hipSuccess) return hip_fail(e, "exchange launch");
+    if (timing) {
+        HIP_TRY(hipEventRecord(c->ev_pool[eb], c->stream));
+        c->exch_ev.emplace_back(ea, eb);
+    }
+    return PT_OK;
+}
+
+int enqueue_cycle(pt_ctx *c)
+{
+    const int k = c->opt.sweeps_per_exchange;
+    int rc = enqueue_sweep(c, k);
+    if (rc) return rc;
+    return enqueue_exchange(c, (uint32_t)k);
+}
+
+int check_inst(pt_ctx *c, int32_t inst)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (inst < 0 || inst >= n_inst_of(c)) return fail(PT_EINVAL, "instance index out of range");
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pt_workspace_bytes(const pt_instance *inst, int32_t n_inst, const pt_options *opt,
+                       size_t *bytes)
+{
+    if (!bytes || !opt) return fail(PT_EINVAL, "null argument");
+    Plan P;
+    int rc = make_plan(inst, n_inst, P);
+    if (rc) return rc;
+    *bytes = P.total_bytes;
+    return PT_OK;
+}
+
+int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_options *opt,
+            void *stream, void *workspace, size_t workspace_bytes)
+{
+    if (!out || !opt) return fail(PT_EINVAL, "null argument");
+    *out = nullptr;
+    if (opt->sweeps_per_exchange < 1) return fail(PT_EINVAL, "sweeps_per_exchange must be >= 1");
+    if (opt->encoding != PT_INT8 && opt->encoding != PT_BITPACK32)
+        return fail(PT_EINVAL, "unknown encoding");
+    if (opt->block_threads < 0 || opt->block_threads > 1024 || (opt->block_threads % 64))
+        return fail(PT_EINVAL, "block_threads must be a multiple of 64 in [64, 1024] or 0");
+    if (opt->tile_replicas < 0) return fail(PT_EINVAL, "tile_replicas must be >= 0");
+    pt_ctx *c = new (std::nothrow) pt_ctx();
+    if (!c) return fail(PT_ENOMEM, "host allocation failed");
+    int rc = make_plan(inst, n_inst, c->plan);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    const Plan &P = c->plan;
+    c->opt = *opt;
+    c->inject_pending = (opt->flags & PT_FLAG_INJECT_LAUNCH_OOR_ONCE) != 0;
+    c->key_flip0 = (uint32_t)opt->seed;
+    c->key_flip1 = (uint32_t)(opt->seed >> 32);
+    c->key_swap0 = c->key_flip0;
+    c->key_swap1 = c->key_flip1 ^ kDomainSwap;
+    auto cleanup = [&](int code) {
+        pt_free(c);
+        return code;
+    };
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipGetDevice"));
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) ==
+            hipSuccess && v > 0)
+        c->lds_limit = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, c->device) ==
+            hipSuccess && v > 0)
+        c->cus = v;
+    if (workspace) {
+        if (workspace_bytes < P.total_bytes)
+            return cleanup(fail(PT_ENOMEM, "workspace smaller than pt_workspace_bytes()"));
+        if (((uintptr_t)workspace) % 256)
+            return cleanup(fail(PT_EINVAL, "workspace must be 256-byte aligned"));
+        c->ws = (char *)workspace;
+    } else {
+        e = hipMalloc((void **)&c->ws, P.total_bytes);
+        if (e != hipSuccess) return cleanup(fail(PT_ENOMEM, "hipMalloc of the workspace failed"));
+        c->own_ws = true;
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        e = hipStreamCreate(&c->stream);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamCreate"));
+        c->own_stream = true;
+    }
+    char *w = c->ws;
+    DevState &st = c->st;
+    st.inst = (const InstDesc *)(w + P.o_inst);
+    st.adj = (const int32_t *)(w + P.o_adj);
+    st.adj_off = (const int32_t *)(w + P.o_off);
+    st.hfield = (const int16_t *)(w + P.o_h);
+    st.blk = (const uint32_t *)(w + P.o_blk);
+    st.cls_off = (const int32_t *)(w + P.o_cls);
+    st.tbl = (const uint32_t *)(w + P.o_tbl);
+    st.db = (const double *)(w + P.o_db);
+    st.dK = (const double *)(w + P.o_dK);
+    st.tiles = (const Tile *)(w + P.o_tiles);
+    st.spins = (int8_t *)(w + P.o_spins);
+    st.E = (int64_t *)(w + P.o_E);
+    st.C = (int64_t *)(w + P.o_C);
+    st.rung_of = (int32_t *)(w + P.o_rung);
+    st.label = (int32_t *)(w + P.o_label);
+    st.rt = (uint64_t *)(w + P.o_rt);
+    st.replica_of = (int32_t *)(w + P.o_repof);
+    st.sumE = (int64_t *)(w + P.o_sumE);
+    st.sumC = (int64_t *)(w + P.o_sumC);
+    st.sumE2 = (int64_t *)(w + P.o_sumE2);
+    st.sumC2 = (int64_t *)(w + P.o_sumC2);
+    st.acc = (uint64_t *)(w + P.o_acc);
+    st.att = (uint64_t *)(w + P.o_att);
+    st.ctr = (Counters *)(w + P.o_ctr);
+    c->d_rep_inst = (const int32_t *)(w + P.o_repinst);
+
+    // one host image of the whole workspace, uploaded in a single copy
+    std::vector<char> img;
+    try {
+        img.assign(P.total_bytes, 0);
+    } catch (...) {
+        return cleanup(fail(PT_ENOMEM, "host staging allocation failed"));
+    }
+    auto put = [&](size_t off, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(img.data() + off, src, bytes);
+    };
+    put(P.o_inst, P.desc.data(), P.desc.size() * sizeof(InstDesc));
+    put(P.o_adj, P.adj.data(), P.adj.size() * 4);
+    put(P.o_off, P.adj_off.data(), P.adj_off.size() * 4);
+    put(P.o_h, P.hfield.data(), P.hfield.size() * 2);
+    put(P.o_blk, P.blk.data(), P.blk.size() * 4);
+    put(P.o_cls, P.cls_off.data(), P.cls_off.size() * 4);
+    put(P.o_tbl, P.tbl.data(), P.tbl.size() * 4);
+    put(P.o_db, P.db.data(), P.db.size() * 8);
+    put(P.o_dK, P.dK.data(), P.dK.size() * 8);
+    put(P.o_repinst, P.rep_inst.data(), P.rep_inst.size() * 4);
+    for (int n = 0; n < n_inst; ++n) {
+        const InstDesc &d = P.desc[n];
+        for (int r = 0; r < d.R; ++r) {
+            ((int32_t *)(img.data() + P.o_rung))[d.rep_base + r] = r;
+            ((int32_t *)(img.data() + P.o_repof))[d.rep_base + r] = r;
+            ((int32_t *)(img.data() + P.o_label))[d.rep_base + r] = (r == 0) ? PT_LABEL_UP : PT_LABEL_NONE;
+        }
+    }
+    e = hipMemcpyAsync(c->ws, img.data(), P.total_bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "upload"));
+    e = launch_init_spins(st, c->d_rep_inst, (int)P.total_reps, c->key_flip0,
+                          c->key_flip1 ^ kDomainInit, c->stream);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "init launch"));
+    e = launch_energy(st, c->d_rep_inst, 0, (int)P.total_reps, c->stream);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "energy launch"));
+    c->block_threads = opt->block_threads > 0 ? opt->block_threads : 256;
+    rc = build_tiles(c, opt->tile_replicas);
+    if (rc) return cleanup(rc);
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "init synchronise"));
+    *out = c;
+    return PT_OK;
+}
+
+int pt_sweep(pt_ctx *c, int32_t n_sweeps)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (n_sweeps < 0) return fail(PT_EINVAL, "n_sweeps < 0");
+    if (n_sweeps == 0) return PT_OK;
+    int rc = enqueue_sweep(c, n_sweeps);
+    if (rc) return rc;
+    hipError_t e = launch_advance(c->st, n_inst_of(c), (uint32_t)n_sweeps, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "advance launch");
+    return PT_OK;
+}
+
+int pt_exchange(pt_ctx *c)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    return enqueue_exchange(c, 0);
+}
+
+int pt_run(pt_ctx *c, int32_t n_cycles)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (n_cycles < 0) return fail(PT_EINVAL, "n_cycles < 0");
+    const bool eager = (c->opt.flags & (PT_FLAG_NO_GRAPH | PT_FLAG_TIMING)) != 0 ||
+                       c->inject_pending;
+    if (eager) {
+        for (int i = 0; i < n_cycles; ++i) {
+            int rc = enqueue_cycle(c);
+            if (rc) return rc;
+        }
+        return PT_OK;
+    }
+    // replay a captured graph of G cycles; the remainder runs eagerly
+    const int G = 16;
+    int done = 0;
+    if (n_cycles >= G) {
+        if (!c->graph) {
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            int rc = PT_OK;
+            for (int i = 0; i < G && rc == PT_OK; ++i) rc = enqueue_cycle(c);
+            hipError_t e = hipStreamEndCapture(c->stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                c->graph = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            c->graph_cycles = G;
+        }
+        for (; done + G <= n_cycles; done += G) HIP_TRY(hipGraphLaunch(c->graph, c->stream));
+    }
+    for (; done < n_cycles; ++done) {
+        int rc = enqueue_cycle(c);
+        if (rc) return rc;
+    }
+    return PT_OK;
+}
+
+int pt_sync(pt_ctx *c)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return PT_OK;
+}
+
+int pt_observables(pt_ctx *c, int32_t inst, pt_obs *o)
+{
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (!o) return fail(PT_EINVAL, "null output");
+    const InstDesc &d = c->plan.desc[inst];
+    const int R = d.R, b = d.rep_base, pb = d.pair_base;
+    char *w = c->ws;
+    const Plan &P = c->plan;
+    auto get = [&](void *dst, size_t off, size_t bytes) -> int {
+        if (!dst || !bytes) return PT_OK;
+        HIP_TRY(hipMemcpyAsync(dst, w + off, bytes, hipMemcpyDeviceToHost, c->stream));
+        return PT_OK;
+    };
+    std::vector<int32_t> label(R);
+    Counters ctr{};
+    if ((rc = get(o->E_cl, P.o_E + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(o->C, P.o_C + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(o->rung_of, P.o_rung + (size_t)b * 4, (size_t)R * 4))) return rc;
+    if ((rc = get(o->replica_of, P.o_repof + (size_t)b * 4, (size_t)R * 4))) return rc;
+    if ((rc = get(o->acc, P.o_acc + (size_t)pb * 8, (size_t)(R - 1) * 8))) return rc;
+    if ((rc = get(o->att, P.o_att + (size_t)pb * 8, (size_t)(R - 1) * 8))) return rc;
+    if ((rc = get(o->roundtrips, P.o_rt + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(label.data(), P.o_label + (size_t)b * 4, (size_t)R * 4))) return rc;
+    if ((rc = get(o->sumE, P.o_sumE + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(o->sumC, P.o_sumC + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(o->sumE2, P.o_sumE2 + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(o->sumC2, P.o_sumC2 + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(&ctr, P.o_ctr + (size_t)inst * sizeof(Counters), sizeof(Counters)))) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (o->label)
+        for (int r = 0; r < R; ++r) o->label[r] = (int8_t)label[r];
+    o->t = ctr.t;
+    o->e = ctr.e;
+    o->n_acc = ctr.n_acc;
+    return PT_OK;
+}
+
+int pt_get_spins(pt_ctx *c, int32_t inst, int8_t *out)
+{
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (!out) return fail(PT_EINVAL, "null output");
+    const InstDesc &d = c->plan.desc[inst];
+    const size_t rows = (size_t)d.R * d.M;
+    std::vector<int8_t> buf(rows * d.Npad);
+    HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + c->plan.o_spins + d.spin_base, buf.size(),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (size_t r = 0; r < rows; ++r) std::memcpy(out + r * d.N, buf.data() + r * d.Npad, d.N);
+    return PT_OK;
+}
+
+int pt_set_spins(pt_ctx *c, int32_t inst, const int8_t *in)
+{
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (!in) return fail(PT_EINVAL, "null input");
+    const InstDesc &d = c->plan.desc[inst];
+    const size_t rows = (size_t)d.R * d.M;
+    std::vector<int8_t> buf(rows * d.Npad, 0);
+    for (size_t r = 0; r < rows; ++r)
+        for (int i = 0; i < d.N; ++i) {
+            const int8_t v = in[r * d.N + i];
+            if (v != 1 && v != -1) return fail(PT_EINVAL, "spins must be +1 or -1");
+            buf[r * d.Npad + i] = v;
+        }
+    HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_spins + d.spin_base, buf.data(), buf.size(),
+                           hipMemcpyHostToDevice, c->stream));
+    hipError_t e = launch_energy(c->st, c->d_rep_inst, d.rep_base, d.R, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "energy launch");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return PT_OK;
+}
+
+int pt_save(pt_ctx *c, void *buf, size_t *len)
+{
+    if (!c || !len) return fail(PT_EINVAL, "null argument");
+    const size_t need = sizeof(CkptHeader) + c->plan.state_bytes;
+    if (!buf) {
+        *len = need;
+        return PT_OK;
+    }
+    if (*len < need) return fail(PT_EINVAL, "checkpoint buffer too small");
+    CkptHeader h{kMagic, kVersion, c->plan.state_bytes, c->opt.seed, n_inst_of(c),
+                 c->opt.encoding, c->plan.flips_per_sweep};
+    std::memcpy(buf, &h, sizeof h);
+    HIP_TRY(hipMemcpyAsync((char *)buf + sizeof h, c->ws + c->plan.o_state, c->plan.state_bytes,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *len = need;
+    return PT_OK;
+}
+
+int pt_load(pt_ctx *c, const void *buf, size_t len)
+{
+    if (!c || !buf) return fail(PT_EINVAL, "null argument");
+    if (len < sizeof(CkptHeader)) return fail(PT_ESTATE, "checkpoint too short");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    if (h.magic != kMagic || h.version != kVersion) return fail(PT_ESTATE, "not a checkpoint");
+    if (h.state_bytes != c->plan.state_bytes || h.n_inst != n_inst_of(c) ||
+        h.seed != c->opt.seed || h.flips_per_sweep != c->plan.flips_per_sweep ||
+        len != sizeof h + h.state_bytes)
+        return fail(PT_ESTATE, "checkpoint belongs to different instances or options");
+    HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_state, (const char *)buf + sizeof h, h.state_bytes,
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return PT_OK;
+}
+
+int pt_get_info(pt_ctx *c, pt_info *o)
+{
+    if (!c || !o) return fail(PT_EINVAL, "null argument");
+    int rc = harvest_events(c);
+    if (rc) return rc;
+    o->n_instances = n_inst_of(c);
+    o->n_tiles = (int)c->tiles.size();
+    o->block_threads = c->block_threads;
+    o->lds_bytes = c->lds_bytes;
+    o->max_tile_replicas = c->max_P;
+    o->fallbacks = c->fallbacks;
+    o->encoding = c->opt.encoding;
+    o->device_cus = c->cus;
+    o->flips_per_sweep = c->plan.flips_per_sweep;
+    o->sweep_ms = c->sweep_ms;
+    o->sweep_launches = c->sweep_n;
+    o->exchange_ms = c->exch_ms;
+    o->exchange_launches = c->exch_n;
+    return PT_OK;
+}
+
+int pt_timing_reset(pt_ctx *c)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    int rc = harvest_events(c);
+    if (rc) return rc;
+    c->sweep_ms = c->exch_ms = 0;
+    c->sweep_n = c->exch_n = 0;
+    return PT_OK;
+}
+
+void pt_free(pt_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *pt_strerror(int code)
+{
+    switch (code) {
+    case PT_OK: return "ok";
+    case PT_EINVAL: return "invalid argument";
+    case PT_ENOMEM: return "out of memory";
+    case PT_EHIP: return "HIP runtime error";
+    case PT_ELAUNCH: return "kernel launch failed in every configuration";
+    case PT_ESTATE: return "invalid state";
+    default: return "unknown error";
+    }
+}
+
+const char *pt_last_error(void) { return g_last_error.c_str(); }
+
+uint32_t pt_threshold(double dS) { return threshold(dS); }
+
+int pt_threshold_device(const double *dS, uint32_t *out, int32_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!dS || !out))) return fail(PT_EINVAL, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_threshold_eval(dS, out, n, s);
+    if (e != hipSuccess) return hip_fail(e, "threshold launch");
+    HIP_TRY(hipStreamSynchronize(s));
+    return PT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+"""Host-side checks of the C-ABI library that need no GPU: every symbol the header
+declares is exported, the host threshold rule matches the oracle's bit for bit, and
+invalid instances are rejected with PT_EINVAL before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptqmc.h")
+
+
+def _lib():
+    from paper_1004_0023_amd import ptqmc
+    if not os.path.exists(ptqmc.LIB_PATH):
+        pytest.skip("library not built")
+    return ptqmc
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pt_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("pt_init", "pt_sweep", "pt_exchange", "pt_run", "pt_observables", "pt_get_spins",
+                 "pt_save", "pt_load", "pt_free", "pt_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    ptqmc = _lib()
+    L = C.CDLL(ptqmc.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert sorted(ptqmc.EXPORTS) == declared_functions()
+
+
+def test_host_threshold_matches_oracle_bitwise():
+    ptqmc = _lib()
+    rng = np.random.default_rng(3)
+    xs = np.concatenate([np.linspace(-5, 40, 30001), rng.random(20000) * 45 - 2,
+                         [0.0, -0.0, 1e-300, 5e-324, 22.18070977791825, 32.0, 1e6]])
+    for x in xs:
+        assert ptqmc.threshold(float(x)) == oracle.metropolis_threshold(float(x)), x
+
+
+def _ws_bytes(inst_list, ptqmc, **kw):
+    """pt_workspace_bytes validates the batch without touching the GPU."""
+    L = ptqmc.lib()
+    keep = []
+    recs = (ptqmc._Instance * len(inst_list))()
+    for n, inst in enumerate(inst_list):
+        E = int(inst.edges.shape[0])
+        arrs = [np.ascontiguousarray(a, dt) for a, dt in (
+            (inst.edges[:, 0] if E else np.zeros(1), np.int32),
+            (inst.edges[:, 1] if E else np.zeros(1), np.int32),
+            (inst.J if E else np.zeros(1), np.int8), (inst.h, np.int8),
+            (inst.color, np.uint8), (inst.b, np.float64), (inst.K, np.float64))]
+        keep += arrs
+        recs[n] = ptqmc._Instance(inst.N, inst.M, inst.R, E, inst.n_colors,
+                                  *[a.ctypes.data for a in arrs])
+    opt = ptqmc._Options(1, kw.get("k", 1), 0, 0, 0, 0)
+    nb = C.c_size_t(0)
+    rc = L.pt_workspace_bytes(C.cast(recs, C.c_void_p), len(inst_list), C.byref(opt), C.byref(nb))
+    return rc, int(nb.value), L.pt_last_error().decode()
+
+
+def test_workspace_size_of_workloads():
+    ptqmc = _lib()
+    rc, nb, _ = _ws_bytes([W.config1()], ptqmc)
+    assert rc == 0 and nb > 1024
+    rc, nb2, _ = _ws_bytes([W.config2()], ptqmc)
+    assert rc == 0 and nb2 > 32 * 64 * 128
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda i: setattr(i, "M", 3), "M must be 1 or even"),
+    (lambda i: i.__dict__.update(R=1, b=i.b[:1], K=i.K[:1]), "R must be"),
+    (lambda i: i.color.__setitem__(slice(None), 0), "improper colouring"),
+    (lambda i: i.K.__setitem__(0, -1.0), "K must be finite"),
+    (lambda i: i.b.__setitem__(1, np.nan), "non-finite b"),
+    (lambda i: i.edges.__setitem__(0, [3, 3]), "needs 0 <= i < j"),
+])
+def test_invalid_instances_rejected(mutate, needle):
+    ptqmc = _lib()
+    inst = W.config1()
+    inst.edges = inst.edges.copy()
+    inst.color = inst.color.copy()
+    inst.b = inst.b.copy()
+    inst.K = inst.K.copy()
+    mutate(inst)
+    rc, _, msg = _ws_bytes([inst], ptqmc)
+    assert rc == ptqmc.PT_EINVAL and needle in msg
+
+
+def test_field_bound_rejected():
+    ptqmc = _lib()
+    inst = W.make_instance(3, np.array([[0, 1], [1, 2]]), np.array([127, 127], np.int8),
+                           np.array([0, 127, 0], np.int8), 2, [1.0, 2.0], 1.0)
+    rc, _, _ = _ws_bytes([inst], ptqmc)
+    assert rc == 0
+    big = [W.make_instance(9, np.array([[0, j] for j in range(1, 9)]),
+                           np.full(8, 127, np.int8), np.full(9, 127, np.int8), 2, [1.0, 2.0], 1.0)]
+    rc, _, msg = _ws_bytes(big, ptqmc)
+    assert rc == ptqmc.PT_EINVAL and "1023" in msg

@@ -1,0 +1,221 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Everything is integer or decided by identical IEEE operations, so the bar is bit
+equality: spins, integer energies, the replica permutation, labels, swap counts, round
+trips and accumulators.  The oracle runs one instance at a time with that instance's
+batch index.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("E_cl", "C", "rung_of", "replica_of", "acc", "att", "roundtrips", "label", "sumE",
+        "sumC", "sumE2", "sumC2")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ptqmc():
+    import torch
+    from paper_1004_0023_amd import ptqmc as P
+    torch.cuda.set_device(0)
+    P.lib()
+    return P
+
+
+def assert_same(sampler, n, ref, what=""):
+    got = sampler.observables(n)
+    want = ref.observables()
+    for k in KEYS:
+        assert np.array_equal(np.asarray(got[k]), np.asarray(want[k])), f"{what} inst {n}: {k}"
+    assert (got["t"], got["e"], got["n_acc"]) == (want["t"], want["e"], want["n_acc"]), what
+    assert np.array_equal(sampler.spins(n), ref.s), f"{what} inst {n}: spins"
+
+
+def edge_batch():
+    """Small instances covering the degenerate shapes: a lone spin, ragged N, classical
+    M=1, M=2, R=2 and odd R, a colouring that is not contiguous, large couplings and
+    fields, and a dense graph with many colours."""
+    rng = np.random.default_rng([1004, 23])
+    out = [
+        W.make_instance(1, np.zeros((0, 2), np.int32), np.zeros(0, np.int8),
+                        np.array([1], np.int8), 4, [0.5, 1.0, 2.0], 1.0, name="lone"),
+        W.random_small_instance(rng, 5, 6, 3, d=2, jmax=2, hmax=2, name="ragged"),
+        W.random_small_instance(rng, 10, 1, 4, d=3, jmax=3, hmax=1, name="classical"),
+        W.random_small_instance(rng, 7, 2, 2, d=2, jmax=1, hmax=0, name="m2r2"),
+        W.random_small_instance(rng, 13, 8, 5, d=4, jmax=7, hmax=5, relabel=False,
+                                name="noncontig"),
+        W.random_small_instance(rng, 12, 4, 6, d=11, jmax=1, hmax=1, name="dense"),
+        W.random_small_instance(rng, 33, 10, 7, d=3, jmax=120, hmax=100, t_min=2.0,
+                                t_max=60.0, name="bigfield"),
+    ]
+    return out
+
+
+def oracle_batch(insts, seed, k, cycles, extra_sweeps=0):
+    refs = []
+    for n, inst in enumerate(insts):
+        r = oracle.OracleChain(inst, seed, index=n)
+        r.run(k, cycles)
+        if extra_sweeps:
+            r.sweep(extra_sweeps)
+        refs.append(r)
+    return refs
+
+
+def test_device_threshold_bitwise(ptqmc):
+    say("case: device threshold rule vs oracle")
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([np.linspace(-5, 40, 50001), rng.random(50000) * 45 - 2,
+                         [0.0, 1e-300, 5e-324, 22.18070977791825, 32.0, 1e6, -1e6]])
+    got = ptqmc.threshold_device(xs)
+    want = np.array([oracle.metropolis_threshold(float(x)) for x in xs], dtype=np.uint32)
+    assert np.array_equal(got, want)
+
+
+def test_init_matches_oracle(ptqmc):
+    say("case: init, edge batch")
+    insts = edge_batch()
+    seed = 0xABCDEF0123456789
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=1) as s:
+        for n, inst in enumerate(insts):
+            assert_same(s, n, oracle.OracleChain(inst, seed, index=n), "init")
+
+
+def test_config1_full_run(ptqmc):
+    inst = W.config1()
+    seed = W.sampler_seed(1)
+    say("case: config 1, 10^4 sweeps, exchange every sweep")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=1) as s:
+        s.run(10_000)
+        ref = oracle.OracleChain(inst, seed)
+        ref.run(1, 10_000)
+        assert_same(s, 0, ref, "config1")
+
+
+def test_config2_truncated(ptqmc):
+    inst = W.config2()
+    seed = W.sampler_seed(2)
+    say("case: config 2, 40 cycles of 10 sweeps")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10) as s:
+        s.run(40)
+        ref = oracle.OracleChain(inst, seed)
+        ref.run(10, 40)
+        assert_same(s, 0, ref, "config2")
+
+
+@pytest.mark.parametrize("tile_replicas,block_threads", [(0, 0), (1, 64), (3, 512), (2, 1024)])
+def test_edge_batch_launch_shapes(ptqmc, tile_replicas, block_threads):
+    insts = edge_batch()
+    seed = 0x10040023
+    k, cycles = 3, 25
+    say(f"case: edge batch, tile_replicas={tile_replicas} block_threads={block_threads}")
+    refs = oracle_batch(insts, seed, k, cycles)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_replicas=tile_replicas,
+                       block_threads=block_threads) as s:
+        s.run(cycles)
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], f"shape({tile_replicas},{block_threads})")
+
+
+def test_split_calls_graph_and_eager_agree(ptqmc):
+    insts = edge_batch()[:4]
+    seed = 77
+    say("case: pt_run graph vs eager vs split sweep/exchange")
+    refs = oracle_batch(insts, seed, 2, 40, extra_sweeps=3)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=2) as a, \
+            ptqmc.Sampler(insts, seed, sweeps_per_exchange=2, flags=ptqmc.PT_FLAG_NO_GRAPH) as b, \
+            ptqmc.Sampler(insts, seed, sweeps_per_exchange=2) as c:
+        a.run(40)          # graph path (>= 16 cycles)
+        b.run(40)          # eager
+        for _ in range(40):
+            c.sweep(1)
+            c.sweep(1)
+            c.exchange()
+        for s in (a, b, c):
+            s.sweep(3)
+        for n in range(len(insts)):
+            for s, tag in ((a, "graph"), (b, "eager"), (c, "split")):
+                assert_same(s, n, refs[n], tag)
+
+
+def test_checkpoint_resume(ptqmc):
+    insts = edge_batch()[1:5]
+    seed = 2025
+    say("case: save/load resume")
+    refs = oracle_batch(insts, seed, 2, 30)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=2) as a:
+        a.run(13)
+        blob = a.save()
+        with ptqmc.Sampler(insts, seed, sweeps_per_exchange=2) as b:
+            b.load(blob)
+            b.run(17)
+            for n in range(len(insts)):
+                assert_same(b, n, refs[n], "resumed")
+        with ptqmc.Sampler(insts, seed + 1, sweeps_per_exchange=2) as other:
+            with pytest.raises(ptqmc.PTError):
+                other.load(blob)
+
+
+def test_set_spins_recomputes_energies(ptqmc):
+    inst = W.config1()
+    say("case: set_spins")
+    rng = np.random.default_rng(0)
+    s_new = rng.choice(np.array([-1, 1], np.int8), size=(inst.R, inst.M, inst.N))
+    with ptqmc.Sampler([inst], 5) as s:
+        s.set_spins(0, s_new)
+        assert np.array_equal(s.spins(0), s_new)
+        ref = oracle.OracleChain(inst, 5)
+        E, Cc = ref.energies(s_new)
+        obs = s.observables(0)
+        assert np.array_equal(obs["E_cl"], E) and np.array_equal(obs["C"], Cc)
+        with pytest.raises(ptqmc.PTError):
+            s.set_spins(0, np.zeros_like(s_new))
+
+
+def test_injected_launch_failure_falls_back(ptqmc):
+    insts = edge_batch()[4:6]
+    seed = 31
+    say("case: injected out-of-resources fallback")
+    refs = oracle_batch(insts, seed, 2, 10)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=2, tile_replicas=4,
+                       flags=ptqmc.PT_FLAG_INJECT_LAUNCH_OOR_ONCE) as s:
+        s.run(10)
+        assert s.info()["fallbacks"] >= 1
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], "fallback")
+
+
+def test_config3_full_batch_sampled(ptqmc):
+    """All 512 instances of the batched workload in the launch configuration the
+    benchmark uses; a sample of instances is re-run by the oracle, and the whole batch is
+    checked for invariants (energies equal a recomputation, permutations are bijections)."""
+    insts = W.config3()
+    seed = W.sampler_seed(3)
+    k, cycles = 10, 3
+    say("case: config 3, 512 instances, 3 cycles of 10 sweeps")
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k) as s:
+        s.run(cycles)
+        sample = [0, 1, 97, 255, 384, 511]
+        for n in sample:
+            ref = oracle.OracleChain(insts[n], seed, index=n)
+            ref.run(k, cycles)
+            assert_same(s, n, ref, "config3")
+        for n in range(0, 512, 37):
+            obs = s.observables(n)
+            ref = oracle.OracleChain(insts[n], seed, index=n, init=False)
+            E, Cc = ref.energies(s.spins(n))
+            assert np.array_equal(obs["E_cl"], E) and np.array_equal(obs["C"], Cc)
+            assert sorted(obs["replica_of"]) == list(range(insts[n].R))
+            assert np.array_equal(obs["rung_of"][obs["replica_of"]], np.arange(insts[n].R))
+            assert obs["t"] == k * cycles and obs["e"] == cycles
