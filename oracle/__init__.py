@@ -103,16 +103,17 @@ def metropolis_threshold(dS: float) -> int:
     return int(lib().or_metropolis_threshold(float(dS)))
 
 
-def flip_word(seed, n, N, c, t, k, i) -> int:
-    return int(lib().or_flip_word(seed, n, N, c, t, k, i))
+def flip_word(seed, n, M, c, t, k, i) -> int:
+    """Word of the flip attempt at (instance n, slot c, sweep t, slice k, site i)."""
+    return int(lib().or_flip_word(seed, n, M, c, t, k, i))
 
 
 def swap_word(seed, n, r, e) -> int:
     return int(lib().or_swap_word(seed, n, r, e))
 
 
-def init_spin(seed, n, N, c, k, i) -> int:
-    return int(lib().or_init_spin(seed, n, N, c, k, i))
+def init_spin(seed, n, M, c, k, i) -> int:
+    return int(lib().or_init_spin(seed, n, M, c, k, i))
 
 
 class OracleChain:

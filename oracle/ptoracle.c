@@ -26,7 +26,7 @@
  *   swaps: deterministic even/odd pairs (r, r+1), r = e mod 2, at exchange step e;
  *     swaps exchange the rung labels of the replicas, not their spins;
  *   random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), counter
- *     keyed by (site block, sweep, replica slot, instance) -- see or_flip_word.
+ *     keyed by (site and slice group, sweep, replica slot, instance) -- see or_flip_word.
  *
  * Floating point: FP64 throughout; build with -ffp-contract=off and without
  * -ffast-math so every product and sum is a separately rounded IEEE operation.
@@ -99,21 +99,38 @@ static void key_for(uint64_t seed, uint32_t domain, uint32_t key[2])
     key[1] = (uint32_t)(seed >> 32) ^ domain;
 }
 
-static int32_t quads(int32_t N) { return (N + 3) / 4; }
+/* Random counters of a spin draw.  Slice k has parity p = k mod 2 and index m = k div 2
+ * within its parity (M == 1: p = m = 0).  The four same-parity slices m = 4g..4g+3 of
+ * one site share one Philox call, word (m mod 4):
+ *   ctr0 = (2 i + p) * ceil(Mh / 4) + m div 4,  Mh = M / 2 (1 when M == 1). */
+static int32_t slice_groups(int32_t M) { int32_t Mh = (M >= 2) ? M / 2 : 1; return (Mh + 3) / 4; }
+
+static uint32_t spin_counter0(int32_t M, int32_t k, int32_t i)
+{
+    int32_t p = (M >= 2) ? (k & 1) : 0;
+    int32_t m = (M >= 2) ? (k >> 1) : 0;
+    return ((uint32_t)(2 * i + p)) * (uint32_t)slice_groups(M) + (uint32_t)(m >> 2);
+}
+
+static int32_t spin_word(int32_t M, int32_t k)
+{
+    int32_t m = (M >= 2) ? (k >> 1) : 0;
+    return m & 3;
+}
 
 /* Word used by the flip attempt of (instance n, slot c, sweep t, slice k, site i):
- * word (i mod 4) of Philox(ctr = (k*ceil(N/4) + i/4, t, c, n)). */
-uint32_t or_flip_word(uint64_t seed, int32_t n, int32_t N, int32_t c, uint64_t t,
+ * word (m mod 4) of Philox(ctr = (spin_counter0, t, c, n)). */
+uint32_t or_flip_word(uint64_t seed, int32_t n, int32_t M, int32_t c, uint64_t t,
                       int32_t k, int32_t i)
 {
     uint32_t key[2], ctr[4], out[4];
     key_for(seed, OR_DOMAIN_FLIP, key);
-    ctr[0] = (uint32_t)k * (uint32_t)quads(N) + (uint32_t)(i >> 2);
+    ctr[0] = spin_counter0(M, k, i);
     ctr[1] = (uint32_t)t;
     ctr[2] = (uint32_t)c;
     ctr[3] = (uint32_t)n;
     or_philox4x32_10(ctr, key, out);
-    return out[i & 3];
+    return out[spin_word(M, k)];
 }
 
 /* Word used by the swap attempt of pair (r, r+1) at exchange step e:
@@ -130,18 +147,18 @@ uint32_t or_swap_word(uint64_t seed, int32_t n, int32_t r, uint64_t e)
     return out[0];
 }
 
-/* Initial spin of (instance n, slot c, slice k, site i): the top bit of word (i mod 4)
- * of Philox(ctr = (k*ceil(N/4) + i/4, 0, c, n)) in the INIT domain; 1 -> +1. */
-int8_t or_init_spin(uint64_t seed, int32_t n, int32_t N, int32_t c, int32_t k, int32_t i)
+/* Initial spin of (instance n, slot c, slice k, site i): the top bit of word (m mod 4) of
+ * Philox(ctr = (spin_counter0, 0, c, n)) in the INIT domain; 1 -> +1. */
+int8_t or_init_spin(uint64_t seed, int32_t n, int32_t M, int32_t c, int32_t k, int32_t i)
 {
     uint32_t key[2], ctr[4], out[4];
     key_for(seed, OR_DOMAIN_INIT, key);
-    ctr[0] = (uint32_t)k * (uint32_t)quads(N) + (uint32_t)(i >> 2);
+    ctr[0] = spin_counter0(M, k, i);
     ctr[1] = 0u;
     ctr[2] = (uint32_t)c;
     ctr[3] = (uint32_t)n;
     or_philox4x32_10(ctr, key, out);
-    return (out[i & 3] >> 31) ? (int8_t)1 : (int8_t)-1;
+    return (out[spin_word(M, k)] >> 31) ? (int8_t)1 : (int8_t)-1;
 }
 
 /* ------------------------------------------------------------- deterministic exp */
@@ -267,7 +284,7 @@ void or_init(const or_instance *in, or_state *st, uint64_t seed)
     for (int32_t c = 0; c < R; ++c)
         for (int32_t k = 0; k < M; ++k)
             for (int32_t i = 0; i < N; ++i)
-                st->s[((size_t)c * M + k) * N + i] = or_init_spin(seed, in->index, N, c, k, i);
+                st->s[((size_t)c * M + k) * N + i] = or_init_spin(seed, in->index, M, c, k, i);
     for (int32_t r = 0; r < R; ++r) {
         st->replica_of[r] = r;
         st->rung_of[r] = r;
@@ -310,7 +327,7 @@ static void attempt_flip(const or_instance *in, const or_adj *adj, or_state *st,
     double K = (M >= 2) ? in->K[rung] : 0.0;
     double dS = b * (double)dE - K * (double)dC;
     uint32_t thr = or_metropolis_threshold(dS);
-    uint32_t u = or_flip_word(seed, in->index, N, c, t, k, i);
+    uint32_t u = or_flip_word(seed, in->index, M, c, t, k, i);
     if (u <= thr) {
         row[i] = (int8_t)(-s);
         st->E[c] += dE;

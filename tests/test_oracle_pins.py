@@ -110,16 +110,34 @@ def test_philox_matches_rocrand_engine(tmp_path):
 
 
 def test_draw_words_follow_counter_layout():
-    # flip word: word (i & 3) of Philox((k*ceil(N/4) + i//4, t, c, n), (lo, hi ^ 0))
+    # flip word: slice k = 2m + p; word (m & 3) of
+    # Philox(((2i + p) * ceil((M/2)/4) + m // 4, t, c, n), (lo, hi ^ 0))
     seed = 0x0123456789ABCDEF
-    N, n, c, t, k = 10, 5, 3, 77, 4
-    for i in range(N):
-        w = oracle.philox4x32_10([k * 3 + i // 4, t, c, n], [seed & 0xFFFFFFFF, seed >> 32])
-        assert oracle.flip_word(seed, n, N, c, t, k, i) == int(w[i & 3])
+    n, c, t = 5, 3, 77
+    for M in (1, 2, 6, 16):
+        Mh = M // 2 if M >= 2 else 1
+        G = (Mh + 3) // 4
+        for k in range(M):
+            p, m = (k % 2, k // 2) if M >= 2 else (0, 0)
+            for i in range(7):
+                w = oracle.philox4x32_10([(2 * i + p) * G + m // 4, t, c, n],
+                                         [seed & 0xFFFFFFFF, seed >> 32])
+                assert oracle.flip_word(seed, n, M, c, t, k, i) == int(w[m & 3])
+                w = oracle.philox4x32_10([(2 * i + p) * G + m // 4, 0, c, n],
+                                         [seed & 0xFFFFFFFF, (seed >> 32) ^ 0x494E4954])
+                assert oracle.init_spin(seed, n, M, c, k, i) == (1 if int(w[m & 3]) >> 31 else -1)
     w = oracle.philox4x32_10([6, 11, 0, n], [seed & 0xFFFFFFFF, (seed >> 32) ^ 0x53574150])
     assert oracle.swap_word(seed, n, 6, 11) == int(w[0])
-    w = oracle.philox4x32_10([k * 3 + 2, 0, c, n], [seed & 0xFFFFFFFF, (seed >> 32) ^ 0x494E4954])
-    assert oracle.init_spin(seed, n, N, c, k, 9) == (1 if int(w[1]) >> 31 else -1)
+
+
+def test_every_draw_uses_a_distinct_counter():
+    """Within one sweep of one replica every (slice, site) attempt reads a different
+    (counter, word) pair of the oracle's draw layout, so no random number is reused."""
+    seed = 99
+    for N, M in ((5, 1), (6, 2), (7, 6), (9, 16), (3, 40)):
+        words = [oracle.flip_word(seed, 0, M, 0, 0, k, i) for k in range(M) for i in range(N)]
+        # 32-bit words from distinct counters collide with probability ~ n^2 / 2^33
+        assert len(set(words)) == len(words)
 
 
 # ------------------------------------------------------------------ exp and thresholds
@@ -206,7 +224,7 @@ def brute_force_sweeps(inst, seed, index, s, rung_of, t0, n_sweeps):
                     K = inst.K[rung] if inst.M >= 2 else 0.0
                     dS = inst.b[rung] * float(E1 - E0) - K * float(C1 - C0)
                     thr = oracle.metropolis_threshold(dS)
-                    u = oracle.flip_word(seed, index, inst.N, c, t, k, i)
+                    u = oracle.flip_word(seed, index, inst.M, c, t, k, i)
                     if u <= thr:
                         s[c, k, i] = -s[c, k, i]
     return s
@@ -239,7 +257,7 @@ def test_init_spins_and_energies_from_definition():
     for c in range(3):
         for k in range(4):
             for i in range(9):
-                assert o.s[c, k, i] == oracle.init_spin(seed, 2, 9, c, k, i)
+                assert o.s[c, k, i] == oracle.init_spin(seed, 2, 4, c, k, i)
         assert (o.E[c], o.C[c]) == replica_terms(inst, o.s[c])
     assert list(o.replica_of) == [0, 1, 2] and list(o.rung_of) == [0, 1, 2]
     assert list(o.label) == [oracle.LABEL_UP, oracle.LABEL_NONE, oracle.LABEL_NONE]
