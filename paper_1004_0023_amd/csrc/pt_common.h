@@ -26,6 +26,16 @@ struct Words4 {
     uint32_t w[4];
 };
 
+// Three-input xor: one v_bitop3_b32 (truth table 0x96) on gfx950.
+__host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
 __host__ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                     uint32_t c3, uint32_t k0, uint32_t k1)
 {
@@ -33,8 +43,8 @@ __host__ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, ui
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)kPhiloxM0 * c0;
         const uint64_t pb = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
@@ -93,32 +103,41 @@ __host__ __device__ __forceinline__ uint32_t threshold(double dS)
 
 // ------------------------------------------------------------------ device layout
 
-// Table of thresholds of one rung, indexed [b][f + F][tau] with b = (s > 0), f the local
+// Table of thresholds of one rung, indexed [x][f + F][tau] with x = (s + 1)/2, f the local
 // field, tau = t'/2 + 1 in {0, 1, 2}: size 2 * (2F + 1) * 3 words.
 __host__ __device__ __forceinline__ int table_words(int F) { return 2 * (2 * F + 1) * 3; }
 
+// Spin layout of one replica (device memory and LDS): bytes x = (s + 1)/2 in {0, 1},
+// ordered [p][i][m] with slice k = 2m + p (parity-split, slice-minor): the Mh = M/2
+// slices of one parity of one site are contiguous, so a 32-bit word holds the four
+// same-parity slices that one Philox call serves.  M == 1: one parity, Mh = 1.
 struct InstDesc {
-    int32_t N, M, R, Npad;   // Npad = N rounded up to 4: row stride of a slice in bytes
-    int32_t Nq;              // ceil(N / 4): Philox blocks per slice
-    int32_t F;               // max |local field|
+    int32_t N, M, R;
+    int32_t Mh;        // slices per parity
+    int32_t G4;        // ceil(Mh / 4): Philox calls per (site, parity)
+    int32_t parities;  // 2 if M >= 2 else 1
+    int32_t F;         // max |local field|
+    int32_t D;         // max degree (fast-path neighbour rows are padded to D)
     int32_t n_colors;
-    int32_t unit_j;          // all |J| == 1
-    int32_t rep_base;        // first global replica / rung index
-    int32_t pair_base;       // first global pair index (R - 1 pairs)
-    int32_t adj_base;        // first neighbour entry
-    int32_t site_base;       // first site (offsets have N + 1 entries at site_base + n)
-    int32_t blk_base;        // first colour-block entry
-    int32_t cls_base;        // first class offset (n_colors + 1 entries)
-    int32_t tbl_base;        // first threshold word (R tables)
-    int32_t tbl_words;       // words per rung table
-    int64_t spin_base;       // first spin byte ([R][M][Npad])
+    int32_t fast;      // 1: byte-SWAR kernel applies to this instance
+    int32_t rep_base;  // first global replica / rung index
+    int32_t pair_base; // first global pair index (R - 1 pairs)
+    int32_t adj_base;  // first generic neighbour entry
+    int32_t off_base;  // first neighbour offset (N + 1 per instance)
+    int32_t site_base; // first per-site entry (fields, biases, class lists)
+    int32_t ent_base;  // first fast-path neighbour entry (N * D per instance)
+    int32_t cls_base;  // first class offset (n_colors + 1 per instance)
+    int32_t tbl_base;  // first threshold word (R tables)
+    int32_t tbl_words; // words per rung table
+    int32_t rep_bytes; // bytes per replica in device memory (N * M rounded up to 16)
+    int64_t spin_base; // first spin byte of the instance
 };
 
 struct Tile {
     int32_t inst;  // instance
     int32_t c0;    // first replica slot
-    int32_t P;     // replicas in the tile
-    int32_t pad;
+    int32_t P;     // replicas in the tile (a power of two on the fast path)
+    int32_t fast;  // which sweep kernel runs it
 };
 
 struct Counters {
@@ -132,17 +151,20 @@ struct Counters {
 struct DevState {
     // immutable after init
     const InstDesc *inst;
-    const int32_t *adj;       // neighbour entry: (j & 0xFFFF) | (J << 16)
+    const int32_t *adj;       // generic neighbour entry: (j & 0xFFFF) | (J << 16)
     const int32_t *adj_off;   // per site: first entry (N + 1 per instance)
     const int16_t *hfield;    // per site
-    const uint32_t *blk;      // colour-block entry: (blk << 4) | mask
-    const int32_t *cls_off;   // per colour: first block entry (n_colors + 1 per instance)
+    const uint32_t *ent;      // fast neighbour entry: (j*Mh) << 16 | w1 << 8 | w0
+    const uint32_t *bias;     // fast per-site bias (h - sum|J| + F) in every byte
+    const uint16_t *csite;    // sites of each colour, colour by colour
+    const int32_t *cls_off;   // per colour: first class site (n_colors + 1 per instance)
     const uint32_t *tbl;      // threshold tables
     const double *db;         // per pair: b_r - b_{r+1}
     const double *dK;         // per pair: K_r - K_{r+1}
     const Tile *tiles;
+    const int32_t *rep_inst;  // global replica -> instance
     // mutable state
-    int8_t *spins;
+    uint8_t *spins;
     int64_t *E;       // per replica slot
     int64_t *C;
     int32_t *rung_of;

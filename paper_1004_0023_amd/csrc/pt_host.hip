@@ -45,7 +45,7 @@ int hip_fail(hipError_t e, const char *what)
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr uint32_t kMagic = 0x51505450u;  // checkpoint tag
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 constexpr int kMaxField = 1023;
 
 // Host copy of everything that is uploaded once, plus the layout of the workspace.
@@ -53,13 +53,15 @@ struct Plan {
     std::vector<InstDesc> desc;
     std::vector<int32_t> adj, adj_off, cls_off, rep_inst;
     std::vector<int16_t> hfield;
-    std::vector<uint32_t> blk, tbl;
+    std::vector<uint16_t> csite;
+    std::vector<uint32_t> ent, bias, tbl;
     std::vector<double> db, dK;
-    std::vector<int32_t> n_adj, n_blk;  // per instance
+    std::vector<int32_t> n_adj;  // per instance
     int64_t total_reps = 0, total_pairs = 0, spin_bytes = 0;
     uint64_t flips_per_sweep = 0;
     // byte offsets in the workspace
-    size_t o_inst, o_adj, o_off, o_h, o_blk, o_cls, o_tbl, o_db, o_dK, o_tiles, o_repinst;
+    size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
+        o_repinst;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_acc, o_att, o_ctr;
@@ -105,29 +107,32 @@ int validate(const pt_instance &in, int idx)
     return PT_OK;
 }
 
-// Threshold table of one rung: [b][f + F][tau], b = (s > 0), tau = t'/2 + 1.
+// Threshold table of one rung: [x][f + F][tau], x = (s + 1)/2, tau = t'/2 + 1.
 void build_table(uint32_t *out, int F, int M, double b, double K)
 {
     const double Keff = (M >= 2) ? K : 0.0;
-    for (int bb = 0; bb < 2; ++bb) {
-        const int s = bb ? 1 : -1;
+    for (int x = 0; x < 2; ++x) {
+        const int s = x ? 1 : -1;
         for (int f = -F; f <= F; ++f) {
             for (int tau = 0; tau < 3; ++tau) {
                 const int tp = 2 * (tau - 1);
                 const int64_t dE = -2 * (int64_t)s * f;
                 const int64_t dC = -2 * (int64_t)s * tp;
                 const double dS = b * (double)dE - Keff * (double)dC;
-                out[(bb * (2 * F + 1) + (f + F)) * 3 + tau] = threshold(dS);
+                out[(x * (2 * F + 1) + (f + F)) * 3 + tau] = threshold(dS);
             }
         }
     }
 }
 
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
 int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
 {
     if (!inst || n_inst < 1) return fail(PT_EINVAL, "need at least one instance");
     P = Plan();
-    int64_t rep = 0, pair = 0, adjb = 0, siteb = 0, blkb = 0, clsb = 0, tblb = 0, spinb = 0;
+    int64_t rep = 0, pair = 0, adjb = 0, offb = 0, siteb = 0, entb = 0, clsb = 0, tblb = 0,
+            spinb = 0;
     for (int n = 0; n < n_inst; ++n) {
         int rc = validate(inst[n], n);
         if (rc) return rc;
@@ -136,17 +141,18 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
         d.N = in.N;
         d.M = in.M;
         d.R = in.R;
-        d.Npad = (in.N + 3) & ~3;
-        d.Nq = (in.N + 3) / 4;
+        d.Mh = (in.M >= 2) ? in.M / 2 : 1;
+        d.G4 = (d.Mh + 3) / 4;
+        d.parities = (in.M >= 2) ? 2 : 1;
         d.n_colors = in.n_colors;
-        // neighbour lists
+        // generic neighbour lists: (j & 0xFFFF) | (J << 16)
         std::vector<int32_t> deg(in.N + 1, 0);
-        bool unit = true;
         for (int e = 0; e < in.n_edges; ++e) {
             deg[in.edge_i[e] + 1]++;
             deg[in.edge_j[e] + 1]++;
-            if (std::abs((int)in.edge_J[e]) != 1) unit = false;
         }
+        int D = 0;
+        for (int i = 0; i < in.N; ++i) D = std::max(D, deg[i + 1]);
         for (int i = 0; i < in.N; ++i) deg[i + 1] += deg[i];
         std::vector<int32_t> fill(in.N, 0), entries(2 * (size_t)in.n_edges);
         for (int e = 0; e < in.n_edges; ++e) {
@@ -156,43 +162,61 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
             entries[deg[j] + fill[j]++] = (i & 0xFFFF) | (int32_t)((uint32_t)J << 16);
         }
         int F = 0;
+        std::vector<int> sumabs(in.N, 0);
         for (int i = 0; i < in.N; ++i) {
-            int fs = std::abs((int)in.h[i]);
-            for (int e = deg[i]; e < deg[i + 1]; ++e) fs += std::abs(entries[e] >> 16);
-            F = std::max(F, fs);
+            for (int e = deg[i]; e < deg[i + 1]; ++e) sumabs[i] += std::abs(entries[e] >> 16);
+            F = std::max(F, sumabs[i] + std::abs((int)in.h[i]));
         }
         d.F = F;
-        d.unit_j = unit ? 1 : 0;
-        // colour blocks: for colour g, every Philox block (4 consecutive labels) holding a
-        // site of colour g, with the mask of those sites
-        std::vector<int32_t> cls(in.n_colors + 1, 0);
-        std::vector<uint32_t> blocks;
-        for (int g = 0; g < in.n_colors; ++g) {
-            cls[g] = (int32_t)blocks.size();
-            for (int q = 0; q < d.Nq; ++q) {
-                uint32_t mask = 0;
-                for (int b = 0; b < 4; ++b) {
-                    const int i = 4 * q + b;
-                    if (i < in.N && in.color[i] == g) mask |= 1u << b;
-                }
-                if (mask) blocks.push_back(((uint32_t)q << 4) | mask);
-            }
-        }
-        cls[in.n_colors] = (int32_t)blocks.size();
+        d.D = std::max(D, 1);
+        d.fast = (in.M >= 8 && in.M % 8 == 0 && is_pow2(in.M / 8) && F <= 20 &&
+                  (int64_t)(in.N - 1) * d.Mh <= 65535) ? 1 : 0;
         d.tbl_words = table_words(F);
+        d.rep_bytes = (int32_t)align_up((size_t)in.N * in.M, 16);
         d.rep_base = (int32_t)rep;
         d.pair_base = (int32_t)pair;
         d.adj_base = (int32_t)adjb;
+        d.off_base = (int32_t)offb;
         d.site_base = (int32_t)siteb;
-        d.blk_base = (int32_t)blkb;
+        d.ent_base = (int32_t)entb;
         d.cls_base = (int32_t)clsb;
         d.tbl_base = (int32_t)tblb;
         d.spin_base = spinb;
+        // sites of each colour, colour by colour
+        std::vector<int32_t> cls(in.n_colors + 1, 0);
+        for (int i = 0; i < in.N; ++i) cls[in.color[i] + 1]++;
+        for (int g = 0; g < in.n_colors; ++g) cls[g + 1] += cls[g];
+        std::vector<int32_t> cfill(in.n_colors, 0);
+        std::vector<uint16_t> sites(in.N);
+        for (int i = 0; i < in.N; ++i) sites[cls[in.color[i]] + cfill[in.color[i]]++] = (uint16_t)i;
+        // fast-path rows: D entries per site, (j*Mh) << 16 | w1 << 8 | w0 with w0 / w1 the
+        // contribution |J| [J < 0] / |J| [J > 0] of a neighbour whose spin byte is 0 / 1;
+        // padding entries point at the site itself with weight 0
+        if (d.fast) {
+            for (int i = 0; i < in.N; ++i) {
+                int e = deg[i];
+                for (int k = 0; k < d.D; ++k, ++e) {
+                    uint32_t word = ((uint32_t)(i * d.Mh) << 16);
+                    if (e < deg[i + 1]) {
+                        const int j = entries[e] & 0xFFFF;
+                        const int J = entries[e] >> 16;
+                        const uint32_t w0 = (J < 0) ? (uint32_t)(-J) : 0u;
+                        const uint32_t w1 = (J > 0) ? (uint32_t)J : 0u;
+                        word = ((uint32_t)(j * d.Mh) << 16) | (w1 << 8) | w0;
+                    }
+                    P.ent.push_back(word);
+                }
+                const uint32_t b = (uint32_t)(in.h[i] - sumabs[i] + F) & 0xFFu;
+                P.bias.push_back(b * 0x01010101u);
+            }
+        } else {
+            for (int i = 0; i < in.N; ++i) P.bias.push_back(0);
+        }
         P.desc.push_back(d);
         P.adj.insert(P.adj.end(), entries.begin(), entries.end());
         P.adj_off.insert(P.adj_off.end(), deg.begin(), deg.end());
         for (int i = 0; i < in.N; ++i) P.hfield.push_back(in.h[i]);
-        P.blk.insert(P.blk.end(), blocks.begin(), blocks.end());
+        P.csite.insert(P.csite.end(), sites.begin(), sites.end());
         P.cls_off.insert(P.cls_off.end(), cls.begin(), cls.end());
         const size_t t0 = P.tbl.size();
         P.tbl.resize(t0 + (size_t)in.R * d.tbl_words);
@@ -205,17 +229,17 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
         }
         for (int c = 0; c < in.R; ++c) P.rep_inst.push_back(n);
         P.n_adj.push_back(2 * in.n_edges);
-        P.n_blk.push_back((int32_t)blocks.size());
         P.flips_per_sweep += (uint64_t)in.R * in.N * in.M;
         rep += in.R;
         pair += in.R - 1;
         adjb += 2 * (int64_t)in.n_edges;
+        offb += in.N + 1;
         siteb += in.N;
-        blkb += (int64_t)blocks.size();
+        entb += d.fast ? (int64_t)in.N * d.D : 0;
         clsb += in.n_colors + 1;
         tblb += (int64_t)in.R * d.tbl_words;
-        spinb += (int64_t)align_up((size_t)in.R * in.M * d.Npad, 16);
-        if (rep > (1 << 30) || tblb > (1ll << 31) || adjb > (1ll << 31))
+        spinb += (int64_t)in.R * d.rep_bytes;
+        if (rep > (1 << 30) || tblb > (1ll << 31) || adjb > (1ll << 31) || entb > (1ll << 31))
             return fail(PT_EINVAL, "batch too large");
     }
     P.total_reps = rep;
@@ -232,7 +256,9 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
     P.o_adj = take(P.adj.size() * 4);
     P.o_off = take(P.adj_off.size() * 4);
     P.o_h = take(P.hfield.size() * 2);
-    P.o_blk = take(P.blk.size() * 4);
+    P.o_ent = take(P.ent.size() * 4);
+    P.o_bias = take(P.bias.size() * 4);
+    P.o_csite = take(P.csite.size() * 2);
     P.o_cls = take(P.cls_off.size() * 4);
     P.o_tbl = take(P.tbl.size() * 4);
     P.o_db = take(P.db.size() * 8);
@@ -277,13 +303,13 @@ struct pt_ctx {
     bool own_ws = false;
     Plan plan;
     DevState st{};
-    const int32_t *d_rep_inst = nullptr;
     pt_options opt{};
     uint32_t key_flip0 = 0, key_flip1 = 0, key_swap0 = 0, key_swap1 = 0;
     // launch shape
-    std::vector<Tile> tiles;
+    std::vector<Tile> tiles;   // fast-kernel tiles first, then generic ones
+    int n_fast_tiles = 0;
     int block_threads = 256;
-    int lds_bytes = 0;
+    int lds_fast = 0, lds_generic = 0;
     int max_P = 1;
     int lds_limit = 65536;
     int cus = 256;
@@ -304,53 +330,67 @@ namespace {
 
 int n_inst_of(const pt_ctx *c) { return (int)c->plan.desc.size(); }
 
-// Choose tiles: P replicas of one instance per workgroup, P limited by LDS, and sized so
-// the batch yields a few workgroups per CU when it can (the paper's chain packing,
-// Section 5, stops packing once multiprocessors would go idle).
+// Choose tiles: P replicas of one instance per workgroup, P limited by LDS (and a power of
+// two on the fast path), sized so the batch yields a few workgroups per CU when it can
+// (the paper's chain packing, Section 5, stops packing once multiprocessors would go
+// idle).
 int build_tiles(pt_ctx *c, int force_P)
 {
     const Plan &P = c->plan;
     // the tile list is uploaded from c->tiles: let any earlier upload finish first
     HIP_TRY(hipStreamSynchronize(c->stream));
     int64_t total_bytes = 0;
-    for (const auto &d : P.desc) total_bytes += (int64_t)d.R * d.M * d.Npad;
-    const int64_t target_tiles = 4ll * c->cus;
-    int64_t target_bytes = std::max<int64_t>(total_bytes / target_tiles, 4096);
+    for (const auto &d : P.desc) total_bytes += (int64_t)d.R * d.N * d.M;
+    int64_t target_bytes = std::max<int64_t>(total_bytes / (2ll * c->cus), 4096);
     target_bytes = std::min<int64_t>(target_bytes, 64 * 1024);
-    c->tiles.clear();
-    int lds_max = 0, maxP = 1;
+    std::vector<Tile> fast, generic;
+    int lds_f = 0, lds_g = 0, maxP = 1;
     for (int n = 0; n < (int)P.desc.size(); ++n) {
         const InstDesc &d = P.desc[n];
         int pmax = 0;
         for (int p = d.R; p >= 1; --p)
-            if (sweep_tile_lds_bytes(d, P.n_adj[n], P.n_blk[n], p) <= c->lds_limit) {
+            if (sweep_tile_lds_bytes(d, P.n_adj[n], p) <= c->lds_limit &&
+                (!d.fast || is_pow2(p))) {
                 pmax = p;
                 break;
             }
         if (pmax < 1)
             return fail(PT_EINVAL, "instance " + std::to_string(n) +
                                        ": one replica does not fit in LDS (N*M too large)");
-        int p = (int)std::max<int64_t>(1, target_bytes / ((int64_t)d.M * d.Npad));
+        int p = (int)std::max<int64_t>(1, target_bytes / ((int64_t)d.N * d.M));
         if (force_P > 0) p = force_P;
-        p = std::min(p, pmax);
-        for (int c0 = 0; c0 < d.R; c0 += p) {
-            Tile t{n, c0, std::min(p, d.R - c0), 0};
-            c->tiles.push_back(t);
-            lds_max = std::max(lds_max, sweep_tile_lds_bytes(d, P.n_adj[n], P.n_blk[n], t.P));
-            maxP = std::max(maxP, t.P);
+        p = std::max(1, std::min(p, pmax));
+        if (d.fast)
+            while (!is_pow2(p)) --p;
+        for (int c0 = 0; c0 < d.R;) {
+            int q = std::min(p, d.R - c0);
+            if (d.fast)
+                while (!is_pow2(q)) --q;
+            Tile t{n, c0, q, d.fast};
+            (d.fast ? fast : generic).push_back(t);
+            const int b = sweep_tile_lds_bytes(d, P.n_adj[n], q);
+            (d.fast ? lds_f : lds_g) = std::max(d.fast ? lds_f : lds_g, b);
+            maxP = std::max(maxP, q);
+            c0 += q;
         }
     }
     // largest tiles first: the device dispatches workgroups roughly in order, so the
     // longest work starts earliest (the paper's "hardest chains first" work pool)
-    std::stable_sort(c->tiles.begin(), c->tiles.end(), [&](const Tile &a, const Tile &b) {
+    auto bigger = [&](const Tile &a, const Tile &b) {
         const InstDesc &da = P.desc[a.inst], &db = P.desc[b.inst];
         return (int64_t)a.P * da.M * da.N > (int64_t)b.P * db.M * db.N;
-    });
-    c->lds_bytes = lds_max;
+    };
+    std::stable_sort(fast.begin(), fast.end(), bigger);
+    std::stable_sort(generic.begin(), generic.end(), bigger);
+    c->tiles = fast;
+    c->tiles.insert(c->tiles.end(), generic.begin(), generic.end());
+    c->n_fast_tiles = (int)fast.size();
+    c->lds_fast = lds_f;
+    c->lds_generic = lds_g;
     c->max_P = maxP;
     HIP_TRY(hipMemcpyAsync(c->ws + P.o_tiles, c->tiles.data(), c->tiles.size() * sizeof(Tile),
                            hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(sweep_kernel_set_lds(c->lds_bytes));
+    HIP_TRY(sweep_kernels_set_lds(c->lds_fast, c->lds_generic));
     return PT_OK;
 }
 
@@ -415,21 +455,28 @@ int enqueue_sweep(pt_ctx *c, int n_sweeps)
         L.key0 = c->key_flip0;
         L.key1 = c->key_flip1;
         L.n_sweeps = n_sweeps;
-        L.n_tiles = (int)c->tiles.size();
         L.block_threads = c->block_threads;
-        L.lds_bytes = c->lds_bytes;
         int ea = -1, eb = -1;
         if (timing) {
             int rc = event_pair(c, ea, eb);
             if (rc) return rc;
             HIP_TRY(hipEventRecord(c->ev_pool[ea], c->stream));
         }
-        hipError_t e;
+        hipError_t e = hipSuccess;
         if (c->inject_pending) {
             c->inject_pending = false;
             e = hipErrorLaunchOutOfResources;
         } else {
-            e = launch_sweep(L, c->stream);
+            L.tile0 = 0;
+            L.n_tiles = c->n_fast_tiles;
+            L.lds_bytes = c->lds_fast;
+            e = launch_sweep(L, true, c->stream);
+            if (e == hipSuccess) {
+                L.tile0 = c->n_fast_tiles;
+                L.n_tiles = (int)c->tiles.size() - c->n_fast_tiles;
+                L.lds_bytes = c->lds_generic;
+                e = launch_sweep(L, false, c->stream);
+            }
         }
         if (e == hipSuccess) {
             if (timing) {
@@ -566,13 +613,15 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.adj = (const int32_t *)(w + P.o_adj);
     st.adj_off = (const int32_t *)(w + P.o_off);
     st.hfield = (const int16_t *)(w + P.o_h);
-    st.blk = (const uint32_t *)(w + P.o_blk);
+    st.ent = (const uint32_t *)(w + P.o_ent);
+    st.bias = (const uint32_t *)(w + P.o_bias);
+    st.csite = (const uint16_t *)(w + P.o_csite);
     st.cls_off = (const int32_t *)(w + P.o_cls);
     st.tbl = (const uint32_t *)(w + P.o_tbl);
     st.db = (const double *)(w + P.o_db);
     st.dK = (const double *)(w + P.o_dK);
     st.tiles = (const Tile *)(w + P.o_tiles);
-    st.spins = (int8_t *)(w + P.o_spins);
+    st.spins = (uint8_t *)(w + P.o_spins);
     st.E = (int64_t *)(w + P.o_E);
     st.C = (int64_t *)(w + P.o_C);
     st.rung_of = (int32_t *)(w + P.o_rung);
@@ -586,7 +635,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.acc = (uint64_t *)(w + P.o_acc);
     st.att = (uint64_t *)(w + P.o_att);
     st.ctr = (Counters *)(w + P.o_ctr);
-    c->d_rep_inst = (const int32_t *)(w + P.o_repinst);
+    st.rep_inst = (const int32_t *)(w + P.o_repinst);
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;
@@ -602,7 +651,9 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     put(P.o_adj, P.adj.data(), P.adj.size() * 4);
     put(P.o_off, P.adj_off.data(), P.adj_off.size() * 4);
     put(P.o_h, P.hfield.data(), P.hfield.size() * 2);
-    put(P.o_blk, P.blk.data(), P.blk.size() * 4);
+    put(P.o_ent, P.ent.data(), P.ent.size() * 4);
+    put(P.o_bias, P.bias.data(), P.bias.size() * 4);
+    put(P.o_csite, P.csite.data(), P.csite.size() * 2);
     put(P.o_cls, P.cls_off.data(), P.cls_off.size() * 4);
     put(P.o_tbl, P.tbl.data(), P.tbl.size() * 4);
     put(P.o_db, P.db.data(), P.db.size() * 8);
@@ -618,10 +669,10 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     }
     e = hipMemcpyAsync(c->ws, img.data(), P.total_bytes, hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return cleanup(hip_fail(e, "upload"));
-    e = launch_init_spins(st, c->d_rep_inst, (int)P.total_reps, c->key_flip0,
+    e = launch_init_spins(st, (int)P.total_reps, c->key_flip0,
                           c->key_flip1 ^ kDomainInit, c->stream);
     if (e != hipSuccess) return cleanup(hip_fail(e, "init launch"));
-    e = launch_energy(st, c->d_rep_inst, 0, (int)P.total_reps, c->stream);
+    e = launch_energy(st, 0, (int)P.total_reps, c->stream);
     if (e != hipSuccess) return cleanup(hip_fail(e, "energy launch"));
     c->block_threads = opt->block_threads > 0 ? opt->block_threads : 256;
     rc = build_tiles(c, opt->tile_replicas);
@@ -740,18 +791,29 @@ int pt_observables(pt_ctx *c, int32_t inst, pt_obs *o)
     return PT_OK;
 }
 
+// Device layout of one replica: bytes x = (s + 1)/2 ordered [p][i][m], slice k = 2m + p.
+static inline size_t spin_pos(const InstDesc &d, int k, int i)
+{
+    const int p = (d.M >= 2) ? (k & 1) : 0;
+    const int m = (d.M >= 2) ? (k >> 1) : 0;
+    return (size_t)p * d.N * d.Mh + (size_t)i * d.Mh + m;
+}
+
 int pt_get_spins(pt_ctx *c, int32_t inst, int8_t *out)
 {
     int rc = check_inst(c, inst);
     if (rc) return rc;
     if (!out) return fail(PT_EINVAL, "null output");
     const InstDesc &d = c->plan.desc[inst];
-    const size_t rows = (size_t)d.R * d.M;
-    std::vector<int8_t> buf(rows * d.Npad);
+    std::vector<uint8_t> buf((size_t)d.R * d.rep_bytes);
     HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + c->plan.o_spins + d.spin_base, buf.size(),
                            hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    for (size_t r = 0; r < rows; ++r) std::memcpy(out + r * d.N, buf.data() + r * d.Npad, d.N);
+    for (int r = 0; r < d.R; ++r)
+        for (int k = 0; k < d.M; ++k)
+            for (int i = 0; i < d.N; ++i)
+                out[((size_t)r * d.M + k) * d.N + i] =
+                    (int8_t)(2 * buf[(size_t)r * d.rep_bytes + spin_pos(d, k, i)] - 1);
     return PT_OK;
 }
 
@@ -761,17 +823,17 @@ int pt_set_spins(pt_ctx *c, int32_t inst, const int8_t *in)
     if (rc) return rc;
     if (!in) return fail(PT_EINVAL, "null input");
     const InstDesc &d = c->plan.desc[inst];
-    const size_t rows = (size_t)d.R * d.M;
-    std::vector<int8_t> buf(rows * d.Npad, 0);
-    for (size_t r = 0; r < rows; ++r)
-        for (int i = 0; i < d.N; ++i) {
-            const int8_t v = in[r * d.N + i];
-            if (v != 1 && v != -1) return fail(PT_EINVAL, "spins must be +1 or -1");
-            buf[r * d.Npad + i] = v;
-        }
+    std::vector<uint8_t> buf((size_t)d.R * d.rep_bytes, 0);
+    for (int r = 0; r < d.R; ++r)
+        for (int k = 0; k < d.M; ++k)
+            for (int i = 0; i < d.N; ++i) {
+                const int8_t v = in[((size_t)r * d.M + k) * d.N + i];
+                if (v != 1 && v != -1) return fail(PT_EINVAL, "spins must be +1 or -1");
+                buf[(size_t)r * d.rep_bytes + spin_pos(d, k, i)] = (uint8_t)((v + 1) / 2);
+            }
     HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_spins + d.spin_base, buf.data(), buf.size(),
                            hipMemcpyHostToDevice, c->stream));
-    hipError_t e = launch_energy(c->st, c->d_rep_inst, d.rep_base, d.R, c->stream);
+    hipError_t e = launch_energy(c->st, d.rep_base, d.R, c->stream);
     if (e != hipSuccess) return hip_fail(e, "energy launch");
     HIP_TRY(hipStreamSynchronize(c->stream));
     return PT_OK;
@@ -807,6 +869,12 @@ int pt_load(pt_ctx *c, const void *buf, size_t len)
         h.seed != c->opt.seed || h.flips_per_sweep != c->plan.flips_per_sweep ||
         len != sizeof h + h.state_bytes)
         return fail(PT_ESTATE, "checkpoint belongs to different instances or options");
+    {
+        // every spin byte must be 0 or 1: the kernels index tables with them
+        const uint8_t *sp = (const uint8_t *)buf + sizeof h + (c->plan.o_spins - c->plan.o_state);
+        for (int64_t b = 0; b < c->plan.spin_bytes; ++b)
+            if (sp[b] > 1) return fail(PT_ESTATE, "checkpoint holds invalid spins");
+    }
     HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_state, (const char *)buf + sizeof h, h.state_bytes,
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -821,7 +889,7 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->n_instances = n_inst_of(c);
     o->n_tiles = (int)c->tiles.size();
     o->block_threads = c->block_threads;
-    o->lds_bytes = c->lds_bytes;
+    o->lds_bytes = std::max(c->lds_fast, c->lds_generic);
     o->max_tile_replicas = c->max_P;
     o->fallbacks = c->fallbacks;
     o->encoding = c->opt.encoding;

@@ -9,6 +9,7 @@ struct SweepLaunch {
     DevState st;
     uint32_t key0, key1;   // flip-domain Philox key
     int32_t n_sweeps;
+    int32_t tile0;         // first tile of this launch
     int32_t n_tiles;
     int32_t block_threads;
     int32_t lds_bytes;
@@ -16,18 +17,17 @@ struct SweepLaunch {
 
 // Each returns the hipError_t of the launch itself (asynchronous execution errors
 // surface at the next synchronisation).
-hipError_t launch_init_spins(const DevState &st, const int32_t *rep_inst, int32_t n_reps,
-                             uint32_t key0, uint32_t key1, hipStream_t s);
-hipError_t launch_energy(const DevState &st, const int32_t *rep_inst, int32_t rep_first,
-                         int32_t n_reps, hipStream_t s);
-hipError_t launch_sweep(const SweepLaunch &L, hipStream_t s);
+hipError_t launch_init_spins(const DevState &st, int32_t n_reps, uint32_t key0, uint32_t key1,
+                             hipStream_t s);
+hipError_t launch_energy(const DevState &st, int32_t rep_first, int32_t n_reps, hipStream_t s);
+hipError_t launch_sweep(const SweepLaunch &L, bool fast, hipStream_t s);
 hipError_t launch_exchange(const DevState &st, int32_t n_inst, uint32_t key0, uint32_t key1,
                            uint32_t t_add, hipStream_t s);
 hipError_t launch_advance(const DevState &st, int32_t n_inst, uint32_t t_add, hipStream_t s);
 hipError_t launch_threshold_eval(const double *dS, uint32_t *out, int32_t n, hipStream_t s);
-hipError_t sweep_kernel_set_lds(int32_t bytes);
+hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes);
 
-// LDS bytes a tile of P replicas of instance d needs in the sweep kernel.
-int32_t sweep_tile_lds_bytes(const InstDesc &d, int32_t n_adj, int32_t n_blk, int32_t P);
+// LDS bytes a tile of P replicas of instance d needs in its sweep kernel.
+int32_t sweep_tile_lds_bytes(const InstDesc &d, int32_t n_adj, int32_t P);
 
 }  // namespace ptq

@@ -1,11 +1,18 @@
 // pt_kernels.hip -- gfx950 kernels of the parallel-tempering sampler.
 //
-//   init_spins   draws the initial spins (INIT-domain Philox words)
-//   energy       E_cl and C of replicas from their spins in device memory
-//   sweep_tile   n Metropolis sweeps of a tile of replicas held in LDS, colour class by
-//                colour class, then E_cl and C of each replica from the final spins
-//   exchange     one even/odd replica-exchange step per instance (one workgroup each)
-//   advance      t += n
+//   init_spins     initial spins from INIT-domain Philox words
+//   energy         E_cl and C of replicas from their spins in device memory
+//   sweep_fast     n Metropolis sweeps of a tile of replicas held in LDS: one lane per
+//                  (site, four same-parity slices), byte-SWAR local fields (v_perm per
+//                  neighbour), one Philox call per lane and class; then E_cl and C
+//   sweep_generic  the same chain for any shape (odd slice groups, M = 1, large fields),
+//                  one byte at a time
+//   exchange       one even/odd replica-exchange step per instance (one workgroup each)
+//   advance        t += n
+//
+// Both sweep kernels visit colour classes (slice parity p, spatial colour g) in order;
+// a class is an independent set, so its sites are updated in parallel and the result
+// is independent of the launch shape.
 #include "pt_internal.h"
 
 #pragma clang fp contract(off)
@@ -39,64 +46,72 @@ __device__ __forceinline__ long long block_sum(long long v, long long *scratch)
     return tot;
 }
 
-__device__ __forceinline__ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+__host__ __device__ __forceinline__ int64_t a16(int64_t x) { return (x + 15) & ~(int64_t)15; }
+
+// Philox counter word 0 of the draws of (site i, parity p, slice group g4).
+__device__ __forceinline__ uint32_t spin_ctr0(int i, int p, int G4, int g4)
+{
+    return (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)g4;
+}
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
 // ------------------------------------------------------------------ init
 
-__global__ void init_spins_kernel(DevState st, const int32_t *rep_inst, uint32_t key0,
-                                  uint32_t key1)
+__global__ void init_spins_kernel(DevState st, uint32_t key0, uint32_t key1)
 {
     const int g = blockIdx.x;  // global replica
-    const int n = rep_inst[g];
+    const int n = st.rep_inst[g];
     const InstDesc d = st.inst[n];
     const int c = g - d.rep_base;
-    int8_t *base = st.spins + d.spin_base + (int64_t)c * d.M * d.Npad;
-    const int items = d.M * d.Nq;
+    uint8_t *base = st.spins + d.spin_base + (int64_t)c * d.rep_bytes;
+    const int items = d.N * d.parities * d.G4;
     for (int it = threadIdx.x; it < items; it += blockDim.x) {
-        const int k = it / d.Nq;
-        const int q = it - k * d.Nq;
-        const Words4 u = philox10((uint32_t)k * (uint32_t)d.Nq + (uint32_t)q, 0u, (uint32_t)c,
-                                  (uint32_t)n, key0, key1);
-        uint32_t packed = 0;
+        const int g4 = it % d.G4;
+        const int ip = it / d.G4;
+        const int p = ip % d.parities;
+        const int i = ip / d.parities;
+        const Words4 u = philox10(spin_ctr0(i, p, d.G4, g4), 0u, (uint32_t)c, (uint32_t)n, key0, key1);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int i = 4 * q + b;
-            const uint32_t v = (i < d.N) ? ((u.w[b] >> 31) ? 0x01u : 0xFFu) : 0u;
-            packed |= v << (8 * b);
+            const int m = 4 * g4 + b;
+            if (m < d.Mh) base[(int64_t)p * d.N * d.Mh + (int64_t)i * d.Mh + m] = (uint8_t)(u.w[b] >> 31);
         }
-        *reinterpret_cast<uint32_t *>(base + (int64_t)k * d.Npad + 4 * q) = packed;
     }
 }
 
-// ------------------------------------------------------------------ energy from global
+// ------------------------------------------------------------------ energy from device memory
 
-__global__ void energy_kernel(DevState st, const int32_t *rep_inst, int32_t rep_first)
+__device__ __forceinline__ int spin_of(const uint8_t *rep, const InstDesc &d, int k, int i)
+{
+    const int p = (d.M >= 2) ? (k & 1) : 0;
+    const int m = (d.M >= 2) ? (k >> 1) : 0;
+    return 2 * (int)rep[(int64_t)p * d.N * d.Mh + (int64_t)i * d.Mh + m] - 1;
+}
+
+__global__ void energy_kernel(DevState st, int32_t rep_first)
 {
     __shared__ long long scratch[16];
     const int g = rep_first + blockIdx.x;
-    const int n = rep_inst[g];
+    const int n = st.rep_inst[g];
     const InstDesc d = st.inst[n];
     const int c = g - d.rep_base;
-    const int8_t *base = st.spins + d.spin_base + (int64_t)c * d.M * d.Npad;
-    const int32_t *off = st.adj_off + d.site_base + n;
+    const uint8_t *rep = st.spins + d.spin_base + (int64_t)c * d.rep_bytes;
+    const int32_t *off = st.adj_off + d.off_base;
     const int32_t *adj = st.adj + d.adj_base;
     const int16_t *hf = st.hfield + d.site_base;
     long long e2 = 0, cc = 0;
     for (int it = threadIdx.x; it < d.M * d.N; it += blockDim.x) {
         const int k = it / d.N;
         const int i = it - k * d.N;
-        const int8_t *row = base + (int64_t)k * d.Npad;
-        const int s = row[i];
+        const int s = spin_of(rep, d, k, i);
         int f = 2 * hf[i];
         for (int e = off[i]; e < off[i + 1]; ++e) {
             const int a = adj[e];
-            f += (a >> 16) * row[a & 0xFFFF];
+            f += (a >> 16) * spin_of(rep, d, k, a & 0xFFFF);
         }
         e2 += (long long)s * f;
-        if (d.M >= 2) {
-            const int8_t *nxt = base + (int64_t)((k + 1 == d.M) ? 0 : k + 1) * d.Npad;
-            cc += (long long)s * nxt[i];
-        }
+        if (d.M >= 2) cc += (long long)s * spin_of(rep, d, (k + 1 == d.M) ? 0 : k + 1, i);
     }
     e2 = block_sum(e2, scratch);
     cc = block_sum(cc, scratch);
@@ -106,161 +121,341 @@ __global__ void energy_kernel(DevState st, const int32_t *rep_inst, int32_t rep_
     }
 }
 
-// ------------------------------------------------------------------ sweep
+// ------------------------------------------------------------------ tile staging
 
 struct TileLds {
-    int8_t *sp;
-    int32_t *adj;
-    int32_t *off;
-    int16_t *h;
-    uint32_t *blk;
-    int32_t *cls;
-    uint32_t *tbl;
-    long long *red;
+    uint8_t *sp;       // P replicas, rep_lds bytes each
+    uint32_t *ent;     // fast: N * D entries
+    uint32_t *bias;    // fast: N
+    int32_t *adj;      // generic: neighbour entries
+    int32_t *off;      // generic: N + 1
+    int16_t *h;        // generic: N
+    uint16_t *csite;   // N
+    int32_t *coff;     // n_colors + 1
+    uint32_t *tbl;     // P tables
+    long long *red;    // reduction scratch
 };
 
-__device__ __forceinline__ TileLds carve(char *lds, const InstDesc &d, int n_adj, int n_blk,
-                                         int P)
+__host__ __device__ __forceinline__ int64_t rep_lds_bytes(const InstDesc &d)
 {
+    return ((int64_t)d.N * d.M + 3) & ~(int64_t)3;
+}
+
+// Shared by the host (to size the launch) and the kernels (to carve LDS).
+__host__ __device__ __forceinline__ int64_t carve_offsets(const InstDesc &d, int n_adj, int P,
+                                                          int64_t o[10])
+{
+    int64_t x = 0;
+    o[0] = x; x = a16(x + (int64_t)P * rep_lds_bytes(d));
+    o[1] = x; x = a16(x + (d.fast ? (int64_t)d.N * d.D * 4 : 0));
+    o[2] = x; x = a16(x + (d.fast ? (int64_t)d.N * 4 : 0));
+    o[3] = x; x = a16(x + (d.fast ? 0 : (int64_t)n_adj * 4));
+    o[4] = x; x = a16(x + (d.fast ? 0 : (int64_t)(d.N + 1) * 4));
+    o[5] = x; x = a16(x + (d.fast ? 0 : (int64_t)d.N * 2));
+    o[6] = x; x = a16(x + (int64_t)d.N * 2);
+    o[7] = x; x = a16(x + (int64_t)(d.n_colors + 1) * 4);
+    o[8] = x; x = a16(x + (int64_t)P * d.tbl_words * 4);
+    o[9] = x; x = a16(x + 2 * 16 * 8);
+    return x;
+}
+
+__device__ __forceinline__ TileLds carve(char *lds, const InstDesc &d, int n_adj, int P)
+{
+    int64_t o[10];
+    carve_offsets(d, n_adj, P, o);
     TileLds t;
-    size_t o = 0;
-    t.sp = reinterpret_cast<int8_t *>(lds + o);
-    o = align16(o + (size_t)P * d.M * d.Npad);
-    t.adj = reinterpret_cast<int32_t *>(lds + o);
-    o = align16(o + (size_t)n_adj * 4);
-    t.off = reinterpret_cast<int32_t *>(lds + o);
-    o = align16(o + (size_t)(d.N + 1) * 4);
-    t.h = reinterpret_cast<int16_t *>(lds + o);
-    o = align16(o + (size_t)d.N * 2);
-    t.blk = reinterpret_cast<uint32_t *>(lds + o);
-    o = align16(o + (size_t)n_blk * 4);
-    t.cls = reinterpret_cast<int32_t *>(lds + o);
-    o = align16(o + (size_t)(d.n_colors + 1) * 4);
-    t.tbl = reinterpret_cast<uint32_t *>(lds + o);
-    o = align16(o + (size_t)P * d.tbl_words * 4);
-    t.red = reinterpret_cast<long long *>(lds + o);
+    t.sp = reinterpret_cast<uint8_t *>(lds + o[0]);
+    t.ent = reinterpret_cast<uint32_t *>(lds + o[1]);
+    t.bias = reinterpret_cast<uint32_t *>(lds + o[2]);
+    t.adj = reinterpret_cast<int32_t *>(lds + o[3]);
+    t.off = reinterpret_cast<int32_t *>(lds + o[4]);
+    t.h = reinterpret_cast<int16_t *>(lds + o[5]);
+    t.csite = reinterpret_cast<uint16_t *>(lds + o[6]);
+    t.coff = reinterpret_cast<int32_t *>(lds + o[7]);
+    t.tbl = reinterpret_cast<uint32_t *>(lds + o[8]);
+    t.red = reinterpret_cast<long long *>(lds + o[9]);
     return t;
 }
 
-__global__ void __launch_bounds__(1024) sweep_tile_kernel(SweepLaunch L)
+// Copy P replicas (each rep_bytes apart in device memory, rep_lds apart in LDS) in 32-bit
+// words; both strides are multiples of 4.
+__device__ __forceinline__ void copy_spins_in(uint32_t *dst, const uint32_t *src, int P,
+                                              int rep_words_dev, int rep_words_lds)
+{
+    const int total = P * rep_words_lds;
+    for (int w = threadIdx.x; w < total; w += blockDim.x) {
+        const int q = w / rep_words_lds;
+        const int r = w - q * rep_words_lds;
+        dst[w] = src[(int64_t)q * rep_words_dev + r];
+    }
+}
+
+__device__ __forceinline__ void copy_spins_out(uint32_t *dst, const uint32_t *src, int P,
+                                               int rep_words_dev, int rep_words_lds)
+{
+    const int total = P * rep_words_lds;
+    for (int w = threadIdx.x; w < total; w += blockDim.x) {
+        const int q = w / rep_words_lds;
+        const int r = w - q * rep_words_lds;
+        dst[(int64_t)q * rep_words_dev + r] = src[w];
+    }
+}
+
+__device__ __forceinline__ void stage_common(const DevState &st, const InstDesc &d, int n,
+                                             const Tile &tile, const TileLds &t, int n_adj)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(
+        st.spins + d.spin_base + (int64_t)tile.c0 * d.rep_bytes);
+    copy_spins_in(reinterpret_cast<uint32_t *>(t.sp), src, tile.P, d.rep_bytes / 4,
+                  (int)(rep_lds_bytes(d) / 4));
+    for (int i = tid; i < d.N; i += nt) t.csite[i] = st.csite[d.site_base + i];
+    for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
+    for (int q = 0; q < tile.P; ++q) {
+        const int rung = st.rung_of[d.rep_base + tile.c0 + q];
+        const uint32_t *tsrc = st.tbl + d.tbl_base + (int64_t)rung * d.tbl_words;
+        for (int w = tid; w < d.tbl_words; w += nt) t.tbl[q * d.tbl_words + w] = tsrc[w];
+    }
+    if (d.fast) {
+        for (int e = tid; e < d.N * d.D; e += nt) t.ent[e] = st.ent[d.ent_base + e];
+        for (int i = tid; i < d.N; i += nt) t.bias[i] = st.bias[d.site_base + i];
+    } else {
+        for (int e = tid; e < n_adj; e += nt) t.adj[e] = st.adj[d.adj_base + e];
+        for (int i = tid; i <= d.N; i += nt) t.off[i] = st.adj_off[d.off_base + i];
+        for (int i = tid; i < d.N; i += nt) t.h[i] = st.hfield[d.site_base + i];
+    }
+    (void)n;
+}
+
+__device__ __forceinline__ void write_back(const DevState &st, const InstDesc &d,
+                                           const Tile &tile, const TileLds &t)
+{
+    uint32_t *dst = reinterpret_cast<uint32_t *>(st.spins + d.spin_base +
+                                                 (int64_t)tile.c0 * d.rep_bytes);
+    copy_spins_out(dst, reinterpret_cast<const uint32_t *>(t.sp), tile.P, d.rep_bytes / 4,
+                   (int)(rep_lds_bytes(d) / 4));
+}
+
+// ------------------------------------------------------------------ fast sweep
+
+__device__ __forceinline__ uint32_t lds32(const uint8_t *base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const uint32_t *>(base + byte_off);
+}
+
+__device__ __forceinline__ uint32_t popc(uint32_t x) { return (uint32_t)__popc(x); }
+
+__global__ void __launch_bounds__(1024) sweep_fast_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
-    const Tile tile = st.tiles[blockIdx.x];
+    const Tile tile = st.tiles[L.tile0 + blockIdx.x];
     const int n = tile.inst;
     const InstDesc d = st.inst[n];
-    const int P = tile.P;
-    const int c0 = tile.c0;
-    const int32_t *goff = st.adj_off + d.site_base + n;
-    const int n_adj = goff[d.N] - goff[0];
-    const int32_t *gcls = st.cls_off + d.cls_base;
-    const int n_blk = gcls[d.n_colors] - gcls[0];
-    TileLds t = carve(lds, d, n_adj, n_blk, P);
-    const int tid = threadIdx.x;
-    const int nt = blockDim.x;
-
-    // stage the tile: spins, neighbour lists, fields, colour blocks, rung tables
-    {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(
-            st.spins + d.spin_base + (int64_t)c0 * d.M * d.Npad);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(t.sp);
-        const int words = P * d.M * d.Npad / 4;
-        for (int w = tid; w < words; w += nt) dst[w] = src[w];
-        const int a0 = goff[0];
-        for (int e = tid; e < n_adj; e += nt) t.adj[e] = st.adj[d.adj_base + e];
-        for (int i = tid; i <= d.N; i += nt) t.off[i] = goff[i] - a0;
-        for (int i = tid; i < d.N; i += nt) t.h[i] = st.hfield[d.site_base + i];
-        const int b0 = gcls[0];
-        for (int e = tid; e < n_blk; e += nt) t.blk[e] = st.blk[d.blk_base + e];
-        for (int g = tid; g <= d.n_colors; g += nt) t.cls[g] = gcls[g] - b0;
-        for (int q = 0; q < P; ++q) {
-            const int rung = st.rung_of[d.rep_base + c0 + q];
-            const uint32_t *tsrc = st.tbl + d.tbl_base + (int64_t)rung * d.tbl_words;
-            for (int w = tid; w < d.tbl_words; w += nt) t.tbl[q * d.tbl_words + w] = tsrc[w];
-        }
-    }
+    TileLds t = carve(lds, d, 0, tile.P);
+    stage_common(st, d, n, tile, t, 0);
     const uint64_t t0 = st.ctr[n].t;
     __syncthreads();
 
-    const int M = d.M, N = d.N, Npad = d.Npad, F = d.F;
-    const int parities = (M >= 2) ? 2 : 1;
-    const int Mc = (M >= 2) ? M / 2 : 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int N = d.N, Mh = d.Mh, G4 = d.G4, D = d.D, F = d.F;
+    const uint32_t NM = (uint32_t)(N * d.M), NMh = (uint32_t)(N * Mh);
+    const int lgG4 = ilog2(G4);
+    const int lgL = ilog2(tile.P) + lgG4;  // lanes per site: P * G4
+    const int Lmask = (1 << lgL) - 1;
+    const uint32_t sel_x = (uint32_t)(2 * F + 1) << 8;  // v_perm table: x -> x * (2F + 1)
+    const int tw = d.tbl_words;
+    const uint32_t c0 = (uint32_t)tile.c0;
+
+    for (int sw = 0; sw < L.n_sweeps; ++sw) {
+        const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
+        for (int p = 0; p < 2; ++p) {
+            for (int g = 0; g < d.n_colors; ++g) {
+                const int s0 = t.coff[g];
+                const int items = (t.coff[g + 1] - s0) << lgL;
+                for (int it = tid; it < items; it += nt) {
+                    const int r = it & Lmask;
+                    const int i = t.csite[s0 + (it >> lgL)];
+                    const int q = r >> lgG4;
+                    const int g4 = r & (G4 - 1);
+                    const uint32_t qbase = (uint32_t)q * NM;
+                    const uint32_t own = qbase + (uint32_t)p * NMh + (uint32_t)(i * Mh + 4 * g4);
+                    const uint32_t oth_row = qbase + (uint32_t)(p ^ 1) * NMh + (uint32_t)(i * Mh);
+                    const uint32_t X = lds32(t.sp, own);
+                    const uint32_t Wc = lds32(t.sp, oth_row + 4 * g4);
+                    // time neighbours live in the other parity: byte b of T is x(k-1) + x(k+1)
+                    uint32_t T;
+                    if (p == 0) {
+                        const uint32_t Wp = lds32(t.sp, oth_row + 4 * ((g4 - 1) & (G4 - 1)));
+                        T = __builtin_amdgcn_alignbyte(Wc, Wp, 3) + Wc;
+                    } else {
+                        const uint32_t Wn = lds32(t.sp, oth_row + 4 * ((g4 + 1) & (G4 - 1)));
+                        T = __builtin_amdgcn_alignbyte(Wn, Wc, 1) + Wc;
+                    }
+                    const Words4 u = philox10(spin_ctr0(i, p, G4, g4), tt, c0 + (uint32_t)q,
+                                              (uint32_t)n, L.key0, L.key1);
+                    // weighted count of "aligned" neighbours per slice byte
+                    uint32_t acc = 0;
+                    const uint32_t *er = t.ent + i * D;
+                    const uint32_t nb_base = own - (uint32_t)(i * Mh);
+                    for (int e = 0; e < D; ++e) {
+                        const uint32_t ent = er[e];
+                        const uint32_t w = lds32(t.sp, nb_base + (ent >> 16));
+                        acc += __builtin_amdgcn_perm(0u, ent, w);
+                    }
+                    const uint32_t V = __builtin_amdgcn_perm(0u, sel_x, X) + (acc << 1) + t.bias[i];
+                    const uint32_t IDX = V + (V << 1) + T;  // 3V + tau in every byte
+                    const uint32_t *tb = t.tbl + q * tw;
+                    uint32_t flip = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const uint32_t thr = tb[(IDX >> (8 * b)) & 0xFFu];
+                        flip |= (u.w[b] <= thr ? 1u : 0u) << (8 * b);
+                    }
+                    *reinterpret_cast<uint32_t *>(t.sp + own) = X ^ flip;
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    // E_cl and C of every replica of the tile from its final spins
+    for (int q = 0; q < tile.P; ++q) {
+        long long ee = 0, cc = 0;
+        const uint32_t qbase = (uint32_t)q * NM;
+        for (int it = tid; it < N * G4; it += nt) {
+            const int i = it >> lgG4;
+            const int g4 = it & (G4 - 1);
+            const uint32_t row = (uint32_t)(i * Mh + 4 * g4);
+            const uint32_t X0 = lds32(t.sp, qbase + row);
+            const uint32_t X1 = lds32(t.sp, qbase + NMh + row);
+            const uint32_t X0n = lds32(t.sp, qbase + (uint32_t)(i * Mh + 4 * ((g4 + 1) & (G4 - 1))));
+            // time bonds (2m, 2m+1) and (2m+1, 2m+2): 8 per group
+            const uint32_t dis_t = popc(X0 ^ X1) + popc(X1 ^ __builtin_amdgcn_alignbyte(X0n, X0, 1));
+            cc += 8 - 2 * (long long)dis_t;
+            // fields over the group's 8 slices
+            const int hval = (int)(t.bias[i] & 0xFFu) - F;  // h - sum|J|
+            int sumJ = 0;
+            const uint32_t *er = t.ent + i * D;
+            long long eterm = 0;
+            for (int e = 0; e < D; ++e) {
+                const uint32_t ent = er[e];
+                const int w0 = (int)(ent & 0xFFu), w1 = (int)((ent >> 8) & 0xFFu);
+                const int J = w1 - w0;
+                sumJ += w0 + w1;
+                const uint32_t joff = ent >> 16;
+                if (J != 0 && joff > (uint32_t)(i * Mh)) {  // each edge once (j > i)
+                    const uint32_t Y0 = lds32(t.sp, qbase + joff + 4 * g4);
+                    const uint32_t Y1 = lds32(t.sp, qbase + NMh + joff + 4 * g4);
+                    eterm += (long long)J * (8 - 2 * (long long)(popc(X0 ^ Y0) + popc(X1 ^ Y1)));
+                }
+            }
+            const int h = hval + sumJ;
+            eterm += (long long)h * (2 * (long long)(popc(X0) + popc(X1)) - 8);
+            ee += eterm;
+        }
+        ee = block_sum(ee, t.red);
+        cc = block_sum(cc, t.red);
+        if (tid == 0) {
+            st.E[d.rep_base + tile.c0 + q] = ee;
+            st.C[d.rep_base + tile.c0 + q] = cc;
+        }
+    }
+    write_back(st, d, tile, t);
+}
+
+// ------------------------------------------------------------------ generic sweep
+
+__device__ __forceinline__ int lds_x(const uint8_t *rep, const InstDesc &d, int k, int i)
+{
+    const int p = (d.M >= 2) ? (k & 1) : 0;
+    const int m = (d.M >= 2) ? (k >> 1) : 0;
+    return rep[p * d.N * d.Mh + i * d.Mh + m];
+}
+
+__global__ void __launch_bounds__(1024) sweep_generic_kernel(SweepLaunch L)
+{
+    extern __shared__ __align__(16) char lds[];
+    const DevState &st = L.st;
+    const Tile tile = st.tiles[L.tile0 + blockIdx.x];
+    const int n = tile.inst;
+    const InstDesc d = st.inst[n];
+    const int n_adj = st.adj_off[d.off_base + d.N];
+    TileLds t = carve(lds, d, n_adj, tile.P);
+    stage_common(st, d, n, tile, t, n_adj);
+    const uint64_t t0 = st.ctr[n].t;
+    __syncthreads();
+
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int N = d.N, M = d.M, Mh = d.Mh, G4 = d.G4, F = d.F;
+    const int rep_lds = (int)rep_lds_bytes(d);
+    const int Lq = tile.P * G4;  // lanes per site
     const int bstride = 2 * F + 1;
 
     for (int sw = 0; sw < L.n_sweeps; ++sw) {
         const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
-        for (int p = 0; p < parities; ++p) {
+        for (int p = 0; p < d.parities; ++p) {
             for (int g = 0; g < d.n_colors; ++g) {
-                const int e0 = t.cls[g];
-                const int nb = t.cls[g + 1] - e0;
-                const int per_rep = Mc * nb;
-                const int items = P * per_rep;
+                const int s0 = t.coff[g];
+                const int items = (t.coff[g + 1] - s0) * Lq;
                 for (int it = tid; it < items; it += nt) {
-                    const int q = it / per_rep;
-                    const int rem = it - q * per_rep;
-                    const int mi = rem / nb;
-                    const int ei = rem - mi * nb;
-                    const int k = (M >= 2) ? 2 * mi + p : 0;
-                    const uint32_t ent = t.blk[e0 + ei];
-                    const int bq = (int)(ent >> 4);
-                    const uint32_t mask = ent & 15u;
-                    const Words4 u = philox10((uint32_t)k * (uint32_t)d.Nq + (uint32_t)bq, tt,
-                                              (uint32_t)(c0 + q), (uint32_t)n, L.key0, L.key1);
-                    int8_t *row = t.sp + (q * M + k) * Npad;
-                    const int8_t *prv = t.sp + (q * M + (k == 0 ? M - 1 : k - 1)) * Npad;
-                    const int8_t *nxt = t.sp + (q * M + (k + 1 == M ? 0 : k + 1)) * Npad;
+                    const int si = it / Lq;
+                    const int r = it - si * Lq;
+                    const int q = r / G4;
+                    const int g4 = r - q * G4;
+                    const int i = t.csite[s0 + si];
+                    uint8_t *rep = t.sp + q * rep_lds;
+                    const Words4 u = philox10(spin_ctr0(i, p, G4, g4), tt,
+                                              (uint32_t)(tile.c0 + q), (uint32_t)n, L.key0, L.key1);
                     const uint32_t *tb = t.tbl + q * d.tbl_words;
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        if (!((mask >> b) & 1u)) continue;
-                        const int i = 4 * bq + b;
-                        const int s = row[i];
+                        const int m = 4 * g4 + b;
+                        if (m >= Mh) break;
+                        const int k = (M >= 2) ? 2 * m + p : 0;
+                        uint8_t *cell = rep + p * N * Mh + i * Mh + m;
+                        const int x = *cell;
                         int f = t.h[i];
                         for (int e = t.off[i]; e < t.off[i + 1]; ++e) {
                             const int a = t.adj[e];
-                            f += (a >> 16) * row[a & 0xFFFF];
+                            f += (a >> 16) * (2 * (int)rep[p * N * Mh + (a & 0xFFFF) * Mh + m] - 1);
                         }
-                        const int tau = (M >= 2) ? ((prv[i] + nxt[i]) >> 1) + 1 : 1;
-                        const int idx = ((s > 0 ? bstride : 0) + f + F) * 3 + tau;
-                        if (u.w[b] <= tb[idx]) row[i] = (int8_t)(-s);
+                        int tau = 1;
+                        if (M >= 2)
+                            tau = lds_x(rep, d, (k == 0) ? M - 1 : k - 1, i) +
+                                  lds_x(rep, d, (k + 1 == M) ? 0 : k + 1, i);
+                        const int idx = (x * bstride + f + F) * 3 + tau;
+                        if (u.w[b] <= tb[idx]) *cell = (uint8_t)(x ^ 1);
                     }
                 }
                 __syncthreads();
             }
         }
     }
-    (void)N;
 
-    // energies of the final configuration, then write the spins back
-    for (int q = 0; q < P; ++q) {
+    for (int q = 0; q < tile.P; ++q) {
         long long e2 = 0, cc = 0;
+        const uint8_t *rep = t.sp + q * rep_lds;
         for (int it = tid; it < M * N; it += nt) {
             const int k = it / N;
             const int i = it - k * N;
-            const int8_t *row = t.sp + (q * M + k) * Npad;
-            const int s = row[i];
+            const int s = 2 * lds_x(rep, d, k, i) - 1;
             int f = 2 * t.h[i];
             for (int e = t.off[i]; e < t.off[i + 1]; ++e) {
                 const int a = t.adj[e];
-                f += (a >> 16) * row[a & 0xFFFF];
+                f += (a >> 16) * (2 * lds_x(rep, d, k, a & 0xFFFF) - 1);
             }
             e2 += (long long)s * f;
-            if (M >= 2) cc += (long long)s * t.sp[(q * M + (k + 1 == M ? 0 : k + 1)) * Npad + i];
+            if (M >= 2) cc += (long long)s * (2 * lds_x(rep, d, (k + 1 == M) ? 0 : k + 1, i) - 1);
         }
         e2 = block_sum(e2, t.red);
         cc = block_sum(cc, t.red);
         if (tid == 0) {
-            st.E[d.rep_base + c0 + q] = e2 / 2;
-            st.C[d.rep_base + c0 + q] = cc;
+            st.E[d.rep_base + tile.c0 + q] = e2 / 2;
+            st.C[d.rep_base + tile.c0 + q] = cc;
         }
     }
-    {
-        uint32_t *dst = reinterpret_cast<uint32_t *>(st.spins + d.spin_base +
-                                                     (int64_t)c0 * d.M * d.Npad);
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(t.sp);
-        const int words = P * d.M * d.Npad / 4;
-        for (int w = tid; w < words; w += nt) dst[w] = src[w];
-    }
+    write_back(st, d, tile, t);
 }
 
 // ------------------------------------------------------------------ exchange
@@ -338,47 +533,47 @@ __global__ void threshold_eval_kernel(const double *dS, uint32_t *out, int32_t n
 
 // ------------------------------------------------------------------ launchers
 
-int32_t sweep_tile_lds_bytes(const InstDesc &d, int32_t n_adj, int32_t n_blk, int32_t P)
+int32_t sweep_tile_lds_bytes(const InstDesc &d, int32_t n_adj, int32_t P)
 {
-    auto a16 = [](int64_t x) { return (x + 15) & ~(int64_t)15; };
-    int64_t o = 0;
-    o = a16(o + (int64_t)P * d.M * d.Npad);
-    o = a16(o + (int64_t)n_adj * 4);
-    o = a16(o + (int64_t)(d.N + 1) * 4);
-    o = a16(o + (int64_t)d.N * 2);
-    o = a16(o + (int64_t)n_blk * 4);
-    o = a16(o + (int64_t)(d.n_colors + 1) * 4);
-    o = a16(o + (int64_t)P * d.tbl_words * 4);
-    o = a16(o + 16 * 8);
-    return (int32_t)(o > 0x7fffffff ? 0x7fffffff : o);
+    int64_t o[10];
+    const int64_t x = carve_offsets(d, n_adj, P, o);
+    return (int32_t)(x > 0x7fffffff ? 0x7fffffff : x);
 }
 
-hipError_t sweep_kernel_set_lds(int32_t bytes)
+hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_tile_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = hipSuccess;
+    if (fast_bytes > 0)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_fast_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, fast_bytes);
+    if (e == hipSuccess && generic_bytes > 0)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_generic_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, generic_bytes);
+    return e;
 }
 
-hipError_t launch_init_spins(const DevState &st, const int32_t *rep_inst, int32_t n_reps,
-                             uint32_t key0, uint32_t key1, hipStream_t s)
+hipError_t launch_init_spins(const DevState &st, int32_t n_reps, uint32_t key0, uint32_t key1,
+                             hipStream_t s)
 {
     if (n_reps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(init_spins_kernel, dim3(n_reps), dim3(256), 0, s, st, rep_inst, key0, key1);
+    hipLaunchKernelGGL(init_spins_kernel, dim3(n_reps), dim3(256), 0, s, st, key0, key1);
     return hipGetLastError();
 }
 
-hipError_t launch_energy(const DevState &st, const int32_t *rep_inst, int32_t rep_first,
-                         int32_t n_reps, hipStream_t s)
+hipError_t launch_energy(const DevState &st, int32_t rep_first, int32_t n_reps, hipStream_t s)
 {
     if (n_reps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(energy_kernel, dim3(n_reps), dim3(256), 0, s, st, rep_inst, rep_first);
+    hipLaunchKernelGGL(energy_kernel, dim3(n_reps), dim3(256), 0, s, st, rep_first);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SweepLaunch &L, hipStream_t s)
+hipError_t launch_sweep(const SweepLaunch &L, bool fast, hipStream_t s)
 {
     if (L.n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sweep_tile_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
+    if (fast)
+        hipLaunchKernelGGL(sweep_fast_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
+    else
+        hipLaunchKernelGGL(sweep_generic_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
     return hipGetLastError();
 }
 

@@ -62,6 +62,33 @@ def edge_batch():
     return out
 
 
+def fast_batch():
+    """Shapes the byte-SWAR kernel takes (M a power-of-two multiple of 8, fields up to
+    20): ragged N, a lone spin, the largest field the byte lanes hold, M = 256, odd R,
+    colours that are not contiguous label ranges, and general integer couplings."""
+    rng = np.random.default_rng([1004, 24])
+    lone = W.make_instance(1, np.zeros((0, 2), np.int32), np.zeros(0, np.int8),
+                           np.array([-1], np.int8), 8, [0.4, 0.9, 1.7], 1.0, name="lone8")
+    # F = 20: a 5-regular graph with |J| = 4 and h = 0
+    N = 10
+    edges = W.random_regular_graph(N, 5, rng)
+    J = rng.choice(np.array([-4, 4], np.int8), size=edges.shape[0])
+    maxf = W.make_instance(N, edges, J, np.zeros(N, np.int8), 16, [0.5, 1.0, 3.0, 9.0], 1.0,
+                           name="F20")
+    assert maxf.F() == 20
+    return [
+        lone,
+        W.random_small_instance(rng, 5, 8, 3, d=2, jmax=2, hmax=2, name="ragged8"),
+        maxf,
+        W.random_small_instance(rng, 7, 256, 2, d=2, jmax=1, hmax=1, name="m256"),
+        W.random_small_instance(rng, 13, 16, 5, d=4, jmax=3, hmax=2, relabel=False,
+                                name="noncontig16"),
+        W.random_small_instance(rng, 9, 32, 7, d=8, jmax=1, hmax=1, name="dense32"),
+        W.random_small_instance(rng, 30, 8, 6, d=3, jmax=3, hmax=0, t_min=0.2, t_max=5.0,
+                                name="general8"),
+    ]
+
+
 def oracle_batch(insts, seed, k, cycles, extra_sweeps=0):
     refs = []
     for n, inst in enumerate(insts):
@@ -84,8 +111,8 @@ def test_device_threshold_bitwise(ptqmc):
 
 
 def test_init_matches_oracle(ptqmc):
-    say("case: init, edge batch")
-    insts = edge_batch()
+    say("case: init, edge and fast batches")
+    insts = edge_batch() + fast_batch()
     seed = 0xABCDEF0123456789
     with ptqmc.Sampler(insts, seed, sweeps_per_exchange=1) as s:
         for n, inst in enumerate(insts):
@@ -114,12 +141,14 @@ def test_config2_truncated(ptqmc):
         assert_same(s, 0, ref, "config2")
 
 
+@pytest.mark.parametrize("batch", ["edge", "fast", "mixed"])
 @pytest.mark.parametrize("tile_replicas,block_threads", [(0, 0), (1, 64), (3, 512), (2, 1024)])
-def test_edge_batch_launch_shapes(ptqmc, tile_replicas, block_threads):
-    insts = edge_batch()
+def test_batch_launch_shapes(ptqmc, batch, tile_replicas, block_threads):
+    insts = {"edge": edge_batch, "fast": fast_batch,
+             "mixed": lambda: fast_batch()[:4] + edge_batch()[:4]}[batch]()
     seed = 0x10040023
     k, cycles = 3, 25
-    say(f"case: edge batch, tile_replicas={tile_replicas} block_threads={block_threads}")
+    say(f"case: {batch} batch, tile_replicas={tile_replicas} block_threads={block_threads}")
     refs = oracle_batch(insts, seed, k, cycles)
     with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_replicas=tile_replicas,
                        block_threads=block_threads) as s:
