@@ -23,8 +23,10 @@
  *                  attempt a flip at every (replica c, slice k = p mod 2, site i of colour
  *                  g).  Field f = h_i + sum_j J_ij s_j^k, t' = s_i^{k-1} + s_i^{k+1};
  *                  dE = -2 s f, dC = -2 s t', dS = b*dE - K*dC (FP64, no fused ops);
- *                  flip iff u <= thr(dS), u = word (i mod 4) of
- *                  Philox4x32-10(ctr = (k*ceil(N/4) + i/4, t, c, n), key = (lo(seed), hi(seed))).
+ *                  flip iff u <= thr(dS).  With k = 2m + p (M == 1: p = m = 0),
+ *                  Mh = M/2 (1 if M == 1) and G = ceil(Mh/4), u = word (m mod 4) of
+ *                  Philox4x32-10(ctr = ((2i + p)*G + m/4, t, c, n), key = (lo(seed), hi(seed))):
+ *                  one call serves four same-parity slices of one site.
  *   thr(dS)      : 2^32-1 if dS <= 0, else clamp(floor(exp(-dS) * 2^32), 1, 2^32-1) - 1,
  *                  with exp evaluated by a fixed sequence of IEEE operations.
  *   exchange e   : pairs (r, r+1), r = e mod 2, e mod 2 + 2, ...; with x, y the replicas at
@@ -34,10 +36,9 @@
  *                  Then: the replica at rung 0 labelled DOWN completes a round trip and
  *                  becomes UP (NONE becomes UP); the replica at rung R-1 labelled UP becomes
  *                  DOWN; per rung, E_cl, C and their squares are accumulated.
- *   init         : s = +1 iff the top bit of word (i mod 4) of
- *                  Philox(ctr = (k*ceil(N/4) + i/4, 0, c, n), key = (lo, hi ^ 0x494E4954)).
- * Vertex labels are used as given: a colour-contiguous labelling makes the four sites of
- * a Philox block share a colour class and is the fast layout.
+ *   init         : s = +1 iff the top bit of word (m mod 4) of
+ *                  Philox(ctr = ((2i + p)*G + m/4, 0, c, n), key = (lo, hi ^ 0x494E4954)).
+ * Vertex labels and colours are used as given (any proper colouring).
  *
  * Conventions.  Every function returning int returns PT_OK (0) or a negative PT_E*
  * code; nothing aborts or throws across this boundary.  pt_last_error() returns a
@@ -64,7 +65,7 @@ extern "C" {
 #define PT_ESTATE (-5)  /* call not valid in the context's state (e.g. bad checkpoint)     */
 
 /* spin encodings (the trajectory is identical under every encoding) */
-#define PT_INT8 0       /* one int8 (+1/-1) per spin                                       */
+#define PT_INT8 0       /* one byte per spin                                                */
 #define PT_BITPACK32 1  /* 32 replicas per uint32 word: bit (c mod 32) of word c/32 at (k, i) */
 
 /* round-trip labels */
@@ -98,14 +99,19 @@ typedef struct {
 } pt_instance;
 
 /* Sampler options.  seed keys every draw; sweeps_per_exchange (k >= 1) is the number of
- * sweeps per pt_run cycle.  tile_replicas and block_threads override the tuner when
- * positive (0 = choose automatically). */
+ * sweeps per pt_run cycle.  Launch shape: a workgroup sweeps a tile of replicas of one
+ * instance held in LDS.  tile_replicas (replicas per tile) or tile_bytes (target spin
+ * bytes per tile) and block_threads (a multiple of 64, at most 1024) fix the shape when
+ * positive.  When all three are 0 the library tunes itself: its first sweep launches try
+ * a few shapes, timed with HIP events, and keep the fastest (the trajectory does not
+ * depend on the shape, so nothing is repeated or lost). */
 typedef struct {
     uint64_t seed;
     int32_t sweeps_per_exchange;
     int32_t encoding;
     uint32_t flags;
     int32_t tile_replicas;
+    int32_t tile_bytes;
     int32_t block_threads;
 } pt_options;
 
@@ -126,6 +132,7 @@ typedef struct {
 typedef struct {
     int32_t n_instances, n_tiles, block_threads, lds_bytes;
     int32_t max_tile_replicas, fallbacks, encoding, device_cus;
+    int32_t tile_bytes, tuned;        /* chosen target tile bytes; 1 once tuning ended */
     uint64_t flips_per_sweep;         /* sum over instances of R*N*M                 */
     double sweep_ms;                  /* summed event time of timed sweep launches   */
     int64_t sweep_launches;           /* number of timed sweep launches              */

@@ -309,6 +309,13 @@ struct pt_ctx {
     std::vector<Tile> tiles;   // fast-kernel tiles first, then generic ones
     int n_fast_tiles = 0;
     int block_threads = 256;
+    int tile_bytes = 0;        // target spin bytes per tile in use
+    // self-tuning: candidate (tile bytes, threads) shapes timed on the first sweep launches
+    bool tuning = false;
+    std::vector<std::pair<int, int>> cand;
+    std::vector<double> cand_ms;
+    size_t cand_next = 0;
+    hipEvent_t tune_ev[2] = {nullptr, nullptr};
     int lds_fast = 0, lds_generic = 0;
     int max_P = 1;
     int lds_limit = 65536;
@@ -334,7 +341,7 @@ int n_inst_of(const pt_ctx *c) { return (int)c->plan.desc.size(); }
 // two on the fast path), sized so the batch yields a few workgroups per CU when it can
 // (the paper's chain packing, Section 5, stops packing once multiprocessors would go
 // idle).
-int build_tiles(pt_ctx *c, int force_P)
+int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
 {
     const Plan &P = c->plan;
     // the tile list is uploaded from c->tiles: let any earlier upload finish first
@@ -343,6 +350,8 @@ int build_tiles(pt_ctx *c, int force_P)
     for (const auto &d : P.desc) total_bytes += (int64_t)d.R * d.N * d.M;
     int64_t target_bytes = std::max<int64_t>(total_bytes / (2ll * c->cus), 4096);
     target_bytes = std::min<int64_t>(target_bytes, 64 * 1024);
+    if (tile_bytes > 0) target_bytes = tile_bytes;
+    c->tile_bytes = (int)target_bytes;
     std::vector<Tile> fast, generic;
     int lds_f = 0, lds_g = 0, maxP = 1;
     for (int n = 0; n < (int)P.desc.size(); ++n) {
@@ -445,7 +454,7 @@ bool out_of_resources(hipError_t e)
 // Launch n sweeps of every tile; on a resource failure halve the tile (and, at one
 // replica per tile, the workgroup) and retry, as the paper's Figure 7 halves its chain
 // packing when a launch runs out of registers.
-int enqueue_sweep(pt_ctx *c, int n_sweeps)
+int enqueue_sweep_once(pt_ctx *c, int n_sweeps)
 {
     if (n_sweeps <= 0) return PT_OK;
     const bool timing = (c->opt.flags & PT_FLAG_TIMING) != 0;
@@ -491,7 +500,7 @@ int enqueue_sweep(pt_ctx *c, int n_sweeps)
         c->fallbacks++;
         drop_graph(c);
         if (c->max_P > 1) {
-            int rc = build_tiles(c, std::max(1, c->max_P / 2));
+            int rc = build_tiles(c, std::max(1, c->max_P / 2), 0);
             if (rc) return rc;
         } else if (c->block_threads > 64) {
             c->block_threads /= 2;
@@ -500,6 +509,39 @@ int enqueue_sweep(pt_ctx *c, int n_sweeps)
                                         hipGetErrorString(e));
         }
     }
+}
+
+// Self-tuning: while candidates remain, each sweep launch uses the next candidate shape
+// and is timed (synchronously) with its own events; afterwards the fastest per-sweep
+// shape is kept.  Launch shape does not change the trajectory, so tuning costs only the
+// slower candidates' extra time.
+int enqueue_sweep(pt_ctx *c, int n_sweeps)
+{
+    if (n_sweeps <= 0) return PT_OK;
+    if (!c->tuning) return enqueue_sweep_once(c, n_sweeps);
+    const auto shape = c->cand[c->cand_next];
+    int rc = build_tiles(c, 0, shape.first);
+    if (rc) return rc;
+    c->block_threads = shape.second;
+    HIP_TRY(hipEventRecord(c->tune_ev[0], c->stream));
+    const int fb = c->fallbacks;
+    rc = enqueue_sweep_once(c, n_sweeps);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(c->tune_ev[1], c->stream));
+    HIP_TRY(hipEventSynchronize(c->tune_ev[1]));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, c->tune_ev[0], c->tune_ev[1]));
+    c->cand_ms[c->cand_next] = (c->fallbacks == fb) ? (double)ms / n_sweeps : 1e30;
+    if (++c->cand_next == c->cand.size()) {
+        size_t best = 0;
+        for (size_t k = 1; k < c->cand.size(); ++k)
+            if (c->cand_ms[k] < c->cand_ms[best]) best = k;
+        c->tuning = false;
+        rc = build_tiles(c, 0, c->cand[best].first);
+        if (rc) return rc;
+        c->block_threads = c->cand[best].second;
+    }
+    return PT_OK;
 }
 
 int enqueue_exchange(pt_ctx *c, uint32_t t_add)
@@ -561,7 +603,8 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
         return fail(PT_EINVAL, "unknown encoding");
     if (opt->block_threads < 0 || opt->block_threads > 1024 || (opt->block_threads % 64))
         return fail(PT_EINVAL, "block_threads must be a multiple of 64 in [64, 1024] or 0");
-    if (opt->tile_replicas < 0) return fail(PT_EINVAL, "tile_replicas must be >= 0");
+    if (opt->tile_replicas < 0 || opt->tile_bytes < 0)
+        return fail(PT_EINVAL, "tile_replicas and tile_bytes must be >= 0");
     pt_ctx *c = new (std::nothrow) pt_ctx();
     if (!c) return fail(PT_ENOMEM, "host allocation failed");
     int rc = make_plan(inst, n_inst, c->plan);
@@ -674,9 +717,19 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     if (e != hipSuccess) return cleanup(hip_fail(e, "init launch"));
     e = launch_energy(st, 0, (int)P.total_reps, c->stream);
     if (e != hipSuccess) return cleanup(hip_fail(e, "energy launch"));
-    c->block_threads = opt->block_threads > 0 ? opt->block_threads : 256;
-    rc = build_tiles(c, opt->tile_replicas);
+    c->block_threads = opt->block_threads > 0 ? opt->block_threads : 1024;
+    rc = build_tiles(c, opt->tile_replicas, opt->tile_bytes);
     if (rc) return cleanup(rc);
+    if (opt->tile_replicas == 0 && opt->tile_bytes == 0 && opt->block_threads == 0) {
+        for (int tb : {8 * 1024, 32 * 1024, 64 * 1024, 128 * 1024})
+            for (int th : {512, 1024}) c->cand.emplace_back(tb, th);
+        c->cand_ms.assign(c->cand.size(), 0.0);
+        c->tuning = true;
+        for (auto &ev : c->tune_ev) {
+            e = hipEventCreate(&ev);
+            if (e != hipSuccess) return cleanup(hip_fail(e, "hipEventCreate"));
+        }
+    }
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return cleanup(hip_fail(e, "init synchronise"));
     *out = c;
@@ -706,7 +759,7 @@ int pt_run(pt_ctx *c, int32_t n_cycles)
     if (!c) return fail(PT_EINVAL, "null context");
     if (n_cycles < 0) return fail(PT_EINVAL, "n_cycles < 0");
     const bool eager = (c->opt.flags & (PT_FLAG_NO_GRAPH | PT_FLAG_TIMING)) != 0 ||
-                       c->inject_pending;
+                       c->inject_pending || c->tuning;
     if (eager) {
         for (int i = 0; i < n_cycles; ++i) {
             int rc = enqueue_cycle(c);
@@ -894,6 +947,8 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->fallbacks = c->fallbacks;
     o->encoding = c->opt.encoding;
     o->device_cus = c->cus;
+    o->tile_bytes = c->tile_bytes;
+    o->tuned = c->tuning ? 0 : 1;
     o->flips_per_sweep = c->plan.flips_per_sweep;
     o->sweep_ms = c->sweep_ms;
     o->sweep_launches = c->sweep_n;
@@ -918,6 +973,8 @@ void pt_free(pt_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto e : c->tune_ev)
+        if (e) (void)hipEventDestroy(e);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

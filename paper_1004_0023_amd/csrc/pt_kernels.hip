@@ -245,6 +245,118 @@ __device__ __forceinline__ uint32_t lds32(const uint8_t *base, uint32_t byte_off
 
 __device__ __forceinline__ uint32_t popc(uint32_t x) { return (uint32_t)__popc(x); }
 
+// n sweeps of one tile on the fast path; DT > 0 fixes the (padded) degree at compile time
+// so the neighbour loads of a lane are issued together.
+// One lane's update of site i, replica q, slice group g4 in parity p: four Metropolis
+// attempts served by one Philox call.  DT > 0 fixes the (padded) degree at compile time
+// so the neighbour loads are issued together.
+template <int DT>
+__device__ __forceinline__ void fast_item(const SweepLaunch &L, const InstDesc &d,
+                                          const TileLds &t, int n, uint32_t tt, uint32_t c0,
+                                          int p, int i, int q, int g4, int lgMh)
+{
+    const int G4 = d.G4;
+    const int D = (DT > 0) ? DT : d.D;
+    const uint32_t NM = (uint32_t)(d.N * d.M), NMh = (uint32_t)(d.N * d.Mh);
+    const uint32_t qbase = (uint32_t)q * NM;
+    const uint32_t irow = (uint32_t)i << lgMh;
+    const uint32_t nb_base = qbase + (uint32_t)p * NMh + 4u * (uint32_t)g4;
+    const uint32_t own = nb_base + irow;
+    const uint32_t oth_row = qbase + (uint32_t)(p ^ 1) * NMh + irow;
+    const uint32_t X = lds32(t.sp, own);
+    const uint32_t Wc = lds32(t.sp, oth_row + 4 * g4);
+    // time neighbours live in the other parity: byte b of T is x(k-1) + x(k+1)
+    uint32_t T;
+    if (p == 0) {
+        const uint32_t Wp = lds32(t.sp, oth_row + 4 * ((g4 - 1) & (G4 - 1)));
+        T = __builtin_amdgcn_alignbyte(Wc, Wp, 3) + Wc;
+    } else {
+        const uint32_t Wn = lds32(t.sp, oth_row + 4 * ((g4 + 1) & (G4 - 1)));
+        T = __builtin_amdgcn_alignbyte(Wn, Wc, 1) + Wc;
+    }
+    // weighted count of neighbours per slice byte
+    const uint32_t *er = t.ent + i * D;
+    uint32_t acc = 0;
+    if (DT > 0) {
+        uint32_t ents[DT > 0 ? DT : 1], ws[DT > 0 ? DT : 1];
+#pragma unroll
+        for (int e = 0; e < DT; ++e) ents[e] = er[e];
+#pragma unroll
+        for (int e = 0; e < DT; ++e) ws[e] = lds32(t.sp, nb_base + (ents[e] >> 16));
+#pragma unroll
+        for (int e = 0; e < DT; ++e) acc += __builtin_amdgcn_perm(0u, ents[e], ws[e]);
+    } else {
+        for (int e = 0; e < D; ++e) {
+            const uint32_t ent = er[e];
+            acc += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, nb_base + (ent >> 16)));
+        }
+    }
+    const Words4 u = philox10(spin_ctr0(i, p, G4, g4), tt, c0 + (uint32_t)q, (uint32_t)n,
+                              L.key0, L.key1);
+    const uint32_t sel_x = (uint32_t)(2 * d.F + 1) << 8;  // v_perm table: x -> x * (2F + 1)
+    const uint32_t V = __builtin_amdgcn_perm(0u, sel_x, X) + (acc << 1) + t.bias[i];
+    const uint32_t IDX = V + (V << 1) + T;  // 3V + tau in every byte
+    const uint32_t *tb = t.tbl + q * d.tbl_words;
+    uint32_t flip = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t thr = tb[(IDX >> (8 * b)) & 0xFFu];
+        flip |= (u.w[b] <= thr ? 1u : 0u) << (8 * b);
+    }
+    *reinterpret_cast<uint32_t *>(t.sp + own) = X ^ flip;
+}
+
+// n sweeps of one tile on the fast path.  A class holds ns sites x P replicas x G4 slice
+// groups; lanes run over slice groups fastest, so the lanes of a site read one neighbour
+// row entry (broadcast) and consecutive words of each neighbour row.
+template <int DT>
+__device__ __forceinline__ void fast_sweeps(const SweepLaunch &L, const InstDesc &d,
+                                            const Tile &tile, const TileLds &t, uint64_t t0)
+{
+    const int n = tile.inst;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lgG4 = ilog2(d.G4);
+    const int lgMh = lgG4 + 2;  // Mh = 4 * G4 on the fast path
+    const int lgL = ilog2(tile.P) + lgG4;  // lanes per site: P * G4
+    const int Lmask = (1 << lgL) - 1;
+    const uint32_t c0 = (uint32_t)tile.c0;
+    if ((1 << lgL) <= nt) {
+        // every thread keeps one (replica, slice group) and strides over the sites
+        const int r = tid & Lmask;
+        const int q = r >> lgG4;
+        const int g4 = r & (d.G4 - 1);
+        const int sstep = nt >> lgL;
+        for (int sw = 0; sw < L.n_sweeps; ++sw) {
+            const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
+            for (int p = 0; p < 2; ++p) {
+                for (int g = 0; g < d.n_colors; ++g) {
+                    const int s0 = t.coff[g];
+                    const int s1 = t.coff[g + 1];
+                    for (int si = s0 + (tid >> lgL); si < s1; si += sstep)
+                        fast_item<DT>(L, d, t, n, tt, c0, p, t.csite[si], q, g4, lgMh);
+                    __syncthreads();
+                }
+            }
+        }
+    } else {
+        for (int sw = 0; sw < L.n_sweeps; ++sw) {
+            const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
+            for (int p = 0; p < 2; ++p) {
+                for (int g = 0; g < d.n_colors; ++g) {
+                    const int s0 = t.coff[g];
+                    const int items = (t.coff[g + 1] - s0) << lgL;
+                    for (int it = tid; it < items; it += nt) {
+                        const int r = it & Lmask;
+                        fast_item<DT>(L, d, t, n, tt, c0, p, t.csite[s0 + (it >> lgL)],
+                                      r >> lgG4, r & (d.G4 - 1), lgMh);
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+    }
+}
+
 __global__ void __launch_bounds__(1024) sweep_fast_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
@@ -257,67 +369,22 @@ __global__ void __launch_bounds__(1024) sweep_fast_kernel(SweepLaunch L)
     const uint64_t t0 = st.ctr[n].t;
     __syncthreads();
 
+    switch (d.D) {
+    case 1: fast_sweeps<1>(L, d, tile, t, t0); break;
+    case 2: fast_sweeps<2>(L, d, tile, t, t0); break;
+    case 3: fast_sweeps<3>(L, d, tile, t, t0); break;
+    case 4: fast_sweeps<4>(L, d, tile, t, t0); break;
+    case 5: fast_sweeps<5>(L, d, tile, t, t0); break;
+    case 6: fast_sweeps<6>(L, d, tile, t, t0); break;
+    case 7: fast_sweeps<7>(L, d, tile, t, t0); break;
+    case 8: fast_sweeps<8>(L, d, tile, t, t0); break;
+    default: fast_sweeps<0>(L, d, tile, t, t0); break;
+    }
+
     const int tid = threadIdx.x, nt = blockDim.x;
     const int N = d.N, Mh = d.Mh, G4 = d.G4, D = d.D, F = d.F;
     const uint32_t NM = (uint32_t)(N * d.M), NMh = (uint32_t)(N * Mh);
     const int lgG4 = ilog2(G4);
-    const int lgL = ilog2(tile.P) + lgG4;  // lanes per site: P * G4
-    const int Lmask = (1 << lgL) - 1;
-    const uint32_t sel_x = (uint32_t)(2 * F + 1) << 8;  // v_perm table: x -> x * (2F + 1)
-    const int tw = d.tbl_words;
-    const uint32_t c0 = (uint32_t)tile.c0;
-
-    for (int sw = 0; sw < L.n_sweeps; ++sw) {
-        const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
-        for (int p = 0; p < 2; ++p) {
-            for (int g = 0; g < d.n_colors; ++g) {
-                const int s0 = t.coff[g];
-                const int items = (t.coff[g + 1] - s0) << lgL;
-                for (int it = tid; it < items; it += nt) {
-                    const int r = it & Lmask;
-                    const int i = t.csite[s0 + (it >> lgL)];
-                    const int q = r >> lgG4;
-                    const int g4 = r & (G4 - 1);
-                    const uint32_t qbase = (uint32_t)q * NM;
-                    const uint32_t own = qbase + (uint32_t)p * NMh + (uint32_t)(i * Mh + 4 * g4);
-                    const uint32_t oth_row = qbase + (uint32_t)(p ^ 1) * NMh + (uint32_t)(i * Mh);
-                    const uint32_t X = lds32(t.sp, own);
-                    const uint32_t Wc = lds32(t.sp, oth_row + 4 * g4);
-                    // time neighbours live in the other parity: byte b of T is x(k-1) + x(k+1)
-                    uint32_t T;
-                    if (p == 0) {
-                        const uint32_t Wp = lds32(t.sp, oth_row + 4 * ((g4 - 1) & (G4 - 1)));
-                        T = __builtin_amdgcn_alignbyte(Wc, Wp, 3) + Wc;
-                    } else {
-                        const uint32_t Wn = lds32(t.sp, oth_row + 4 * ((g4 + 1) & (G4 - 1)));
-                        T = __builtin_amdgcn_alignbyte(Wn, Wc, 1) + Wc;
-                    }
-                    const Words4 u = philox10(spin_ctr0(i, p, G4, g4), tt, c0 + (uint32_t)q,
-                                              (uint32_t)n, L.key0, L.key1);
-                    // weighted count of "aligned" neighbours per slice byte
-                    uint32_t acc = 0;
-                    const uint32_t *er = t.ent + i * D;
-                    const uint32_t nb_base = own - (uint32_t)(i * Mh);
-                    for (int e = 0; e < D; ++e) {
-                        const uint32_t ent = er[e];
-                        const uint32_t w = lds32(t.sp, nb_base + (ent >> 16));
-                        acc += __builtin_amdgcn_perm(0u, ent, w);
-                    }
-                    const uint32_t V = __builtin_amdgcn_perm(0u, sel_x, X) + (acc << 1) + t.bias[i];
-                    const uint32_t IDX = V + (V << 1) + T;  // 3V + tau in every byte
-                    const uint32_t *tb = t.tbl + q * tw;
-                    uint32_t flip = 0;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const uint32_t thr = tb[(IDX >> (8 * b)) & 0xFFu];
-                        flip |= (u.w[b] <= thr ? 1u : 0u) << (8 * b);
-                    }
-                    *reinterpret_cast<uint32_t *>(t.sp + own) = X ^ flip;
-                }
-                __syncthreads();
-            }
-        }
-    }
 
     // E_cl and C of every replica of the tile from its final spins
     for (int q = 0; q < tile.P; ++q) {

@@ -43,7 +43,7 @@ class _Instance(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("sweeps_per_exchange", C.c_int32),
                 ("encoding", C.c_int32), ("flags", C.c_uint32), ("tile_replicas", C.c_int32),
-                ("block_threads", C.c_int32)]
+                ("tile_bytes", C.c_int32), ("block_threads", C.c_int32)]
 
 
 class _Obs(C.Structure):
@@ -58,6 +58,7 @@ class _Info(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("n_tiles", C.c_int32), ("block_threads", C.c_int32),
                 ("lds_bytes", C.c_int32), ("max_tile_replicas", C.c_int32),
                 ("fallbacks", C.c_int32), ("encoding", C.c_int32), ("device_cus", C.c_int32),
+                ("tile_bytes", C.c_int32), ("tuned", C.c_int32),
                 ("flips_per_sweep", C.c_uint64), ("sweep_ms", C.c_double),
                 ("sweep_launches", C.c_int64), ("exchange_ms", C.c_double),
                 ("exchange_launches", C.c_int64)]
@@ -141,7 +142,8 @@ class Sampler:
 
     def __init__(self, instances: Iterable, seed: int, sweeps_per_exchange: int = 1,
                  encoding: int = PT_INT8, flags: int = 0, tile_replicas: int = 0,
-                 block_threads: int = 0, stream: Optional[torch.cuda.Stream] = None,
+                 block_threads: int = 0, tile_bytes: int = 0,
+                 stream: Optional[torch.cuda.Stream] = None,
                  torch_workspace: bool = True):
         self.instances = list(instances)
         self._keep: List[np.ndarray] = []
@@ -161,7 +163,8 @@ class Sampler:
                                 b.ctypes.data, K.ctypes.data)
         self._recs = recs
         self.opt = _Options(int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweeps_per_exchange),
-                            int(encoding), int(flags), int(tile_replicas), int(block_threads))
+                            int(encoding), int(flags), int(tile_replicas), int(tile_bytes),
+                            int(block_threads))
         L = lib()
         nbytes = C.c_size_t(0)
         _check(L.pt_workspace_bytes(C.cast(recs, C.c_void_p), len(self.instances),

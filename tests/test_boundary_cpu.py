@@ -67,7 +67,7 @@ def _ws_bytes(inst_list, ptqmc, **kw):
         keep += arrs
         recs[n] = ptqmc._Instance(inst.N, inst.M, inst.R, E, inst.n_colors,
                                   *[a.ctypes.data for a in arrs])
-    opt = ptqmc._Options(1, kw.get("k", 1), 0, 0, 0, 0)
+    opt = ptqmc._Options(1, kw.get("k", 1), 0, 0, 0, 0, 0)
     nb = C.c_size_t(0)
     rc = L.pt_workspace_bytes(C.cast(recs, C.c_void_p), len(inst_list), C.byref(opt), C.byref(nb))
     return rc, int(nb.value), L.pt_last_error().decode()
