@@ -1,15 +1,25 @@
 """Benchmark: spin-flip attempts per second of the parallel-tempering sampler on one GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3]
 
 A step is one PT cycle over the whole batch: sweeps_per_exchange Metropolis sweeps of
-every replica of every instance, the energy bookkeeping, then one replica-exchange
-step with its statistics and accumulators.  All state is resident in device memory
-when the timed region starts.  Prints one JSON line.
+every replica of every instance (with the energy bookkeeping of each replica), then one
+replica-exchange step with its statistics, round-trip labels and accumulators.  All
+state is resident in device memory when the timed region starts.  Prints one JSON line.
+
+The default workload is the batched one (512 instances of uneven size in one launch),
+the configuration whose sweep kernel the roofline target refers to; --config 1, 2 or 4
+selects the single-instance workloads.
+
+    python bench.py --copy-calibration BYTES
+
+runs a plain device-to-device copy of BYTES bytes (used to scale the HBM counters of a
+profiler run; prints one JSON line and nothing else).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -18,36 +28,42 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-import numpy as np  # noqa: E402
-
-# MI355X: 256 compute units, 4 SIMDs x 16 lanes each (64 lanes of 32-bit integer work per
-# clock per CU), 2.4 GHz peak engine clock.
+# MI355X: 256 compute units, each with 4 SIMDs of 16 lanes (64 lanes of 32-bit integer
+# work per clock), at a 2.4 GHz peak engine clock.
 CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
-PEAK_INT_OPS = CUS * LANES_PER_CU * CLOCK_HZ  # 3.93e13 full-rate 32-bit VALU ops/s
-MUL64_ISSUE_COST = 4  # a 32x32->64 multiply issues at quarter rate
+PEAK_INT_OPS = CUS * LANES_PER_CU * CLOCK_HZ  # 3.93e13 32-bit VALU lane-ops/s
+
+SWEEP_SOURCE = os.path.join(ROOT, "paper_1004_0023_amd", "csrc", "pt_kernels.hip")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_fast_kernel_config3_traffic.json")
 
 
 def ops_per_flip(avg_degree: float) -> float:
-    """Algorithmic 32-bit VALU work of one Metropolis attempt, in full-rate issue slots:
-    a quarter of a Philox4x32-10 call (10 rounds of two 32x32->64 products and two
-    three-input xors), the spatial field (a multiply-add per neighbour), the time field
-    (one add) and the table index, compare and select (five)."""
-    philox = 10 * (2 * MUL64_ISSUE_COST + 2) / 4.0
-    return philox + 2.0 * avg_degree + 1.0 + 5.0
+    """Algorithmic 32-bit VALU lane-operations of one Metropolis attempt in the byte-SWAR
+    formulation (four same-parity slices of a site per 32-bit word, one Philox call per
+    word):
+      Philox4x32-10, a quarter of a call: 10 rounds x (2 products + 2 three-input xors) / 4 = 10
+      local field: per neighbour one byte lookup and one add, shared by 4 slices     = d / 2
+      time field: one byte-align and one add per word                                 = 0.5
+      threshold index 3V + tau: five operations per word                              = 1.25
+      per attempt: index extraction, comparison, flip-bit merge                       = 3
+      spin update: one xor per word                                                   = 0.25
+    """
+    return 10.0 + avg_degree / 2.0 + 0.5 + 1.25 + 3.0 + 0.25
 
 
 def workload(config: int):
     import workloads as W
     if config == 1:
         insts = [W.config1()]
-        desc = "config1: N=8 3-regular, M=16, R=8, T in [0.1,2.0], Gamma=1"
+        desc = "config1: N=8 3-regular, M=16, R=8, T in [0.1,2.0], Gamma=1, 1 instance"
     elif config == 2:
         insts = [W.config2()]
-        desc = "config2: N=128 6-regular, J in +-{1,2,3}, h=0, M=64, R=32, T in [0.05,3.0], Gamma=1"
+        desc = ("config2: N=128 6-regular, J in +-{1,2,3}, h=0, M=64, R=32, T in [0.05,3.0], "
+                "Gamma=1, 1 instance")
     elif config == 3:
         insts = W.config3()
-        desc = ("config3: 512 instances, N~U[32,512], d~U{4..8}, M in {32,64,128}, "
-                "R in {16,32,64}, T in [0.1,3.0], Gamma=1")
+        desc = ("config3: 512 instances in one launch, N~U[32,512], d~U{4..8}, M in "
+                "{32,64,128}, R in {16,32,64}, T in [0.1,3.0], Gamma=1")
     elif config == 4:
         insts = [W.config4()]
         desc = "config4: 8x8x16 periodic cubic N=1024, J=+-1, h=0, M=256, R=64, Gamma=1.5"
@@ -58,7 +74,7 @@ def workload(config: int):
 
 def cpu_baseline(insts, seed, k, budget_s=15.0):
     """The oracle as it stands, single-threaded on the host, on a bounded sample: whole
-    PT cycles of the first instance (index 0), as many as fit in about budget_s."""
+    PT cycles of the first instance (batch index 0), as many as fit in about budget_s."""
     import oracle
     inst = insts[0]
     ref = oracle.OracleChain(inst, seed, index=0)
@@ -71,8 +87,36 @@ def cpu_baseline(insts, seed, k, budget_s=15.0):
     dt = time.perf_counter() - t0
     flips = cycles * k * inst.flips_per_sweep
     return {"value": flips / dt, "unit": "spin-flip attempts/s", "cores": 1, "kind": "oracle",
-            "sample": f"instance 0 of the workload ({inst.name}), {cycles} cycles x {k} sweeps "
-                      f"+ exchange, {dt:.1f} s single-threaded"}
+            "sample": f"instance 0 of the workload ({inst.name}: N={inst.N} M={inst.M} "
+                      f"R={inst.R}), {cycles} cycles x {k} sweeps + exchange, {dt:.1f} s "
+                      f"on one host thread"}
+
+
+def traffic_per_launch():
+    """HBM bytes per sweep launch from the committed profiler record, or None when the
+    kernel source has changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+        with open(SWEEP_SOURCE, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != digest:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def copy_calibration(nbytes: int):
+    import torch
+    torch.cuda.set_device(0)
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
 def main():
@@ -80,15 +124,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile-replicas", type=int, default=0)
+    ap.add_argument("--tile-bytes", type=int, default=0)
     ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0)
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "instances and replicas are independent between exchanges, so a multi-GPU "
-              "run would shard them, but no multi-GPU path is built", file=sys.stderr)
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}). "
+              "Instances and replicas are independent between exchanges, so a multi-GPU run "
+              "would shard them, but no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -99,12 +147,13 @@ def main():
     insts, desc = workload(args.config)
     k = W.sweeps_per_exchange(args.config)
     seed = W.sampler_seed(args.config)
-    steps = args.steps if args.steps is not None else W.total_sweeps(args.config) // k
+    default_steps = {1: 10_000, 2: 10_000, 3: 1_000, 4: 2_000}[args.config]
+    steps = args.steps if args.steps is not None else default_steps
     print(f"bench: {desc}; {steps} steps of {k} sweeps + exchange", file=sys.stderr, flush=True)
 
     s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=ptqmc.PT_FLAG_TIMING,
-                      tile_replicas=args.tile_replicas, block_threads=args.block_threads)
-    s.run(args.warmup)
+                      tile_bytes=args.tile_bytes, block_threads=args.block_threads)
+    s.run(args.warmup)  # the first launches also tune the launch shape
     s.sync()
     s.timing_reset()
     torch.cuda.synchronize()
@@ -133,15 +182,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": desc, "instances": len(insts), "sweeps_per_exchange": k,
                    "flips_per_step": flips_per_step, "tiles": info["n_tiles"],
-                   "block_threads": info["block_threads"], "lds_bytes": info["lds_bytes"],
-                   "sweep_kernel_ms": avg_sweep_s * 1e3,
-                   "exchange_kernel_ms": info["exchange_ms"] / max(1, info["exchange_launches"])},
+                   "tile_bytes": info["tile_bytes"], "block_threads": info["block_threads"],
+                   "lds_bytes": info["lds_bytes"], "sweep_kernel_ms": avg_sweep_s * 1e3,
+                   "exchange_kernel_ms": info["exchange_ms"] / max(1, info["exchange_launches"]),
+                   "sweep_kernel_flips_per_s": flips_per_step / avg_sweep_s if avg_sweep_s else None,
+                   "ops_per_launch": ops_launch},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": None},
+                     "frac": achieved / peak, "traffic": traffic_per_launch()},
     }
     s.close()
     if not args.no_cpu_baseline:
