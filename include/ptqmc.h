@@ -78,6 +78,9 @@ extern "C" {
 #define PT_FLAG_NO_GRAPH 0x2u      /* pt_run launches eagerly instead of replaying a graph  */
 #define PT_FLAG_INJECT_LAUNCH_OOR_ONCE 0x4u /* test hook: the first sweep launch is treated
                                              as out of resources, exercising the fallback */
+#define PT_FLAG_SLICE_BLOCKS 0x8u  /* split every replica that could use them into slice
+                                      blocks (one launch per parity phase), as replicas
+                                      too large for one workgroup's LDS always are      */
 
 typedef struct pt_ctx pt_ctx;
 

@@ -119,7 +119,8 @@ struct InstDesc {
     int32_t F;         // max |local field|
     int32_t D;         // max degree (fast-path neighbour rows are padded to D)
     int32_t n_colors;
-    int32_t fast;      // 1: byte-SWAR kernel applies to this instance
+    int32_t fast;      // 1: byte-SWAR kernels apply to this instance
+    int32_t ent_sh;    // fast-path entries hold (j << ent_sh); lg(Mh) when j*Mh fits 16 bits
     int32_t rep_base;  // first global replica / rung index
     int32_t pair_base; // first global pair index (R - 1 pairs)
     int32_t adj_base;  // first generic neighbour entry
@@ -133,11 +134,15 @@ struct InstDesc {
     int64_t spin_base; // first spin byte of the instance
 };
 
+enum TileKind { kTileGeneric = 0, kTileFast = 1, kTileBlock = 2 };
+
 struct Tile {
     int32_t inst;  // instance
     int32_t c0;    // first replica slot
-    int32_t P;     // replicas in the tile (a power of two on the fast path)
-    int32_t fast;  // which sweep kernel runs it
+    int32_t P;     // replicas in the tile (a power of two on the fast paths)
+    int32_t kind;  // TileKind: which sweep kernel runs it
+    int32_t g0;    // slice-block tiles: first four-slice group of the block
+    int32_t ng;    // slice-block tiles: groups in the block (a power of two)
 };
 
 struct Counters {
@@ -154,7 +159,7 @@ struct DevState {
     const int32_t *adj;       // generic neighbour entry: (j & 0xFFFF) | (J << 16)
     const int32_t *adj_off;   // per site: first entry (N + 1 per instance)
     const int16_t *hfield;    // per site
-    const uint32_t *ent;      // fast neighbour entry: (j*Mh) << 16 | w1 << 8 | w0
+    const uint32_t *ent;      // fast neighbour entry: (j << ent_sh) << 16 | w1 << 8 | w0
     const uint32_t *bias;     // fast per-site bias (h - sum|J| + F) in every byte
     const uint16_t *csite;    // sites of each colour, colour by colour
     const int32_t *cls_off;   // per colour: first class site (n_colors + 1 per instance)

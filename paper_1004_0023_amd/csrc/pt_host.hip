@@ -58,6 +58,7 @@ struct Plan {
     std::vector<double> db, dK;
     std::vector<int32_t> n_adj;  // per instance
     int64_t total_reps = 0, total_pairs = 0, spin_bytes = 0;
+    int64_t max_tiles = 0;  // tile slots: one per (replica, four-slice group) at most
     uint64_t flips_per_sweep = 0;
     // byte offsets in the workspace
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
@@ -169,8 +170,12 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
         }
         d.F = F;
         d.D = std::max(D, 1);
-        d.fast = (in.M >= 8 && in.M % 8 == 0 && is_pow2(in.M / 8) && F <= 20 &&
-                  (int64_t)(in.N - 1) * d.Mh <= 65535) ? 1 : 0;
+        d.fast = (in.M >= 8 && in.M % 8 == 0 && is_pow2(in.M / 8) && F <= 20) ? 1 : 0;
+        // whole-replica tiles address a neighbour row as j*Mh taken straight from the
+        // entry; when that exceeds 16 bits the entry holds j and only slice blocks run
+        int lgMh = 0;
+        while ((1 << lgMh) < d.Mh) ++lgMh;
+        d.ent_sh = ((int64_t)(in.N - 1) * d.Mh <= 65535) ? lgMh : 0;
         d.tbl_words = table_words(F);
         d.rep_bytes = (int32_t)align_up((size_t)in.N * in.M, 16);
         d.rep_base = (int32_t)rep;
@@ -189,20 +194,20 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
         std::vector<int32_t> cfill(in.n_colors, 0);
         std::vector<uint16_t> sites(in.N);
         for (int i = 0; i < in.N; ++i) sites[cls[in.color[i]] + cfill[in.color[i]]++] = (uint16_t)i;
-        // fast-path rows: D entries per site, (j*Mh) << 16 | w1 << 8 | w0 with w0 / w1 the
+        // fast-path rows: D entries per site, (j << ent_sh) << 16 | w1 << 8 | w0 with w0 / w1 the
         // contribution |J| [J < 0] / |J| [J > 0] of a neighbour whose spin byte is 0 / 1;
         // padding entries point at the site itself with weight 0
         if (d.fast) {
             for (int i = 0; i < in.N; ++i) {
                 int e = deg[i];
                 for (int k = 0; k < d.D; ++k, ++e) {
-                    uint32_t word = ((uint32_t)(i * d.Mh) << 16);
+                    uint32_t word = ((uint32_t)i << d.ent_sh) << 16;
                     if (e < deg[i + 1]) {
                         const int j = entries[e] & 0xFFFF;
                         const int J = entries[e] >> 16;
                         const uint32_t w0 = (J < 0) ? (uint32_t)(-J) : 0u;
                         const uint32_t w1 = (J > 0) ? (uint32_t)J : 0u;
-                        word = ((uint32_t)(j * d.Mh) << 16) | (w1 << 8) | w0;
+                        word = (((uint32_t)j << d.ent_sh) << 16) | (w1 << 8) | w0;
                     }
                     P.ent.push_back(word);
                 }
@@ -229,6 +234,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
         }
         for (int c = 0; c < in.R; ++c) P.rep_inst.push_back(n);
         P.n_adj.push_back(2 * in.n_edges);
+        P.max_tiles += (int64_t)in.R * std::max(1, d.G4);
         P.flips_per_sweep += (uint64_t)in.R * in.N * in.M;
         rep += in.R;
         pair += in.R - 1;
@@ -263,7 +269,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
     P.o_tbl = take(P.tbl.size() * 4);
     P.o_db = take(P.db.size() * 8);
     P.o_dK = take(P.dK.size() * 8);
-    P.o_tiles = take((size_t)rep * sizeof(Tile));
+    P.o_tiles = take((size_t)P.max_tiles * sizeof(Tile));
     P.o_repinst = take((size_t)rep * 4);
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
@@ -306,8 +312,9 @@ struct pt_ctx {
     pt_options opt{};
     uint32_t key_flip0 = 0, key_flip1 = 0, key_swap0 = 0, key_swap1 = 0;
     // launch shape
-    std::vector<Tile> tiles;   // fast-kernel tiles first, then generic ones
-    int n_fast_tiles = 0;
+    std::vector<Tile> tiles;   // fast-kernel tiles, then generic ones, then slice blocks
+    int n_fast_tiles = 0, n_generic_tiles = 0, n_block_tiles = 0;
+    int lds_block = 0;
     int block_threads = 256;
     int tile_bytes = 0;        // target spin bytes per tile in use
     // self-tuning: candidate (tile bytes, threads) shapes timed on the first sweep launches
@@ -352,8 +359,9 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
     target_bytes = std::min<int64_t>(target_bytes, 64 * 1024);
     if (tile_bytes > 0) target_bytes = tile_bytes;
     c->tile_bytes = (int)target_bytes;
-    std::vector<Tile> fast, generic;
-    int lds_f = 0, lds_g = 0, maxP = 1;
+    const bool force_blocks = (c->opt.flags & PT_FLAG_SLICE_BLOCKS) != 0;
+    std::vector<Tile> fast, generic, block;
+    int lds_f = 0, lds_g = 0, lds_b = 0, maxP = 1;
     for (int n = 0; n < (int)P.desc.size(); ++n) {
         const InstDesc &d = P.desc[n];
         int pmax = 0;
@@ -363,6 +371,22 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
                 pmax = p;
                 break;
             }
+        const int lgMh_n = d.fast ? 31 - __builtin_clz((unsigned)d.Mh) : 0;
+        const bool blocked = d.fast && (pmax < 1 || d.ent_sh != lgMh_n || (force_blocks && d.G4 >= 2));
+        if (blocked) {
+            // slice blocks: ng four-slice groups per parity, halving until a block fits
+            int ng = force_blocks ? std::max(1, d.G4 / 4) : d.G4;
+            while (ng > 1 && ((int64_t)2 * d.N * 4 * (ng + 1) > std::max<int64_t>(target_bytes, 8 * d.N) ||
+                              block_tile_lds_bytes(d, 1, ng) > c->lds_limit))
+                ng /= 2;
+            if (block_tile_lds_bytes(d, 1, ng) > c->lds_limit)
+                return fail(PT_EINVAL, "instance " + std::to_string(n) +
+                                           ": even one slice group does not fit in LDS");
+            for (int c0 = 0; c0 < d.R; ++c0)
+                for (int g0 = 0; g0 < d.G4; g0 += ng) block.push_back(Tile{n, c0, 1, kTileBlock, g0, ng});
+            lds_b = std::max(lds_b, block_tile_lds_bytes(d, 1, ng));
+            continue;
+        }
         if (pmax < 1)
             return fail(PT_EINVAL, "instance " + std::to_string(n) +
                                        ": one replica does not fit in LDS (N*M too large)");
@@ -375,7 +399,7 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
             int q = std::min(p, d.R - c0);
             if (d.fast)
                 while (!is_pow2(q)) --q;
-            Tile t{n, c0, q, d.fast};
+            Tile t{n, c0, q, d.fast ? kTileFast : kTileGeneric, 0, d.G4};
             (d.fast ? fast : generic).push_back(t);
             const int b = sweep_tile_lds_bytes(d, P.n_adj[n], q);
             (d.fast ? lds_f : lds_g) = std::max(d.fast ? lds_f : lds_g, b);
@@ -391,15 +415,21 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
     };
     std::stable_sort(fast.begin(), fast.end(), bigger);
     std::stable_sort(generic.begin(), generic.end(), bigger);
+    if ((int64_t)(fast.size() + generic.size() + block.size()) > P.max_tiles)
+        return fail(PT_ESTATE, "internal: more tiles than reserved tile slots");
     c->tiles = fast;
     c->tiles.insert(c->tiles.end(), generic.begin(), generic.end());
+    c->tiles.insert(c->tiles.end(), block.begin(), block.end());
     c->n_fast_tiles = (int)fast.size();
+    c->n_generic_tiles = (int)generic.size();
+    c->n_block_tiles = (int)block.size();
     c->lds_fast = lds_f;
     c->lds_generic = lds_g;
+    c->lds_block = lds_b;
     c->max_P = maxP;
     HIP_TRY(hipMemcpyAsync(c->ws + P.o_tiles, c->tiles.data(), c->tiles.size() * sizeof(Tile),
                            hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(sweep_kernels_set_lds(c->lds_fast, c->lds_generic));
+    HIP_TRY(sweep_kernels_set_lds(c->lds_fast, c->lds_generic, c->lds_block));
     return PT_OK;
 }
 
@@ -479,13 +509,25 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps)
             L.tile0 = 0;
             L.n_tiles = c->n_fast_tiles;
             L.lds_bytes = c->lds_fast;
-            e = launch_sweep(L, true, c->stream);
+            e = launch_sweep(L, kTileFast, c->stream);
             if (e == hipSuccess) {
                 L.tile0 = c->n_fast_tiles;
-                L.n_tiles = (int)c->tiles.size() - c->n_fast_tiles;
+                L.n_tiles = c->n_generic_tiles;
                 L.lds_bytes = c->lds_generic;
-                e = launch_sweep(L, false, c->stream);
+                e = launch_sweep(L, kTileGeneric, c->stream);
             }
+            // slice blocks: one launch per parity phase of every sweep
+            L.tile0 = c->n_fast_tiles + c->n_generic_tiles;
+            L.n_tiles = c->n_block_tiles;
+            L.lds_bytes = c->lds_block;
+            for (int sw = 0; sw < n_sweeps && e == hipSuccess && L.n_tiles > 0; ++sw)
+                for (int ph = 0; ph < 2 && e == hipSuccess; ++ph) {
+                    L.phase = ph;
+                    L.sweep_off = sw;
+                    L.first = (sw == 0 && ph == 0);
+                    L.last = (sw == n_sweeps - 1 && ph == 1);
+                    e = launch_sweep(L, kTileBlock, c->stream);
+                }
         }
         if (e == hipSuccess) {
             if (timing) {
@@ -601,6 +643,8 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     if (opt->sweeps_per_exchange < 1) return fail(PT_EINVAL, "sweeps_per_exchange must be >= 1");
     if (opt->encoding != PT_INT8 && opt->encoding != PT_BITPACK32)
         return fail(PT_EINVAL, "unknown encoding");
+    if (opt->encoding == PT_BITPACK32)
+        return fail(PT_EINVAL, "PT_BITPACK32 is not built: only PT_INT8 is available");
     if (opt->block_threads < 0 || opt->block_threads > 1024 || (opt->block_threads % 64))
         return fail(PT_EINVAL, "block_threads must be a multiple of 64 in [64, 1024] or 0");
     if (opt->tile_replicas < 0 || opt->tile_bytes < 0)
@@ -942,7 +986,7 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->n_instances = n_inst_of(c);
     o->n_tiles = (int)c->tiles.size();
     o->block_threads = c->block_threads;
-    o->lds_bytes = std::max(c->lds_fast, c->lds_generic);
+    o->lds_bytes = std::max(c->lds_fast, std::max(c->lds_generic, c->lds_block));
     o->max_tile_replicas = c->max_P;
     o->fallbacks = c->fallbacks;
     o->encoding = c->opt.encoding;

@@ -8,11 +8,16 @@ namespace ptq {
 struct SweepLaunch {
     DevState st;
     uint32_t key0, key1;   // flip-domain Philox key
-    int32_t n_sweeps;
+    int32_t n_sweeps;      // whole-replica tiles: sweeps in this launch
     int32_t tile0;         // first tile of this launch
     int32_t n_tiles;
     int32_t block_threads;
     int32_t lds_bytes;
+    // slice-block tiles: one parity phase of sweep t + sweep_off per launch
+    int32_t phase;
+    int32_t sweep_off;
+    int32_t first;         // first launch of a pt_sweep call: clear E_cl, C
+    int32_t last;          // last launch: accumulate E_cl, C
 };
 
 // Each returns the hipError_t of the launch itself (asynchronous execution errors
@@ -20,14 +25,16 @@ struct SweepLaunch {
 hipError_t launch_init_spins(const DevState &st, int32_t n_reps, uint32_t key0, uint32_t key1,
                              hipStream_t s);
 hipError_t launch_energy(const DevState &st, int32_t rep_first, int32_t n_reps, hipStream_t s);
-hipError_t launch_sweep(const SweepLaunch &L, bool fast, hipStream_t s);
+hipError_t launch_sweep(const SweepLaunch &L, int kind, hipStream_t s);
 hipError_t launch_exchange(const DevState &st, int32_t n_inst, uint32_t key0, uint32_t key1,
                            uint32_t t_add, hipStream_t s);
 hipError_t launch_advance(const DevState &st, int32_t n_inst, uint32_t t_add, hipStream_t s);
 hipError_t launch_threshold_eval(const double *dS, uint32_t *out, int32_t n, hipStream_t s);
-hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes);
+hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes);
 
 // LDS bytes a tile of P replicas of instance d needs in its sweep kernel.
 int32_t sweep_tile_lds_bytes(const InstDesc &d, int32_t n_adj, int32_t P);
+// LDS bytes of a slice-block tile: P replicas, ng four-slice groups per parity.
+int32_t block_tile_lds_bytes(const InstDesc &d, int32_t P, int32_t ng);
 
 }  // namespace ptq

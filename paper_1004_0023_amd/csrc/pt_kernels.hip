@@ -431,6 +431,249 @@ __global__ void __launch_bounds__(1024) sweep_fast_kernel(SweepLaunch L)
     write_back(st, d, tile, t);
 }
 
+// ------------------------------------------------------------------ slice-block sweep
+//
+// A replica too large for one workgroup's LDS is split into blocks of ng four-slice
+// groups (both parities).  One launch runs one parity phase p of one sweep for every
+// block.  Parity-p attempts read only the other parity in time, which no block changes
+// during phase p, so each block needs one halo group of the other parity: the group
+// before its range in parity 1 (read in phase 0) and the group after it in parity 0
+// (read in phase 1).  LDS rows, per replica and parity plane, hold ng + 1 words:
+//   plane 0: slots 0..ng-1 = groups g0..g0+ng-1, slot ng = group g0+ng (mod G4)
+//   plane 1: slot 0 = group g0-1 (mod G4), slots 1..ng = groups g0..g0+ng-1
+
+struct BlockLds {
+    uint8_t *sp;       // P replicas x 2 planes x N rows x (ng + 1) words
+    uint32_t *ent;     // N * D entries
+    uint32_t *bias;    // N
+    uint16_t *csite;   // N
+    int32_t *coff;     // n_colors + 1
+    uint32_t *tbl;     // P tables
+    long long *red;    // reduction scratch
+};
+
+__host__ __device__ __forceinline__ int64_t block_offsets(const InstDesc &d, int P, int ng,
+                                                          int64_t o[7])
+{
+    int64_t x = 0;
+    o[0] = x; x = a16(x + (int64_t)P * 2 * d.N * (ng + 1) * 4);
+    o[1] = x; x = a16(x + (int64_t)d.N * d.D * 4);
+    o[2] = x; x = a16(x + (int64_t)d.N * 4);
+    o[3] = x; x = a16(x + (int64_t)d.N * 2);
+    o[4] = x; x = a16(x + (int64_t)(d.n_colors + 1) * 4);
+    o[5] = x; x = a16(x + (int64_t)P * d.tbl_words * 4);
+    o[6] = x; x = a16(x + 2 * 16 * 8);
+    return x;
+}
+
+// Global four-slice group held by LDS slot s of plane pl in a block starting at g0.
+__device__ __forceinline__ int block_slot_group(int pl, int s, int g0, int ng, int G4)
+{
+    const int g = (pl == 0) ? g0 + s : g0 + s - 1;
+    return (g + G4) & (G4 - 1);
+}
+
+template <int DT>
+__device__ __forceinline__ void block_item(const SweepLaunch &L, const InstDesc &d,
+                                           const BlockLds &t, int n, uint32_t tt, uint32_t c0,
+                                           int p, int i, int q, int lg, int g0, int ng)
+{
+    const int D = (DT > 0) ? DT : d.D;
+    const uint32_t RS = 4u * (uint32_t)(ng + 1);             // row stride, bytes
+    const uint32_t PL = (uint32_t)d.N * RS;                  // plane stride
+    const uint32_t qbase = (uint32_t)q * 2u * PL;
+    const uint32_t own_slot = (uint32_t)(lg + p) * 4u;       // plane 1 is shifted by one slot
+    const uint32_t nb_base = qbase + (uint32_t)p * PL + own_slot;
+    const uint32_t own = nb_base + (uint32_t)i * RS;
+    const uint32_t oth_row = qbase + (uint32_t)(p ^ 1) * PL + (uint32_t)i * RS;
+    const uint32_t X = lds32(t.sp, own);
+    uint32_t T;
+    if (p == 0) {
+        const uint32_t Wc = lds32(t.sp, oth_row + 4u * (uint32_t)(lg + 1));
+        const uint32_t Wp = lds32(t.sp, oth_row + 4u * (uint32_t)lg);
+        T = __builtin_amdgcn_alignbyte(Wc, Wp, 3) + Wc;
+    } else {
+        const uint32_t Wc = lds32(t.sp, oth_row + 4u * (uint32_t)lg);
+        const uint32_t Wn = lds32(t.sp, oth_row + 4u * (uint32_t)(lg + 1));
+        T = __builtin_amdgcn_alignbyte(Wn, Wc, 1) + Wc;
+    }
+    // the entry holds j << ent_sh; a block row is RS bytes
+    const int esh = d.ent_sh;
+    const uint32_t *er = t.ent + i * D;
+    uint32_t acc = 0;
+    if (DT > 0) {
+        uint32_t ents[DT > 0 ? DT : 1], ws[DT > 0 ? DT : 1];
+#pragma unroll
+        for (int e = 0; e < DT; ++e) ents[e] = er[e];
+#pragma unroll
+        for (int e = 0; e < DT; ++e) ws[e] = lds32(t.sp, nb_base + ((ents[e] >> 16) >> esh) * RS);
+#pragma unroll
+        for (int e = 0; e < DT; ++e) acc += __builtin_amdgcn_perm(0u, ents[e], ws[e]);
+    } else {
+        for (int e = 0; e < D; ++e) {
+            const uint32_t ent = er[e];
+            acc += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, nb_base + ((ent >> 16) >> esh) * RS));
+        }
+    }
+    const Words4 u = philox10(spin_ctr0(i, p, d.G4, g0 + lg), tt, c0 + (uint32_t)q, (uint32_t)n,
+                              L.key0, L.key1);
+    const uint32_t sel_x = (uint32_t)(2 * d.F + 1) << 8;
+    const uint32_t V = __builtin_amdgcn_perm(0u, sel_x, X) + (acc << 1) + t.bias[i];
+    const uint32_t IDX = V + (V << 1) + T;
+    const uint32_t *tb = t.tbl + q * d.tbl_words;
+    uint32_t flip = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t thr = tb[(IDX >> (8 * b)) & 0xFFu];
+        flip |= (u.w[b] <= thr ? 1u : 0u) << (8 * b);
+    }
+    *reinterpret_cast<uint32_t *>(t.sp + own) = X ^ flip;
+}
+
+template <int DT>
+__device__ __forceinline__ void block_phase(const SweepLaunch &L, const InstDesc &d,
+                                            const Tile &tile, const BlockLds &t, uint32_t tt)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lgng = ilog2(tile.ng);
+    const int lgL = ilog2(tile.P) + lgng;
+    const int Lmask = (1 << lgL) - 1;
+    const int p = L.phase;
+    for (int g = 0; g < d.n_colors; ++g) {
+        const int s0 = t.coff[g];
+        const int items = (t.coff[g + 1] - s0) << lgL;
+        for (int it = tid; it < items; it += nt) {
+            const int r = it & Lmask;
+            block_item<DT>(L, d, t, tile.inst, tt, (uint32_t)tile.c0, p, t.csite[s0 + (it >> lgL)],
+                           r >> lgng, r & (tile.ng - 1), tile.g0, tile.ng);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
+{
+    extern __shared__ __align__(16) char lds[];
+    const DevState &st = L.st;
+    const Tile tile = st.tiles[L.tile0 + blockIdx.x];
+    const int n = tile.inst;
+    const InstDesc d = st.inst[n];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int P = tile.P, ng = tile.ng, g0 = tile.g0, G4 = d.G4, N = d.N;
+    int64_t o[7];
+    block_offsets(d, P, ng, o);
+    BlockLds t;
+    t.sp = reinterpret_cast<uint8_t *>(lds + o[0]);
+    t.ent = reinterpret_cast<uint32_t *>(lds + o[1]);
+    t.bias = reinterpret_cast<uint32_t *>(lds + o[2]);
+    t.csite = reinterpret_cast<uint16_t *>(lds + o[3]);
+    t.coff = reinterpret_cast<int32_t *>(lds + o[4]);
+    t.tbl = reinterpret_cast<uint32_t *>(lds + o[5]);
+    t.red = reinterpret_cast<long long *>(lds + o[6]);
+
+    // stage: both planes of the block (+ halos), rows, biases, colour lists, rung tables
+    const int slots = ng + 1;
+    const int words = P * 2 * N * slots;
+    for (int w = tid; w < words; w += nt) {
+        const int s = w % slots;
+        const int rowi = w / slots;  // (q, pl, i)
+        const int i = rowi % N;
+        const int qp = rowi / N;
+        const int pl = qp & 1;
+        const int q = qp >> 1;
+        const int grp = block_slot_group(pl, s, g0, ng, G4);
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(
+            st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
+            (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh + 4 * grp);
+        reinterpret_cast<uint32_t *>(t.sp)[w] = *src;
+    }
+    for (int e = tid; e < N * d.D; e += nt) t.ent[e] = st.ent[d.ent_base + e];
+    for (int i = tid; i < N; i += nt) t.bias[i] = st.bias[d.site_base + i];
+    for (int i = tid; i < N; i += nt) t.csite[i] = st.csite[d.site_base + i];
+    for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
+    for (int q = 0; q < P; ++q) {
+        const int rung = st.rung_of[d.rep_base + tile.c0 + q];
+        const uint32_t *tsrc = st.tbl + d.tbl_base + (int64_t)rung * d.tbl_words;
+        for (int w = tid; w < d.tbl_words; w += nt) t.tbl[q * d.tbl_words + w] = tsrc[w];
+    }
+    if (L.first && g0 == 0)
+        for (int q = tid; q < P; q += nt) {
+            st.E[d.rep_base + tile.c0 + q] = 0;
+            st.C[d.rep_base + tile.c0 + q] = 0;
+        }
+    const uint32_t tt = (uint32_t)(st.ctr[n].t + (uint64_t)L.sweep_off);
+    __syncthreads();
+
+    switch (d.D) {
+    case 1: block_phase<1>(L, d, tile, t, tt); break;
+    case 2: block_phase<2>(L, d, tile, t, tt); break;
+    case 3: block_phase<3>(L, d, tile, t, tt); break;
+    case 4: block_phase<4>(L, d, tile, t, tt); break;
+    case 5: block_phase<5>(L, d, tile, t, tt); break;
+    case 6: block_phase<6>(L, d, tile, t, tt); break;
+    case 7: block_phase<7>(L, d, tile, t, tt); break;
+    case 8: block_phase<8>(L, d, tile, t, tt); break;
+    default: block_phase<0>(L, d, tile, t, tt); break;
+    }
+
+    // partial E_cl and C of the block's slices after the last phase of the call
+    if (L.last) {
+        const int D = d.D, F = d.F;
+        const uint32_t RS = 4u * (uint32_t)slots, PL = (uint32_t)N * RS;
+        for (int q = 0; q < P; ++q) {
+            long long ee = 0, cc = 0;
+            const uint32_t qbase = (uint32_t)q * 2u * PL;
+            for (int it = tid; it < N * ng; it += nt) {
+                const int i = it / ng;
+                const int lg = it - i * ng;
+                const uint32_t X0 = lds32(t.sp, qbase + (uint32_t)i * RS + 4u * lg);
+                const uint32_t X1 = lds32(t.sp, qbase + PL + (uint32_t)i * RS + 4u * (lg + 1));
+                const uint32_t X0n = lds32(t.sp, qbase + (uint32_t)i * RS + 4u * (lg + 1));
+                const uint32_t dis_t = popc(X0 ^ X1) + popc(X1 ^ __builtin_amdgcn_alignbyte(X0n, X0, 1));
+                cc += 8 - 2 * (long long)dis_t;
+                const int hval = (int)(t.bias[i] & 0xFFu) - F;
+                int sumJ = 0;
+                long long eterm = 0;
+                for (int e = 0; e < D; ++e) {
+                    const uint32_t ent = t.ent[i * D + e];
+                    const int w0 = (int)(ent & 0xFFu), w1 = (int)((ent >> 8) & 0xFFu);
+                    const int J = w1 - w0;
+                    sumJ += w0 + w1;
+                    const uint32_t j = (ent >> 16) >> d.ent_sh;
+                    if (J != 0 && j > (uint32_t)i) {
+                        const uint32_t Y0 = lds32(t.sp, qbase + j * RS + 4u * lg);
+                        const uint32_t Y1 = lds32(t.sp, qbase + PL + j * RS + 4u * (lg + 1));
+                        eterm += (long long)J * (8 - 2 * (long long)(popc(X0 ^ Y0) + popc(X1 ^ Y1)));
+                    }
+                }
+                eterm += (long long)(hval + sumJ) * (2 * (long long)(popc(X0) + popc(X1)) - 8);
+                ee += eterm;
+            }
+            ee = block_sum(ee, t.red);
+            cc = block_sum(cc, t.red);
+            if (tid == 0) {
+                atomicAdd(reinterpret_cast<unsigned long long *>(&st.E[d.rep_base + tile.c0 + q]),
+                          (unsigned long long)ee);
+                atomicAdd(reinterpret_cast<unsigned long long *>(&st.C[d.rep_base + tile.c0 + q]),
+                          (unsigned long long)cc);
+            }
+        }
+    }
+
+    // write back the phase's own groups
+    const int p = L.phase;
+    for (int w = tid; w < P * N * ng; w += nt) {
+        const int lg = w % ng;
+        const int qi = w / ng;
+        const int i = qi % N;
+        const int q = qi / N;
+        const uint32_t v = lds32(t.sp, (uint32_t)q * 2u * N * 4u * slots + (uint32_t)p * N * 4u * slots +
+                                           (uint32_t)i * 4u * slots + 4u * (uint32_t)(lg + p));
+        *reinterpret_cast<uint32_t *>(st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
+                                      (int64_t)p * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + lg)) = v;
+    }
+}
+
 // ------------------------------------------------------------------ generic sweep
 
 __device__ __forceinline__ int lds_x(const uint8_t *rep, const InstDesc &d, int k, int i)
@@ -607,9 +850,20 @@ int32_t sweep_tile_lds_bytes(const InstDesc &d, int32_t n_adj, int32_t P)
     return (int32_t)(x > 0x7fffffff ? 0x7fffffff : x);
 }
 
-hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes)
+int32_t block_tile_lds_bytes(const InstDesc &d, int32_t P, int32_t ng)
+{
+    int64_t o[7];
+    const int64_t x = block_offsets(d, P, ng, o);
+    return (int32_t)(x > 0x7fffffff ? 0x7fffffff : x);
+}
+
+hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes)
 {
     hipError_t e = hipSuccess;
+    if (block_bytes > 0)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_block_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, block_bytes);
+    if (e != hipSuccess) return e;
     if (fast_bytes > 0)
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_fast_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, fast_bytes);
@@ -634,11 +888,13 @@ hipError_t launch_energy(const DevState &st, int32_t rep_first, int32_t n_reps, 
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SweepLaunch &L, bool fast, hipStream_t s)
+hipError_t launch_sweep(const SweepLaunch &L, int kind, hipStream_t s)
 {
     if (L.n_tiles <= 0) return hipSuccess;
-    if (fast)
+    if (kind == kTileFast)
         hipLaunchKernelGGL(sweep_fast_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
+    else if (kind == kTileBlock)
+        hipLaunchKernelGGL(sweep_block_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
     else
         hipLaunchKernelGGL(sweep_generic_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
     return hipGetLastError();

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libptqmc.so")
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ELAUNCH, PT_ESTATE = 0, -1, -2, -3, -4, -5
 PT_INT8, PT_BITPACK32 = 0, 1
 PT_FLAG_TIMING, PT_FLAG_NO_GRAPH, PT_FLAG_INJECT_LAUNCH_OOR_ONCE = 0x1, 0x2, 0x4
+PT_FLAG_SLICE_BLOCKS = 0x8
 LABEL_NONE, LABEL_UP, LABEL_DOWN = 0, 1, 2
 
 EXPORTS = ["pt_workspace_bytes", "pt_init", "pt_sweep", "pt_exchange", "pt_run", "pt_sync",

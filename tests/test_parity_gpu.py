@@ -248,3 +248,45 @@ def test_config3_full_batch_sampled(ptqmc):
             assert sorted(obs["replica_of"]) == list(range(insts[n].R))
             assert np.array_equal(obs["rung_of"][obs["replica_of"]], np.arange(insts[n].R))
             assert obs["t"] == k * cycles and obs["e"] == cycles
+
+
+@pytest.mark.parametrize("tile_bytes,block_threads", [(0, 256), (4096, 1024)])
+def test_slice_blocks_match_oracle(ptqmc, tile_bytes, block_threads):
+    """Replicas forced into slice blocks (one launch per parity phase, halo groups, energy
+    partial sums) reproduce the oracle's trajectory."""
+    insts = fast_batch() + [W.config1()]
+    seed = 0xB10C
+    k, cycles = 3, 12
+    say(f"case: slice blocks, tile_bytes={tile_bytes} block_threads={block_threads}")
+    refs = oracle_batch(insts, seed, k, cycles)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_bytes=tile_bytes,
+                       block_threads=block_threads, flags=ptqmc.PT_FLAG_SLICE_BLOCKS) as s:
+        s.run(cycles)
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], "blocks")
+
+
+def test_config2_slice_blocks(ptqmc):
+    inst = W.config2()
+    seed = W.sampler_seed(2)
+    say("case: config 2 in slice blocks, 6 cycles of 10 sweeps")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, tile_bytes=8192,
+                       block_threads=512, flags=ptqmc.PT_FLAG_SLICE_BLOCKS) as s:
+        s.run(6)
+        ref = oracle.OracleChain(inst, seed)
+        ref.run(10, 6)
+        assert_same(s, 0, ref, "config2 blocks")
+
+
+def test_config4_lattice_one_cycle(ptqmc):
+    """The 8x8x16 lattice (N=1024, M=256, R=64): a replica (256 KiB) exceeds one
+    workgroup's LDS, so it always runs in slice blocks.  One full cycle (10 sweeps and an
+    exchange) against the oracle."""
+    inst = W.config4()
+    seed = W.sampler_seed(4)
+    say("case: config 4, 1 cycle of 10 sweeps")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10) as s:
+        s.run(1)
+        ref = oracle.OracleChain(inst, seed)
+        ref.run(10, 1)
+        assert_same(s, 0, ref, "config4")
