@@ -35,7 +35,8 @@
  *                  Philox(ctr = (r, e, 0, n), key = (lo(seed), hi(seed) ^ 0x53574150)).
  *                  Then: the replica at rung 0 labelled DOWN completes a round trip and
  *                  becomes UP (NONE becomes UP); the replica at rung R-1 labelled UP becomes
- *                  DOWN; per rung, E_cl, C and their squares are accumulated.
+ *                  DOWN; per rung, E_cl, C and their squares are accumulated, and the
+ *                  label of the replica there is counted (UP / DOWN).
  *   init         : s = +1 iff the top bit of word (m mod 4) of
  *                  Philox(ctr = ((2i + p)*G + m/4, 0, c, n), key = (lo, hi ^ 0x494E4954)).
  * Vertex labels and colours are used as given (any proper colouring).
@@ -128,6 +129,9 @@ typedef struct {
     uint64_t *roundtrips;     /* by slot                                              */
     int8_t *label;            /* by slot                                              */
     int64_t *sumE, *sumC, *sumE2, *sumC2; /* by rung, accumulated at every exchange   */
+    uint64_t *nup, *ndown;    /* by rung: exchange steps at which the replica there was
+                                 labelled UP / DOWN (feedback-optimised ladders use
+                                 f(r) = nup / (nup + ndown))                          */
     uint64_t t, e, n_acc;     /* sweeps done, exchange steps done, accumulated samples */
 } pt_obs;
 
@@ -200,6 +204,36 @@ uint32_t pt_threshold(double dS);
 /* The same rule evaluated by the device code that decides swaps, for n values: dS and
  * out are device pointers; runs on stream (NULL: default stream) and synchronises. */
 int pt_threshold_device(const double *dS, uint32_t *out, int32_t n, void *stream);
+
+/* ---------------------------------------------------------------- ladder network
+ * The ladder is data (b_r, K_r) for the sampler; choosing it is outside the Markov chain
+ * (the paper defers ladder selection to its reference [7], Section 2).  The library
+ * carries the FP32 kernels of a small network that proposes ladders from instance
+ * features: 32 -> 128 -> 128 -> 64 with ReLU after the hidden layers; its 64 outputs are
+ * per-rung values (how the caller turns them into (b_r, K_r) is the caller's choice).
+ * Parameters are pt_mlp_param_count() floats: W1[128][32], b1[128], W2[128][128],
+ * b2[128], W3[64][128], b3[64].  All pointers are device pointers; work runs on stream
+ * (NULL: default stream) asynchronously; workspace holds pt_mlp_workspace_bytes(batch)
+ * bytes.  The dense products run on the matrix cores (v_mfma_f32_16x16x4f32). */
+#define PT_MLP_LOSS_SOFTMAX 0 /* -sum_j q_j log softmax(z)_j, rows of q sum to 1        */
+#define PT_MLP_LOSS_SIGMOID 1 /* per-output logistic cross entropy, q in [0, 1]          */
+int32_t pt_mlp_param_count(void);
+size_t pt_mlp_workspace_bytes(int32_t batch);
+
+/* logits[batch][64] for features x[batch][32]. */
+int pt_mlp_forward(const float *params, const float *x, float *logits, int32_t batch,
+                   void *workspace, void *stream);
+
+/* Loss loss_kind (PT_MLP_LOSS_*) against targets target[batch][64]: writes grads
+ * (pt_mlp_param_count() floats) of the batch mean, and loss[0] = the batch sum of the
+ * per-sample losses. */
+int pt_mlp_loss_grad(const float *params, const float *x, const float *target, int32_t batch,
+                     int32_t loss_kind, float *grads, float *loss, void *workspace,
+                     void *stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected, step >= 1) over n parameters. */
+int pt_mlp_adam(float *params, const float *grads, float *m, float *v, int32_t n, float lr,
+                float beta1, float beta2, float eps, int32_t step, void *stream);
 
 #ifdef __cplusplus
 }

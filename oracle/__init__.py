@@ -45,7 +45,7 @@ class _Inst(C.Structure):
 class _State(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("s", "rung_of", "replica_of", "E", "C", "label", "rt",
                                           "acc", "att", "sumE", "sumC", "sumE2", "sumC2",
-                                          "counters")]
+                                          "nup", "ndown", "counters")]
 
 
 _lib = None
@@ -121,7 +121,7 @@ class OracleChain:
     permutation, counters, labels, swap statistics and per-rung accumulators."""
 
     ARRAYS = ("s", "rung_of", "replica_of", "E", "C", "label", "rt", "acc", "att",
-              "sumE", "sumC", "sumE2", "sumC2", "counters")
+              "sumE", "sumC", "sumE2", "sumC2", "nup", "ndown", "counters")
 
     def __init__(self, inst, seed: int, index: int = 0, init: bool = True):
         self.inst = inst
@@ -153,6 +153,8 @@ class OracleChain:
         self.sumC = np.zeros(R, dtype=np.int64)
         self.sumE2 = np.zeros(R, dtype=np.int64)
         self.sumC2 = np.zeros(R, dtype=np.int64)
+        self.nup = np.zeros(R, dtype=np.uint64)
+        self.ndown = np.zeros(R, dtype=np.uint64)
         self.counters = np.zeros(3, dtype=np.uint64)
         self._bind()
         if init:
@@ -212,8 +214,8 @@ class OracleChain:
                     replica_of=self.replica_of.copy(), acc=self.acc[:R - 1].copy(),
                     att=self.att[:R - 1].copy(), roundtrips=self.rt.copy(),
                     label=self.label.copy(), sumE=self.sumE.copy(), sumC=self.sumC.copy(),
-                    sumE2=self.sumE2.copy(), sumC2=self.sumC2.copy(), t=self.t, e=self.e,
-                    n_acc=self.n_acc)
+                    sumE2=self.sumE2.copy(), sumC2=self.sumC2.copy(), nup=self.nup.copy(),
+                    ndown=self.ndown.copy(), t=self.t, e=self.e, n_acc=self.n_acc)
 
 
 def energy_estimators(obs, inst):

@@ -66,6 +66,8 @@ typedef struct {
     uint64_t *acc;       /* [R-1] accepted swaps of pair (r, r+1) */
     uint64_t *att;       /* [R-1] attempted swaps of pair (r, r+1) */
     int64_t *sumE, *sumC, *sumE2, *sumC2; /* [R] by rung */
+    uint64_t *nup, *ndown; /* [R] by rung: exchange steps at which the replica there was
+                              labelled UP / DOWN */
     uint64_t *counters;  /* [0] sweeps t, [1] exchange steps e, [2] n_acc */
 } or_state;
 
@@ -291,6 +293,7 @@ void or_init(const or_instance *in, or_state *st, uint64_t seed)
         st->label[r] = (r == 0) ? OR_LABEL_UP : OR_LABEL_NONE;
         st->rt[r] = 0;
         st->sumE[r] = st->sumC[r] = st->sumE2[r] = st->sumC2[r] = 0;
+        st->nup[r] = st->ndown[r] = 0;
     }
     for (int32_t r = 0; r + 1 < R; ++r) st->acc[r] = st->att[r] = 0;
     st->counters[0] = st->counters[1] = st->counters[2] = 0;
@@ -416,9 +419,11 @@ void or_exchange(const or_instance *in, or_state *st, uint64_t seed)
         st->label[cold] = OR_LABEL_UP;
     }
     if (st->label[hot] == OR_LABEL_UP) st->label[hot] = OR_LABEL_DOWN;
-    /* per-rung accumulators */
+    /* per-rung accumulators, including the label of the replica found at each rung */
     for (int32_t r = 0; r < R; ++r) {
         int32_t c = st->replica_of[r];
+        if (st->label[c] == OR_LABEL_UP) st->nup[r] += 1;
+        if (st->label[c] == OR_LABEL_DOWN) st->ndown[r] += 1;
         st->sumE[r] += st->E[c];
         st->sumC[r] += st->C[c];
         st->sumE2[r] += st->E[c] * st->E[c];

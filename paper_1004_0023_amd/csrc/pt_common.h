@@ -177,6 +177,7 @@ struct DevState {
     uint64_t *rt;
     int32_t *replica_of;  // per rung
     int64_t *sumE, *sumC, *sumE2, *sumC2;
+    uint64_t *nup, *ndown;  // per rung: exchange steps with an UP / DOWN replica there
     uint64_t *acc, *att;  // per pair
     Counters *ctr;        // per instance
 };

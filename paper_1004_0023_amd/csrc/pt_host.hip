@@ -45,7 +45,7 @@ int hip_fail(hipError_t e, const char *what)
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr uint32_t kMagic = 0x51505450u;  // checkpoint tag
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 constexpr int kMaxField = 1023;
 
 // Host copy of everything that is uploaded once, plus the layout of the workspace.
@@ -65,7 +65,7 @@ struct Plan {
         o_repinst;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
-        o_sumC2, o_acc, o_att, o_ctr;
+        o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr;
     size_t state_bytes, total_bytes;
 };
 
@@ -283,6 +283,8 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
     P.o_sumC = take((size_t)rep * 8);
     P.o_sumE2 = take((size_t)rep * 8);
     P.o_sumC2 = take((size_t)rep * 8);
+    P.o_nup = take((size_t)rep * 8);
+    P.o_ndown = take((size_t)rep * 8);
     P.o_acc = take((size_t)pair * 8);
     P.o_att = take((size_t)pair * 8);
     P.o_ctr = take((size_t)n_inst * sizeof(Counters));
@@ -719,6 +721,8 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.sumC = (int64_t *)(w + P.o_sumC);
     st.sumE2 = (int64_t *)(w + P.o_sumE2);
     st.sumC2 = (int64_t *)(w + P.o_sumC2);
+    st.nup = (uint64_t *)(w + P.o_nup);
+    st.ndown = (uint64_t *)(w + P.o_ndown);
     st.acc = (uint64_t *)(w + P.o_acc);
     st.att = (uint64_t *)(w + P.o_att);
     st.ctr = (Counters *)(w + P.o_ctr);
@@ -878,6 +882,8 @@ int pt_observables(pt_ctx *c, int32_t inst, pt_obs *o)
     if ((rc = get(o->sumC, P.o_sumC + (size_t)b * 8, (size_t)R * 8))) return rc;
     if ((rc = get(o->sumE2, P.o_sumE2 + (size_t)b * 8, (size_t)R * 8))) return rc;
     if ((rc = get(o->sumC2, P.o_sumC2 + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(o->nup, P.o_nup + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(o->ndown, P.o_ndown + (size_t)b * 8, (size_t)R * 8))) return rc;
     if ((rc = get(&ctr, P.o_ctr + (size_t)inst * sizeof(Counters), sizeof(Counters)))) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (o->label)

@@ -811,8 +811,12 @@ __global__ void exchange_kernel(DevState st, uint32_t key0, uint32_t key1, uint3
         }
         if (st.label[base + hot] == 1) st.label[base + hot] = 2;
     }
+    __syncthreads();  // labels are final
     for (int r = threadIdx.x; r < R; r += blockDim.x) {
         const int c = st.replica_of[base + r];
+        const int lab = st.label[base + c];
+        if (lab == 1) st.nup[base + r] += 1;
+        if (lab == 2) st.ndown[base + r] += 1;
         const long long E = st.E[base + c];
         const long long C = st.C[base + c];
         st.sumE[base + r] += E;

@@ -21,11 +21,13 @@ PT_INT8, PT_BITPACK32 = 0, 1
 PT_FLAG_TIMING, PT_FLAG_NO_GRAPH, PT_FLAG_INJECT_LAUNCH_OOR_ONCE = 0x1, 0x2, 0x4
 PT_FLAG_SLICE_BLOCKS = 0x8
 LABEL_NONE, LABEL_UP, LABEL_DOWN = 0, 1, 2
+MLP_LOSS_SOFTMAX, MLP_LOSS_SIGMOID = 0, 1
 
 EXPORTS = ["pt_workspace_bytes", "pt_init", "pt_sweep", "pt_exchange", "pt_run", "pt_sync",
            "pt_observables", "pt_get_spins", "pt_set_spins", "pt_save", "pt_load",
            "pt_get_info", "pt_timing_reset", "pt_free", "pt_strerror", "pt_last_error",
-           "pt_threshold", "pt_threshold_device"]
+           "pt_threshold", "pt_threshold_device", "pt_mlp_param_count",
+           "pt_mlp_workspace_bytes", "pt_mlp_forward", "pt_mlp_loss_grad", "pt_mlp_adam"]
 
 
 class PTError(RuntimeError):
@@ -52,6 +54,7 @@ class _Obs(C.Structure):
                 ("replica_of", C.c_void_p), ("acc", C.c_void_p), ("att", C.c_void_p),
                 ("roundtrips", C.c_void_p), ("label", C.c_void_p), ("sumE", C.c_void_p),
                 ("sumC", C.c_void_p), ("sumE2", C.c_void_p), ("sumC2", C.c_void_p),
+                ("nup", C.c_void_p), ("ndown", C.c_void_p),
                 ("t", C.c_uint64), ("e", C.c_uint64), ("n_acc", C.c_uint64)]
 
 
@@ -103,8 +106,16 @@ def lib():
         L.pt_threshold.argtypes = [C.c_double]
         L.pt_threshold.restype = C.c_uint32
         L.pt_threshold_device.argtypes = [vp, vp, i32, vp]
+        L.pt_mlp_param_count.argtypes = []
+        L.pt_mlp_workspace_bytes.argtypes = [i32]
+        L.pt_mlp_workspace_bytes.restype = C.c_size_t
+        L.pt_mlp_forward.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.pt_mlp_loss_grad.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
+        L.pt_mlp_adam.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float,
+                                  C.c_float, i32, vp]
         for name in EXPORTS:
-            if name not in ("pt_free", "pt_strerror", "pt_last_error", "pt_threshold"):
+            if name not in ("pt_free", "pt_strerror", "pt_last_error", "pt_threshold",
+                            "pt_mlp_workspace_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -226,10 +237,11 @@ class Sampler:
                  acc=np.zeros(R - 1, np.uint64), att=np.zeros(R - 1, np.uint64),
                  roundtrips=np.zeros(R, np.uint64), label=np.zeros(R, np.int8),
                  sumE=np.zeros(R, np.int64), sumC=np.zeros(R, np.int64),
-                 sumE2=np.zeros(R, np.int64), sumC2=np.zeros(R, np.int64))
+                 sumE2=np.zeros(R, np.int64), sumC2=np.zeros(R, np.int64),
+                 nup=np.zeros(R, np.uint64), ndown=np.zeros(R, np.uint64))
         rec = _Obs(*[o[k].ctypes.data for k in ("E_cl", "C", "rung_of", "replica_of", "acc",
                                                  "att", "roundtrips", "label", "sumE", "sumC",
-                                                 "sumE2", "sumC2")], 0, 0, 0)
+                                                 "sumE2", "sumC2", "nup", "ndown")], 0, 0, 0)
         _check(lib().pt_observables(self._ctx, int(n), C.byref(rec)))
         o["t"], o["e"], o["n_acc"] = int(rec.t), int(rec.e), int(rec.n_acc)
         return o
@@ -263,3 +275,78 @@ class Sampler:
 
     def timing_reset(self):
         _check(lib().pt_timing_reset(self._ctx))
+
+
+class LadderNet:
+    """Device-side parameters and Adam state of the ladder network, driven through the
+    library's FP32 kernels (forward, soft-target cross-entropy gradient, Adam)."""
+
+    N_IN, N_OUT = 32, 64
+
+    def __init__(self, params: Optional[np.ndarray] = None, seed: int = 0):
+        self.n = int(lib().pt_mlp_param_count())
+        if params is None:
+            params = init_ladder_params(seed)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.n:
+            raise ValueError(f"expected {self.n} parameters, got {p.size}")
+        self.params = torch.from_numpy(p.copy()).cuda()
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self._ws = {}
+
+    def _workspace(self, batch: int):
+        if batch not in self._ws:
+            nb = int(lib().pt_mlp_workspace_bytes(batch))
+            self._ws[batch] = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        return self._ws[batch]
+
+    def forward(self, x) -> torch.Tensor:
+        x = torch.as_tensor(x, dtype=torch.float32).cuda().contiguous()
+        B = x.shape[0]
+        out = torch.empty((B, self.N_OUT), dtype=torch.float32, device="cuda")
+        rc = lib().pt_mlp_forward(self.params.data_ptr(), x.data_ptr(), out.data_ptr(), B,
+                                  self._workspace(B).data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream)
+        _check(rc)
+        return out
+
+    def loss_grad(self, x, q, kind: int = MLP_LOSS_SIGMOID) -> float:
+        x = torch.as_tensor(x, dtype=torch.float32).cuda().contiguous()
+        q = torch.as_tensor(q, dtype=torch.float32).cuda().contiguous()
+        B = x.shape[0]
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        rc = lib().pt_mlp_loss_grad(self.params.data_ptr(), x.data_ptr(), q.data_ptr(), B,
+                                    int(kind), self.grads.data_ptr(), loss.data_ptr(),
+                                    self._workspace(B).data_ptr(),
+                                    torch.cuda.current_stream().cuda_stream)
+        _check(rc)
+        return float(loss.item()) / B
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.step += 1
+        rc = lib().pt_mlp_adam(self.params.data_ptr(), self.grads.data_ptr(), self.m.data_ptr(),
+                               self.v.data_ptr(), self.n, lr, beta1, beta2, eps, self.step,
+                               torch.cuda.current_stream().cuda_stream)
+        _check(rc)
+
+    def numpy_params(self) -> np.ndarray:
+        return self.params.cpu().numpy().copy()
+
+
+def init_ladder_params(seed: int = 0, out_bias: float = 0.0) -> np.ndarray:
+    """He-uniform hidden weights, zero hidden biases, a zero output layer and output
+    biases out_bias."""
+    rng = np.random.default_rng(seed)
+    sizes = [(128, 32), (128,), (128, 128), (128,), (64, 128), (64,)]
+    out = []
+    for k, shp in enumerate(sizes):
+        if len(shp) == 2 and k < 4:
+            lim = np.sqrt(6.0 / shp[1])
+            out.append(rng.uniform(-lim, lim, size=shp).astype(np.float32).ravel())
+        else:
+            fill = out_bias if k == 5 else 0.0
+            out.append(np.full(int(np.prod(shp)), fill, np.float32))
+    return np.concatenate(out)

@@ -303,7 +303,9 @@ def reference_exchange(inst, seed, index, E, C, replica_of, label, rt, e):
         label[cold] = oracle.LABEL_UP
     if label[hot] == oracle.LABEL_UP:
         label[hot] = oracle.LABEL_DOWN
-    return replica_of, label, rt, acc, att
+    nup = np.array([label[replica_of[r]] == oracle.LABEL_UP for r in range(R)], np.uint64)
+    ndown = np.array([label[replica_of[r]] == oracle.LABEL_DOWN for r in range(R)], np.uint64)
+    return replica_of, label, rt, acc, att, nup, ndown
 
 
 def test_exchange_matches_reference_step():
@@ -313,6 +315,8 @@ def test_exchange_matches_reference_step():
     o = oracle.OracleChain(inst, seed, index=1)
     acc_tot = np.zeros(6, np.uint64)
     att_tot = np.zeros(6, np.uint64)
+    up_tot = np.zeros(7, np.uint64)
+    down_tot = np.zeros(7, np.uint64)
     for step in range(40):
         o.sweep(1)
         E = o.E.copy(); Cc = o.C.copy()
@@ -323,7 +327,9 @@ def test_exchange_matches_reference_step():
         assert np.array_equal(o.label, want[1])
         assert np.array_equal(o.rt, want[2])
         acc_tot += want[3]; att_tot += want[4]
+        up_tot += want[5]; down_tot += want[6]
         assert np.array_equal(o.acc, acc_tot) and np.array_equal(o.att, att_tot)
+        assert np.array_equal(o.nup, up_tot) and np.array_equal(o.ndown, down_tot)
         assert np.array_equal(o.rung_of[o.replica_of], np.arange(7))
         assert np.array_equal(o.sumE - sums_before, E[o.replica_of])
     assert o.e == 40 and o.n_acc == 40

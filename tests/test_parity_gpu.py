@@ -16,7 +16,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 KEYS = ("E_cl", "C", "rung_of", "replica_of", "acc", "att", "roundtrips", "label", "sumE",
-        "sumC", "sumE2", "sumC2")
+        "sumC", "sumE2", "sumC2", "nup", "ndown")
 
 
 def say(msg):
