@@ -279,7 +279,7 @@ class Sampler:
 
 class LadderNet:
     """Device-side parameters and Adam state of the ladder network, driven through the
-    library's FP32 kernels (forward, soft-target cross-entropy gradient, Adam)."""
+    library's FP32 kernels (forward, cross-entropy gradients, Adam)."""
 
     N_IN, N_OUT = 32, 64
 
