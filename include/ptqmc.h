@@ -82,6 +82,8 @@ extern "C" {
 #define PT_FLAG_SLICE_BLOCKS 0x8u  /* split every replica that could use them into slice
                                       blocks (one launch per parity phase), as replicas
                                       too large for one workgroup's LDS always are      */
+#define PT_FLAG_FOUR_SLICE_LANES 0x10u /* fast path: one four-slice word per lane instead
+                                          of two (same chain; a measurement and test hook) */
 
 typedef struct pt_ctx pt_ctx;
 
@@ -145,6 +147,8 @@ typedef struct {
     int64_t sweep_launches;           /* number of timed sweep launches              */
     double exchange_ms;
     int64_t exchange_launches;
+    int32_t sweep_groups;             /* launches of whole-replica tiles per sweep call:
+                                         one per occupancy class of the tiles          */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

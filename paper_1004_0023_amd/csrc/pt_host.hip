@@ -327,8 +327,11 @@ struct pt_ctx {
     hipEvent_t tune_ev[2] = {nullptr, nullptr};
     int lds_fast = 0, lds_generic = 0;
     int max_P = 1;
-    int lds_limit = 65536;
+    int lds_limit = 65536;     // LDS one workgroup may use
+    int cu_lds = 65536;        // LDS of one compute unit
+    int cu_threads = 2048;     // resident threads of one compute unit
     int cus = 256;
+    std::vector<int> tile_lds; // LDS bytes of every whole-replica tile (block tiles: 0)
     int fallbacks = 0;
     bool inject_pending = false;
     // graph of whole cycles for pt_run
@@ -409,9 +412,14 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
             c0 += q;
         }
     }
-    // largest tiles first: the device dispatches workgroups roughly in order, so the
-    // longest work starts earliest (the paper's "hardest chains first" work pool)
+    // Tiles in order of decreasing LDS need, ties by decreasing work.  Launches then split
+    // the list into occupancy classes (see launch_groups) and each class starts with its
+    // largest tiles: the device dispatches workgroups roughly in order, so the longest work
+    // starts earliest (the paper's "hardest chains first" work pool, Section 4).
+    auto lds_of = [&](const Tile &t) { return sweep_tile_lds_bytes(P.desc[t.inst], P.n_adj[t.inst], t.P); };
     auto bigger = [&](const Tile &a, const Tile &b) {
+        const int la = lds_of(a), lb = lds_of(b);
+        if (la != lb) return la > lb;
         const InstDesc &da = P.desc[a.inst], &db = P.desc[b.inst];
         return (int64_t)a.P * da.M * da.N > (int64_t)b.P * db.M * db.N;
     };
@@ -424,6 +432,8 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
     c->tiles.insert(c->tiles.end(), block.begin(), block.end());
     c->n_fast_tiles = (int)fast.size();
     c->n_generic_tiles = (int)generic.size();
+    c->tile_lds.assign(c->tiles.size(), 0);
+    for (size_t k = 0; k < fast.size() + generic.size(); ++k) c->tile_lds[k] = lds_of(c->tiles[k]);
     c->n_block_tiles = (int)block.size();
     c->lds_fast = lds_f;
     c->lds_generic = lds_g;
@@ -486,6 +496,41 @@ bool out_of_resources(hipError_t e)
 // Launch n sweeps of every tile; on a resource failure halve the tile (and, at one
 // replica per tile, the workgroup) and retry, as the paper's Figure 7 halves its chain
 // packing when a launch runs out of registers.
+// One launch of whole-replica tiles: a run of consecutive tiles of one kind that the
+// compute units can hold `per_cu` at a time.
+struct LaunchGroup {
+    int kind, tile0, n_tiles, lds_bytes, per_cu;
+};
+
+// Workgroups of `lds` bytes a compute unit holds at once with the current block size.
+int occupancy(const pt_ctx *c, int lds)
+{
+    const int by_threads = std::max(1, c->cu_threads / std::max(1, c->block_threads));
+    const int by_lds = lds > 0 ? std::max(1, c->cu_lds / lds) : by_threads;
+    return std::min(by_threads, by_lds);
+}
+
+// Split the (LDS-descending) tile lists into occupancy classes, one launch each, sized to
+// the largest tile of the class.  A single launch would reserve the largest tile's LDS for
+// every workgroup and hold small tiles to the occupancy of the largest.
+std::vector<LaunchGroup> launch_groups(const pt_ctx *c)
+{
+    std::vector<LaunchGroup> out;
+    auto add_range = [&](int kind, int begin, int end) {
+        int t = begin;
+        while (t < end) {
+            const int k = occupancy(c, c->tile_lds[t]);
+            int u = t + 1;
+            while (u < end && occupancy(c, c->tile_lds[u]) == k) ++u;
+            out.push_back(LaunchGroup{kind, t, u - t, c->tile_lds[t], k});
+            t = u;
+        }
+    };
+    add_range(kTileFast, 0, c->n_fast_tiles);
+    add_range(kTileGeneric, c->n_fast_tiles, c->n_fast_tiles + c->n_generic_tiles);
+    return out;
+}
+
 int enqueue_sweep_once(pt_ctx *c, int n_sweeps)
 {
     if (n_sweeps <= 0) return PT_OK;
@@ -497,6 +542,7 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps)
         L.key1 = c->key_flip1;
         L.n_sweeps = n_sweeps;
         L.block_threads = c->block_threads;
+        L.lane_words = (c->opt.flags & PT_FLAG_FOUR_SLICE_LANES) ? 1 : 2;
         int ea = -1, eb = -1;
         if (timing) {
             int rc = event_pair(c, ea, eb);
@@ -508,15 +554,12 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps)
             c->inject_pending = false;
             e = hipErrorLaunchOutOfResources;
         } else {
-            L.tile0 = 0;
-            L.n_tiles = c->n_fast_tiles;
-            L.lds_bytes = c->lds_fast;
-            e = launch_sweep(L, kTileFast, c->stream);
-            if (e == hipSuccess) {
-                L.tile0 = c->n_fast_tiles;
-                L.n_tiles = c->n_generic_tiles;
-                L.lds_bytes = c->lds_generic;
-                e = launch_sweep(L, kTileGeneric, c->stream);
+            for (const LaunchGroup &g : launch_groups(c)) {
+                L.tile0 = g.tile0;
+                L.n_tiles = g.n_tiles;
+                L.lds_bytes = g.lds_bytes;
+                e = launch_sweep(L, g.kind, c->stream);
+                if (e != hipSuccess) break;
             }
             // slice blocks: one launch per parity phase of every sweep
             L.tile0 = c->n_fast_tiles + c->n_generic_tiles;
@@ -678,6 +721,13 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, c->device) ==
             hipSuccess && v > 0)
         c->cus = v;
+    c->cu_lds = c->lds_limit;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) ==
+            hipSuccess && v > 0)
+        c->cu_lds = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxThreadsPerMultiProcessor, c->device) ==
+            hipSuccess && v > 0)
+        c->cu_threads = v;
     if (workspace) {
         if (workspace_bytes < P.total_bytes)
             return cleanup(fail(PT_ENOMEM, "workspace smaller than pt_workspace_bytes()"));
@@ -769,8 +819,8 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     rc = build_tiles(c, opt->tile_replicas, opt->tile_bytes);
     if (rc) return cleanup(rc);
     if (opt->tile_replicas == 0 && opt->tile_bytes == 0 && opt->block_threads == 0) {
-        for (int tb : {8 * 1024, 32 * 1024, 64 * 1024, 128 * 1024})
-            for (int th : {512, 1024}) c->cand.emplace_back(tb, th);
+        for (int tb : {16 * 1024, 32 * 1024, 64 * 1024})
+            for (int th : {256, 512, 1024}) c->cand.emplace_back(tb, th);
         c->cand_ms.assign(c->cand.size(), 0.0);
         c->tuning = true;
         for (auto &ev : c->tune_ev) {
@@ -1004,6 +1054,7 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->sweep_launches = c->sweep_n;
     o->exchange_ms = c->exch_ms;
     o->exchange_launches = c->exch_n;
+    o->sweep_groups = (int32_t)launch_groups(c).size();
     return PT_OK;
 }
 

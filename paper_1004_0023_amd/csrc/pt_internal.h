@@ -18,6 +18,7 @@ struct SweepLaunch {
     int32_t sweep_off;
     int32_t first;         // first launch of a pt_sweep call: clear E_cl, C
     int32_t last;          // last launch: accumulate E_cl, C
+    int32_t lane_words;    // fast tiles: four-slice words per lane (2 needs G4 >= 2)
 };
 
 // Each returns the hipError_t of the launch itself (asynchronous execution errors

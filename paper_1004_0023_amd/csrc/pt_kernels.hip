@@ -136,9 +136,16 @@ struct TileLds {
     long long *red;    // reduction scratch
 };
 
+// Bytes between the replicas of a tile in LDS: N*M rounded up to whole words, then padded
+// so that the word stride is congruent to the slice-group count G4 modulo 64.  The lanes
+// of a wave run over (replica, slice group) with groups fastest, so replica q's words then
+// start at bank q*G4 and a wave's row reads spread over all banks instead of piling the
+// replicas onto the same ones (which an unpadded stride N*M/4 = 2*N*G4 words does).
 __host__ __device__ __forceinline__ int64_t rep_lds_bytes(const InstDesc &d)
 {
-    return ((int64_t)d.N * d.M + 3) & ~(int64_t)3;
+    int64_t w = ((int64_t)d.N * d.M + 3) >> 2;
+    if (d.G4 >= 1 && d.G4 < 64) w += (((int64_t)d.G4 - w) % 64 + 64) % 64;
+    return 4 * w;
 }
 
 // Shared by the host (to size the launch) and the kernels (to carve LDS).
@@ -177,27 +184,28 @@ __device__ __forceinline__ TileLds carve(char *lds, const InstDesc &d, int n_adj
     return t;
 }
 
-// Copy P replicas (each rep_bytes apart in device memory, rep_lds apart in LDS) in 32-bit
-// words; both strides are multiples of 4.
+// Copy the `words` words of each of P replicas between device memory (replicas
+// rep_words_dev apart) and LDS (replicas rep_words_lds apart, the padded stride); both
+// strides are at least `words`, so the LDS padding never reaches device memory.
 __device__ __forceinline__ void copy_spins_in(uint32_t *dst, const uint32_t *src, int P,
-                                              int rep_words_dev, int rep_words_lds)
+                                              int rep_words_dev, int rep_words_lds, int words)
 {
-    const int total = P * rep_words_lds;
+    const int total = P * words;
     for (int w = threadIdx.x; w < total; w += blockDim.x) {
-        const int q = w / rep_words_lds;
-        const int r = w - q * rep_words_lds;
-        dst[w] = src[(int64_t)q * rep_words_dev + r];
+        const int q = w / words;
+        const int r = w - q * words;
+        dst[q * rep_words_lds + r] = src[(int64_t)q * rep_words_dev + r];
     }
 }
 
 __device__ __forceinline__ void copy_spins_out(uint32_t *dst, const uint32_t *src, int P,
-                                               int rep_words_dev, int rep_words_lds)
+                                               int rep_words_dev, int rep_words_lds, int words)
 {
-    const int total = P * rep_words_lds;
+    const int total = P * words;
     for (int w = threadIdx.x; w < total; w += blockDim.x) {
-        const int q = w / rep_words_lds;
-        const int r = w - q * rep_words_lds;
-        dst[(int64_t)q * rep_words_dev + r] = src[w];
+        const int q = w / words;
+        const int r = w - q * words;
+        dst[(int64_t)q * rep_words_dev + r] = src[q * rep_words_lds + r];
     }
 }
 
@@ -208,7 +216,7 @@ __device__ __forceinline__ void stage_common(const DevState &st, const InstDesc 
     const uint32_t *src = reinterpret_cast<const uint32_t *>(
         st.spins + d.spin_base + (int64_t)tile.c0 * d.rep_bytes);
     copy_spins_in(reinterpret_cast<uint32_t *>(t.sp), src, tile.P, d.rep_bytes / 4,
-                  (int)(rep_lds_bytes(d) / 4));
+                  (int)(rep_lds_bytes(d) / 4), (d.N * d.M + 3) / 4);
     for (int i = tid; i < d.N; i += nt) t.csite[i] = st.csite[d.site_base + i];
     for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
     for (int q = 0; q < tile.P; ++q) {
@@ -233,7 +241,7 @@ __device__ __forceinline__ void write_back(const DevState &st, const InstDesc &d
     uint32_t *dst = reinterpret_cast<uint32_t *>(st.spins + d.spin_base +
                                                  (int64_t)tile.c0 * d.rep_bytes);
     copy_spins_out(dst, reinterpret_cast<const uint32_t *>(t.sp), tile.P, d.rep_bytes / 4,
-                   (int)(rep_lds_bytes(d) / 4));
+                   (int)(rep_lds_bytes(d) / 4), (d.N * d.M + 3) / 4);
 }
 
 // ------------------------------------------------------------------ fast sweep
@@ -243,121 +251,192 @@ __device__ __forceinline__ uint32_t lds32(const uint8_t *base, uint32_t byte_off
     return *reinterpret_cast<const uint32_t *>(base + byte_off);
 }
 
+// NW consecutive words at an offset that is a multiple of 4 * NW (one ds_read_b64 for two)
+template <int NW>
+__device__ __forceinline__ void ldsw(const uint8_t *base, uint32_t byte_off, uint32_t (&w)[NW])
+{
+    if constexpr (NW == 2) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(base + byte_off);
+        w[0] = v.x;
+        w[1] = v.y;
+    } else {
+        w[0] = lds32(base, byte_off);
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ void stsw(uint8_t *base, uint32_t byte_off, const uint32_t (&w)[NW])
+{
+    if constexpr (NW == 2)
+        *reinterpret_cast<uint2 *>(base + byte_off) = make_uint2(w[0], w[1]);
+    else
+        *reinterpret_cast<uint32_t *>(base + byte_off) = w[0];
+}
+
 __device__ __forceinline__ uint32_t popc(uint32_t x) { return (uint32_t)__popc(x); }
 
-// n sweeps of one tile on the fast path; DT > 0 fixes the (padded) degree at compile time
-// so the neighbour loads of a lane are issued together.
-// One lane's update of site i, replica q, slice group g4 in parity p: four Metropolis
-// attempts served by one Philox call.  DT > 0 fixes the (padded) degree at compile time
-// so the neighbour loads are issued together.
-template <int DT>
-__device__ __forceinline__ void fast_item(const SweepLaunch &L, const InstDesc &d,
-                                          const TileLds &t, int n, uint32_t tt, uint32_t c0,
-                                          int p, int i, int q, int g4, int lgMh)
+// Per-launch constants of a fast tile.
+struct FastArgs {
+    uint32_t key0, key1, tt, n, c0;
+    uint32_t NMh;       // bytes of one parity plane of a replica
+    uint32_t rs;        // bytes between replicas in LDS
+    uint32_t sel_x;     // v_perm selector: x -> x * (2F + 1)
+    int G4, lgG4, lgMh, tbl_words;
+};
+
+// One lane's update of site i, replica q, slice groups g4 .. g4 + NW - 1 of parity PAR:
+// 4 * NW Metropolis attempts served by NW Philox calls.  DT > 0 fixes the (padded) degree
+// at compile time so the neighbour loads are issued together.
+template <int DT, int NW, int PAR>
+__device__ __forceinline__ void fast_item(const FastArgs &a, const TileLds &t, int D, int i,
+                                          int q, int g4)
 {
-    const int G4 = d.G4;
-    const int D = (DT > 0) ? DT : d.D;
-    const uint32_t NM = (uint32_t)(d.N * d.M), NMh = (uint32_t)(d.N * d.Mh);
-    const uint32_t qbase = (uint32_t)q * NM;
-    const uint32_t irow = (uint32_t)i << lgMh;
-    const uint32_t nb_base = qbase + (uint32_t)p * NMh + 4u * (uint32_t)g4;
+    const int G4 = a.G4;
+    const uint32_t qbase = (uint32_t)q * a.rs;
+    const uint32_t irow = (uint32_t)i << a.lgMh;
+    const uint32_t nb_base = qbase + (uint32_t)PAR * a.NMh + 4u * (uint32_t)g4;
     const uint32_t own = nb_base + irow;
-    const uint32_t oth_row = qbase + (uint32_t)(p ^ 1) * NMh + irow;
-    const uint32_t X = lds32(t.sp, own);
-    const uint32_t Wc = lds32(t.sp, oth_row + 4 * g4);
-    // time neighbours live in the other parity: byte b of T is x(k-1) + x(k+1)
-    uint32_t T;
-    if (p == 0) {
-        const uint32_t Wp = lds32(t.sp, oth_row + 4 * ((g4 - 1) & (G4 - 1)));
-        T = __builtin_amdgcn_alignbyte(Wc, Wp, 3) + Wc;
+    const uint32_t oth_row = qbase + (uint32_t)(PAR ^ 1) * a.NMh + irow;
+    uint32_t X[NW], Wc[NW], T[NW];
+    ldsw<NW>(t.sp, own, X);
+    ldsw<NW>(t.sp, oth_row + 4u * (uint32_t)g4, Wc);
+    // time neighbours live in the other parity: byte b of T[k] is x(2m+PAR-1) + x(2m+PAR+1)
+    if constexpr (PAR == 0) {
+        const uint32_t Wp = lds32(t.sp, oth_row + 4u * (uint32_t)((g4 - 1) & (G4 - 1)));
+        T[0] = __builtin_amdgcn_alignbyte(Wc[0], Wp, 3) + Wc[0];
+        if constexpr (NW == 2) T[1] = __builtin_amdgcn_alignbyte(Wc[1], Wc[0], 3) + Wc[1];
     } else {
-        const uint32_t Wn = lds32(t.sp, oth_row + 4 * ((g4 + 1) & (G4 - 1)));
-        T = __builtin_amdgcn_alignbyte(Wn, Wc, 1) + Wc;
+        const uint32_t Wn = lds32(t.sp, oth_row + 4u * (uint32_t)((g4 + NW) & (G4 - 1)));
+        if constexpr (NW == 2) {
+            T[0] = __builtin_amdgcn_alignbyte(Wc[1], Wc[0], 1) + Wc[0];
+            T[1] = __builtin_amdgcn_alignbyte(Wn, Wc[1], 1) + Wc[1];
+        } else {
+            T[0] = __builtin_amdgcn_alignbyte(Wn, Wc[0], 1) + Wc[0];
+        }
     }
     // weighted count of neighbours per slice byte
     const uint32_t *er = t.ent + i * D;
-    uint32_t acc = 0;
-    if (DT > 0) {
-        uint32_t ents[DT > 0 ? DT : 1], ws[DT > 0 ? DT : 1];
+    uint32_t acc[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) acc[k] = 0;
+    if constexpr (DT > 0) {
+        uint32_t ents[DT], ws[DT][NW];
 #pragma unroll
         for (int e = 0; e < DT; ++e) ents[e] = er[e];
 #pragma unroll
-        for (int e = 0; e < DT; ++e) ws[e] = lds32(t.sp, nb_base + (ents[e] >> 16));
+        for (int e = 0; e < DT; ++e) ldsw<NW>(t.sp, nb_base + (ents[e] >> 16), ws[e]);
 #pragma unroll
-        for (int e = 0; e < DT; ++e) acc += __builtin_amdgcn_perm(0u, ents[e], ws[e]);
+        for (int e = 0; e < DT; ++e)
+#pragma unroll
+            for (int k = 0; k < NW; ++k) acc[k] += __builtin_amdgcn_perm(0u, ents[e], ws[e][k]);
     } else {
         for (int e = 0; e < D; ++e) {
             const uint32_t ent = er[e];
-            acc += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, nb_base + (ent >> 16)));
+            uint32_t w[NW];
+            ldsw<NW>(t.sp, nb_base + (ent >> 16), w);
+#pragma unroll
+            for (int k = 0; k < NW; ++k) acc[k] += __builtin_amdgcn_perm(0u, ent, w[k]);
         }
     }
-    const Words4 u = philox10(spin_ctr0(i, p, G4, g4), tt, c0 + (uint32_t)q, (uint32_t)n,
-                              L.key0, L.key1);
-    const uint32_t sel_x = (uint32_t)(2 * d.F + 1) << 8;  // v_perm table: x -> x * (2F + 1)
-    const uint32_t V = __builtin_amdgcn_perm(0u, sel_x, X) + (acc << 1) + t.bias[i];
-    const uint32_t IDX = V + (V << 1) + T;  // 3V + tau in every byte
-    const uint32_t *tb = t.tbl + q * d.tbl_words;
-    uint32_t flip = 0;
+    const uint32_t bias = t.bias[i];
+    const uint32_t *tb = t.tbl + q * a.tbl_words;
+    const uint32_t ctr = ((uint32_t)(2 * i + PAR) << a.lgG4) + (uint32_t)g4;
+    uint32_t out[NW];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const uint32_t thr = tb[(IDX >> (8 * b)) & 0xFFu];
-        flip |= (u.w[b] <= thr ? 1u : 0u) << (8 * b);
+    for (int k = 0; k < NW; ++k) {
+        const Words4 u = philox10(ctr + (uint32_t)k, a.tt, a.c0 + (uint32_t)q, a.n, a.key0, a.key1);
+        const uint32_t V = __builtin_amdgcn_perm(0u, a.sel_x, X[k]) + (acc[k] << 1) + bias;
+        const uint32_t IDX = V + (V << 1) + T[k];  // 3V + tau in every byte
+        uint32_t flip = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t thr = tb[(IDX >> (8 * b)) & 0xFFu];
+            flip |= (u.w[b] <= thr ? 1u : 0u) << (8 * b);
+        }
+        out[k] = X[k] ^ flip;
     }
-    *reinterpret_cast<uint32_t *>(t.sp + own) = X ^ flip;
+    stsw<NW>(t.sp, own, out);
 }
 
-// n sweeps of one tile on the fast path.  A class holds ns sites x P replicas x G4 slice
-// groups; lanes run over slice groups fastest, so the lanes of a site read one neighbour
-// row entry (broadcast) and consecutive words of each neighbour row.
-template <int DT>
+// All colour classes of parity PAR.  A class holds ns sites x P replicas x G4/NW lanes;
+// lanes run over slice groups fastest, so the lanes of a site read one neighbour row entry
+// (broadcast) and consecutive words of each neighbour row.
+template <int DT, int NW, int PAR>
+__device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d, const TileLds &t,
+                                           int lgGW, int lgL)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int Lmask = (1 << lgL) - 1;
+    const int D = (DT > 0) ? DT : d.D;
+    if ((1 << lgL) <= nt) {
+        // every thread keeps one (replica, lane group) and strides over the sites
+        const int r = tid & Lmask;
+        const int q = r >> lgGW;
+        const int g4 = NW * (r & ((1 << lgGW) - 1));
+        const int sstep = nt >> lgL;
+        for (int g = 0; g < d.n_colors; ++g) {
+            const int s1 = t.coff[g + 1];
+            for (int si = t.coff[g] + (tid >> lgL); si < s1; si += sstep)
+                fast_item<DT, NW, PAR>(a, t, D, t.csite[si], q, g4);
+            __syncthreads();
+        }
+    } else {
+        for (int g = 0; g < d.n_colors; ++g) {
+            const int s0 = t.coff[g];
+            const int items = (t.coff[g + 1] - s0) << lgL;
+            for (int it = tid; it < items; it += nt) {
+                const int r = it & Lmask;
+                fast_item<DT, NW, PAR>(a, t, D, t.csite[s0 + (it >> lgL)], r >> lgGW,
+                                       NW * (r & ((1 << lgGW) - 1)));
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int DT, int NW>
 __device__ __forceinline__ void fast_sweeps(const SweepLaunch &L, const InstDesc &d,
                                             const Tile &tile, const TileLds &t, uint64_t t0)
 {
-    const int n = tile.inst;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int lgG4 = ilog2(d.G4);
-    const int lgMh = lgG4 + 2;  // Mh = 4 * G4 on the fast path
-    const int lgL = ilog2(tile.P) + lgG4;  // lanes per site: P * G4
-    const int Lmask = (1 << lgL) - 1;
-    const uint32_t c0 = (uint32_t)tile.c0;
-    if ((1 << lgL) <= nt) {
-        // every thread keeps one (replica, slice group) and strides over the sites
-        const int r = tid & Lmask;
-        const int q = r >> lgG4;
-        const int g4 = r & (d.G4 - 1);
-        const int sstep = nt >> lgL;
-        for (int sw = 0; sw < L.n_sweeps; ++sw) {
-            const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
-            for (int p = 0; p < 2; ++p) {
-                for (int g = 0; g < d.n_colors; ++g) {
-                    const int s0 = t.coff[g];
-                    const int s1 = t.coff[g + 1];
-                    for (int si = s0 + (tid >> lgL); si < s1; si += sstep)
-                        fast_item<DT>(L, d, t, n, tt, c0, p, t.csite[si], q, g4, lgMh);
-                    __syncthreads();
-                }
-            }
-        }
-    } else {
-        for (int sw = 0; sw < L.n_sweeps; ++sw) {
-            const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
-            for (int p = 0; p < 2; ++p) {
-                for (int g = 0; g < d.n_colors; ++g) {
-                    const int s0 = t.coff[g];
-                    const int items = (t.coff[g + 1] - s0) << lgL;
-                    for (int it = tid; it < items; it += nt) {
-                        const int r = it & Lmask;
-                        fast_item<DT>(L, d, t, n, tt, c0, p, t.csite[s0 + (it >> lgL)],
-                                      r >> lgG4, r & (d.G4 - 1), lgMh);
-                    }
-                    __syncthreads();
-                }
-            }
-        }
+    FastArgs a;
+    a.key0 = L.key0;
+    a.key1 = L.key1;
+    a.n = (uint32_t)tile.inst;
+    a.c0 = (uint32_t)tile.c0;
+    a.NMh = (uint32_t)(d.N * d.Mh);
+    a.rs = (uint32_t)rep_lds_bytes(d);
+    a.sel_x = (uint32_t)(2 * d.F + 1) << 8;
+    a.G4 = d.G4;
+    a.lgG4 = ilog2(d.G4);
+    a.lgMh = ilog2(d.Mh);
+    a.tbl_words = d.tbl_words;
+    const int lgGW = ilog2(d.G4 / NW);
+    const int lgL = ilog2(tile.P) + lgGW;  // lanes per site: P * G4 / NW
+    for (int sw = 0; sw < L.n_sweeps; ++sw) {
+        a.tt = (uint32_t)(t0 + (uint64_t)sw);
+        fast_phase<DT, NW, 0>(a, d, t, lgGW, lgL);
+        fast_phase<DT, NW, 1>(a, d, t, lgGW, lgL);
     }
 }
 
-__global__ void __launch_bounds__(1024) sweep_fast_kernel(SweepLaunch L)
+template <int NW>
+__device__ __forceinline__ void fast_dispatch(const SweepLaunch &L, const InstDesc &d,
+                                              const Tile &tile, const TileLds &t, uint64_t t0)
+{
+    switch (d.D) {
+    case 1: fast_sweeps<1, NW>(L, d, tile, t, t0); break;
+    case 2: fast_sweeps<2, NW>(L, d, tile, t, t0); break;
+    case 3: fast_sweeps<3, NW>(L, d, tile, t, t0); break;
+    case 4: fast_sweeps<4, NW>(L, d, tile, t, t0); break;
+    case 5: fast_sweeps<5, NW>(L, d, tile, t, t0); break;
+    case 6: fast_sweeps<6, NW>(L, d, tile, t, t0); break;
+    case 7: fast_sweeps<7, NW>(L, d, tile, t, t0); break;
+    case 8: fast_sweeps<8, NW>(L, d, tile, t, t0); break;
+    default: fast_sweeps<0, NW>(L, d, tile, t, t0); break;
+    }
+}
+
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) sweep_fast_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
@@ -369,27 +448,20 @@ __global__ void __launch_bounds__(1024) sweep_fast_kernel(SweepLaunch L)
     const uint64_t t0 = st.ctr[n].t;
     __syncthreads();
 
-    switch (d.D) {
-    case 1: fast_sweeps<1>(L, d, tile, t, t0); break;
-    case 2: fast_sweeps<2>(L, d, tile, t, t0); break;
-    case 3: fast_sweeps<3>(L, d, tile, t, t0); break;
-    case 4: fast_sweeps<4>(L, d, tile, t, t0); break;
-    case 5: fast_sweeps<5>(L, d, tile, t, t0); break;
-    case 6: fast_sweeps<6>(L, d, tile, t, t0); break;
-    case 7: fast_sweeps<7>(L, d, tile, t, t0); break;
-    case 8: fast_sweeps<8>(L, d, tile, t, t0); break;
-    default: fast_sweeps<0>(L, d, tile, t, t0); break;
-    }
+    if (L.lane_words == 2 && d.G4 >= 2)
+        fast_dispatch<2>(L, d, tile, t, t0);
+    else
+        fast_dispatch<1>(L, d, tile, t, t0);
 
     const int tid = threadIdx.x, nt = blockDim.x;
     const int N = d.N, Mh = d.Mh, G4 = d.G4, D = d.D, F = d.F;
-    const uint32_t NM = (uint32_t)(N * d.M), NMh = (uint32_t)(N * Mh);
+    const uint32_t RSq = (uint32_t)rep_lds_bytes(d), NMh = (uint32_t)(N * Mh);
     const int lgG4 = ilog2(G4);
 
     // E_cl and C of every replica of the tile from its final spins
     for (int q = 0; q < tile.P; ++q) {
         long long ee = 0, cc = 0;
-        const uint32_t qbase = (uint32_t)q * NM;
+        const uint32_t qbase = (uint32_t)q * RSq;
         for (int it = tid; it < N * G4; it += nt) {
             const int i = it >> lgG4;
             const int g4 = it & (G4 - 1);

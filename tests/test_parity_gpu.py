@@ -157,6 +157,22 @@ def test_batch_launch_shapes(ptqmc, batch, tile_replicas, block_threads):
             assert_same(s, n, refs[n], f"shape({tile_replicas},{block_threads})")
 
 
+@pytest.mark.parametrize("tile_replicas,block_threads", [(0, 0), (2, 256)])
+def test_four_slice_lanes(ptqmc, tile_replicas, block_threads):
+    """The fast path with one four-slice word per lane instead of two: the same chain."""
+    insts = fast_batch()
+    seed = 0x4F0E5
+    k, cycles = 2, 20
+    say(f"case: fast batch, four-slice lanes, tile_replicas={tile_replicas} "
+        f"block_threads={block_threads}")
+    refs = oracle_batch(insts, seed, k, cycles)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_replicas=tile_replicas,
+                       block_threads=block_threads, flags=ptqmc.PT_FLAG_FOUR_SLICE_LANES) as s:
+        s.run(cycles)
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], "four-slice lanes")
+
+
 def test_split_calls_graph_and_eager_agree(ptqmc):
     insts = edge_batch()[:4]
     seed = 77
@@ -248,6 +264,8 @@ def test_config3_full_batch_sampled(ptqmc):
             assert sorted(obs["replica_of"]) == list(range(insts[n].R))
             assert np.array_equal(obs["rung_of"][obs["replica_of"]], np.arange(insts[n].R))
             assert obs["t"] == k * cycles and obs["e"] == cycles
+        # tiles of very different LDS needs go out in several occupancy classes
+        assert s.info()["sweep_groups"] >= 2
 
 
 @pytest.mark.parametrize("tile_bytes,block_threads", [(0, 256), (4096, 1024)])
