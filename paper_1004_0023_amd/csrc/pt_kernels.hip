@@ -209,6 +209,20 @@ __device__ __forceinline__ void copy_spins_out(uint32_t *dst, const uint32_t *sr
     }
 }
 
+// The threshold tables of the rungs that P consecutive replicas sit on, in one flat loop
+// so that the rung lookups of all replicas are in flight together.
+__device__ __forceinline__ void stage_tables(const DevState &st, const InstDesc &d, int c0, int P,
+                                             uint32_t *dst)
+{
+    const int tw = d.tbl_words;
+    for (int w = threadIdx.x; w < P * tw; w += blockDim.x) {
+        const int q = w / tw;
+        const int k = w - q * tw;
+        const int rung = st.rung_of[d.rep_base + c0 + q];
+        dst[w] = st.tbl[d.tbl_base + (int64_t)rung * tw + k];
+    }
+}
+
 __device__ __forceinline__ void stage_common(const DevState &st, const InstDesc &d, int n,
                                              const Tile &tile, const TileLds &t, int n_adj)
 {
@@ -219,11 +233,7 @@ __device__ __forceinline__ void stage_common(const DevState &st, const InstDesc 
                   (int)(rep_lds_bytes(d) / 4), (d.N * d.M + 3) / 4);
     for (int i = tid; i < d.N; i += nt) t.csite[i] = st.csite[d.site_base + i];
     for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
-    for (int q = 0; q < tile.P; ++q) {
-        const int rung = st.rung_of[d.rep_base + tile.c0 + q];
-        const uint32_t *tsrc = st.tbl + d.tbl_base + (int64_t)rung * d.tbl_words;
-        for (int w = tid; w < d.tbl_words; w += nt) t.tbl[q * d.tbl_words + w] = tsrc[w];
-    }
+    stage_tables(st, d, tile.c0, tile.P, t.tbl);
     if (d.fast) {
         for (int e = tid; e < d.N * d.D; e += nt) t.ent[e] = st.ent[d.ent_base + e];
         for (int i = tid; i < d.N; i += nt) t.bias[i] = st.bias[d.site_base + i];
@@ -369,14 +379,16 @@ __device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d,
     const int Lmask = (1 << lgL) - 1;
     const int D = (DT > 0) ? DT : d.D;
     if ((1 << lgL) <= nt) {
-        // every thread keeps one (replica, lane group) and strides over the sites
+        // every thread keeps one (replica, lane group) and strides over the sites; threads
+        // past the last whole site row (block sizes that are not powers of two) stay idle
         const int r = tid & Lmask;
         const int q = r >> lgGW;
         const int g4 = NW * (r & ((1 << lgGW) - 1));
         const int sstep = nt >> lgL;
+        const int s_first = (tid < (sstep << lgL)) ? (tid >> lgL) : (1 << 30);
         for (int g = 0; g < d.n_colors; ++g) {
             const int s1 = t.coff[g + 1];
-            for (int si = t.coff[g] + (tid >> lgL); si < s1; si += sstep)
+            for (int si = t.coff[g] + s_first; si < s1; si += sstep)
                 fast_item<DT, NW, PAR>(a, t, D, t.csite[si], q, g4);
             __syncthreads();
         }
@@ -458,11 +470,17 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const uint32_t RSq = (uint32_t)rep_lds_bytes(d), NMh = (uint32_t)(N * Mh);
     const int lgG4 = ilog2(G4);
 
-    // E_cl and C of every replica of the tile from its final spins
-    for (int q = 0; q < tile.P; ++q) {
+    // E_cl and C of every replica of the tile from its final spins.  Replicas are dealt to
+    // groups of waves (one wave each when the tile has at least as many replicas as the
+    // workgroup has waves), so the reductions need no workgroup barrier per replica.
+    const int lane = tid & (kWave - 1), wid = tid / kWave, nw = nt / kWave;
+    const int wpr = nw > tile.P ? nw / tile.P : 1;   // waves per replica (powers of two)
+    const int ngroups = nw / wpr;
+    const int grp = wid / wpr, sub = wid - grp * wpr;
+    for (int q = grp; q < tile.P; q += ngroups) {
         long long ee = 0, cc = 0;
         const uint32_t qbase = (uint32_t)q * RSq;
-        for (int it = tid; it < N * G4; it += nt) {
+        for (int it = sub * kWave + lane; it < N * G4; it += wpr * kWave) {
             const int i = it >> lgG4;
             const int g4 = it & (G4 - 1);
             const uint32_t row = (uint32_t)(i * Mh + 4 * g4);
@@ -493,11 +511,29 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             eterm += (long long)h * (2 * (long long)(popc(X0) + popc(X1)) - 8);
             ee += eterm;
         }
-        ee = block_sum(ee, t.red);
-        cc = block_sum(cc, t.red);
-        if (tid == 0) {
-            st.E[d.rep_base + tile.c0 + q] = ee;
-            st.C[d.rep_base + tile.c0 + q] = cc;
+        ee = wave_sum(ee);
+        cc = wave_sum(cc);
+        if (wpr == 1) {
+            if (lane == 0) {
+                st.E[d.rep_base + tile.c0 + q] = ee;
+                st.C[d.rep_base + tile.c0 + q] = cc;
+            }
+        } else if (lane == 0) {
+            t.red[2 * wid] = ee;
+            t.red[2 * wid + 1] = cc;
+        }
+    }
+    if (wpr > 1) {
+        // every group holds exactly one replica here (tile.P < nw)
+        __syncthreads();
+        if (sub == 0 && lane == 0 && grp < tile.P) {
+            long long ee = 0, cc = 0;
+            for (int w = wid; w < wid + wpr; ++w) {
+                ee += t.red[2 * w];
+                cc += t.red[2 * w + 1];
+            }
+            st.E[d.rep_base + tile.c0 + grp] = ee;
+            st.C[d.rep_base + tile.c0 + grp] = cc;
         }
     }
     write_back(st, d, tile, t);
@@ -663,11 +699,7 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
     for (int i = tid; i < N; i += nt) t.bias[i] = st.bias[d.site_base + i];
     for (int i = tid; i < N; i += nt) t.csite[i] = st.csite[d.site_base + i];
     for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
-    for (int q = 0; q < P; ++q) {
-        const int rung = st.rung_of[d.rep_base + tile.c0 + q];
-        const uint32_t *tsrc = st.tbl + d.tbl_base + (int64_t)rung * d.tbl_words;
-        for (int w = tid; w < d.tbl_words; w += nt) t.tbl[q * d.tbl_words + w] = tsrc[w];
-    }
+    stage_tables(st, d, tile.c0, P, t.tbl);
     if (L.first && g0 == 0)
         for (int q = tid; q < P; q += nt) {
             st.E[d.rep_base + tile.c0 + q] = 0;

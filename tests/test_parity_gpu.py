@@ -142,7 +142,8 @@ def test_config2_truncated(ptqmc):
 
 
 @pytest.mark.parametrize("batch", ["edge", "fast", "mixed"])
-@pytest.mark.parametrize("tile_replicas,block_threads", [(0, 0), (1, 64), (3, 512), (2, 1024)])
+@pytest.mark.parametrize("tile_replicas,block_threads",
+                         [(0, 0), (1, 64), (3, 512), (2, 1024), (4, 192), (0, 320)])
 def test_batch_launch_shapes(ptqmc, batch, tile_replicas, block_threads):
     insts = {"edge": edge_batch, "fast": fast_batch,
              "mixed": lambda: fast_batch()[:4] + edge_batch()[:4]}[batch]()
