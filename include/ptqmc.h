@@ -149,6 +149,7 @@ typedef struct {
     int64_t exchange_launches;
     int32_t sweep_groups;             /* launches of whole-replica tiles per sweep call:
                                          one per occupancy class of the tiles          */
+    int32_t block_tiles;              /* slice-block tiles (two launches per sweep)    */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

@@ -819,7 +819,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     rc = build_tiles(c, opt->tile_replicas, opt->tile_bytes);
     if (rc) return cleanup(rc);
     if (opt->tile_replicas == 0 && opt->tile_bytes == 0 && opt->block_threads == 0) {
-        for (int tb : {16 * 1024, 32 * 1024, 64 * 1024})
+        for (int tb : {16 * 1024, 32 * 1024, 64 * 1024, 128 * 1024})
             for (int th : {256, 512, 1024}) c->cand.emplace_back(tb, th);
         c->cand_ms.assign(c->cand.size(), 0.0);
         c->tuning = true;
@@ -1055,6 +1055,7 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->exchange_ms = c->exch_ms;
     o->exchange_launches = c->exch_n;
     o->sweep_groups = (int32_t)launch_groups(c).size();
+    o->block_tiles = c->n_block_tiles;
     return PT_OK;
 }
 

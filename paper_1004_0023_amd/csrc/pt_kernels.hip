@@ -186,26 +186,48 @@ __device__ __forceinline__ TileLds carve(char *lds, const InstDesc &d, int n_adj
 
 // Copy the `words` words of each of P replicas between device memory (replicas
 // rep_words_dev apart) and LDS (replicas rep_words_lds apart, the padded stride); both
-// strides are at least `words`, so the LDS padding never reaches device memory.
-__device__ __forceinline__ void copy_spins_in(uint32_t *dst, const uint32_t *src, int P,
-                                              int rep_words_dev, int rep_words_lds, int words)
+// strides are at least `words`, so the LDS padding never reaches device memory.  The
+// (replica, word) position of a thread advances by blockDim.x each step without a
+// division; when the word count and both strides are multiples of 4 the copy moves 16
+// bytes per access.
+template <bool IN>
+__device__ __forceinline__ void copy_spins(uint32_t *lds_sp, uint32_t *dev, int P,
+                                           int rep_words_dev, int rep_words_lds, int words)
 {
-    const int total = P * words;
-    for (int w = threadIdx.x; w < total; w += blockDim.x) {
-        const int q = w / words;
-        const int r = w - q * words;
-        dst[q * rep_words_lds + r] = src[(int64_t)q * rep_words_dev + r];
-    }
-}
-
-__device__ __forceinline__ void copy_spins_out(uint32_t *dst, const uint32_t *src, int P,
-                                               int rep_words_dev, int rep_words_lds, int words)
-{
-    const int total = P * words;
-    for (int w = threadIdx.x; w < total; w += blockDim.x) {
-        const int q = w / words;
-        const int r = w - q * words;
-        dst[(int64_t)q * rep_words_dev + r] = src[q * rep_words_lds + r];
+    const int nt = blockDim.x;
+    if (((words | rep_words_dev | rep_words_lds) & 3) == 0) {
+        const int wv = words >> 2, dv = rep_words_dev >> 2, lv = rep_words_lds >> 2;
+        uint4 *L4 = reinterpret_cast<uint4 *>(lds_sp);
+        uint4 *D4 = reinterpret_cast<uint4 *>(dev);
+        const int qs = nt / wv, rs = nt - qs * wv;
+        int q = threadIdx.x / wv, r = threadIdx.x - q * wv;
+        for (; q < P;) {
+            if (IN)
+                L4[q * lv + r] = D4[(int64_t)q * dv + r];
+            else
+                D4[(int64_t)q * dv + r] = L4[q * lv + r];
+            q += qs;
+            r += rs;
+            if (r >= wv) {
+                r -= wv;
+                ++q;
+            }
+        }
+    } else {
+        const int qs = nt / words, rs = nt - qs * words;
+        int q = threadIdx.x / words, r = threadIdx.x - q * words;
+        for (; q < P;) {
+            if (IN)
+                lds_sp[q * rep_words_lds + r] = dev[(int64_t)q * rep_words_dev + r];
+            else
+                dev[(int64_t)q * rep_words_dev + r] = lds_sp[q * rep_words_lds + r];
+            q += qs;
+            r += rs;
+            if (r >= words) {
+                r -= words;
+                ++q;
+            }
+        }
     }
 }
 
@@ -214,12 +236,18 @@ __device__ __forceinline__ void copy_spins_out(uint32_t *dst, const uint32_t *sr
 __device__ __forceinline__ void stage_tables(const DevState &st, const InstDesc &d, int c0, int P,
                                              uint32_t *dst)
 {
-    const int tw = d.tbl_words;
-    for (int w = threadIdx.x; w < P * tw; w += blockDim.x) {
-        const int q = w / tw;
-        const int k = w - q * tw;
+    const int tw = d.tbl_words, nt = blockDim.x;
+    const int qs = nt / tw, ks = nt - qs * tw;
+    int q = threadIdx.x / tw, k = threadIdx.x - q * tw;
+    for (; q < P;) {
         const int rung = st.rung_of[d.rep_base + c0 + q];
-        dst[w] = st.tbl[d.tbl_base + (int64_t)rung * tw + k];
+        dst[q * tw + k] = st.tbl[d.tbl_base + (int64_t)rung * tw + k];
+        q += qs;
+        k += ks;
+        if (k >= tw) {
+            k -= tw;
+            ++q;
+        }
     }
 }
 
@@ -229,8 +257,8 @@ __device__ __forceinline__ void stage_common(const DevState &st, const InstDesc 
     const int tid = threadIdx.x, nt = blockDim.x;
     const uint32_t *src = reinterpret_cast<const uint32_t *>(
         st.spins + d.spin_base + (int64_t)tile.c0 * d.rep_bytes);
-    copy_spins_in(reinterpret_cast<uint32_t *>(t.sp), src, tile.P, d.rep_bytes / 4,
-                  (int)(rep_lds_bytes(d) / 4), (d.N * d.M + 3) / 4);
+    copy_spins<true>(reinterpret_cast<uint32_t *>(t.sp), const_cast<uint32_t *>(src), tile.P,
+                     d.rep_bytes / 4, (int)(rep_lds_bytes(d) / 4), (d.N * d.M + 3) / 4);
     for (int i = tid; i < d.N; i += nt) t.csite[i] = st.csite[d.site_base + i];
     for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
     stage_tables(st, d, tile.c0, tile.P, t.tbl);
@@ -250,8 +278,8 @@ __device__ __forceinline__ void write_back(const DevState &st, const InstDesc &d
 {
     uint32_t *dst = reinterpret_cast<uint32_t *>(st.spins + d.spin_base +
                                                  (int64_t)tile.c0 * d.rep_bytes);
-    copy_spins_out(dst, reinterpret_cast<const uint32_t *>(t.sp), tile.P, d.rep_bytes / 4,
-                   (int)(rep_lds_bytes(d) / 4), (d.N * d.M + 3) / 4);
+    copy_spins<false>(reinterpret_cast<uint32_t *>(t.sp), dst, tile.P, d.rep_bytes / 4,
+                      (int)(rep_lds_bytes(d) / 4), (d.N * d.M + 3) / 4);
 }
 
 // ------------------------------------------------------------------ fast sweep
@@ -478,7 +506,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const int ngroups = nw / wpr;
     const int grp = wid / wpr, sub = wid - grp * wpr;
     for (int q = grp; q < tile.P; q += ngroups) {
-        long long ee = 0, cc = 0;
+        // per lane in 32 bits (a replica of the fast path holds at most 2^14 items of
+        // eight slices, each contributing |2E| <= 8 * (4F + 2F) and |C| <= 8)
+        int e2 = 0, c1 = 0;
         const uint32_t qbase = (uint32_t)q * RSq;
         for (int it = sub * kWave + lane; it < N * G4; it += wpr * kWave) {
             const int i = it >> lgG4;
@@ -488,34 +518,35 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             const uint32_t X1 = lds32(t.sp, qbase + NMh + row);
             const uint32_t X0n = lds32(t.sp, qbase + (uint32_t)(i * Mh + 4 * ((g4 + 1) & (G4 - 1))));
             // time bonds (2m, 2m+1) and (2m+1, 2m+2): 8 per group
-            const uint32_t dis_t = popc(X0 ^ X1) + popc(X1 ^ __builtin_amdgcn_alignbyte(X0n, X0, 1));
-            cc += 8 - 2 * (long long)dis_t;
-            // fields over the group's 8 slices
-            const int hval = (int)(t.bias[i] & 0xFFu) - F;  // h - sum|J|
-            int sumJ = 0;
+            const int dis_t = (int)(popc(X0 ^ X1) + popc(X1 ^ __builtin_amdgcn_alignbyte(X0n, X0, 1)));
+            c1 += 8 - 2 * dis_t;
+            // the sweep's byte field: g = f + F = 2 * (weighted aligned neighbours) + bias
             const uint32_t *er = t.ent + i * D;
-            long long eterm = 0;
+            uint32_t A0 = 0, A1 = 0;
+            int sumJ = 0;
             for (int e = 0; e < D; ++e) {
                 const uint32_t ent = er[e];
-                const int w0 = (int)(ent & 0xFFu), w1 = (int)((ent >> 8) & 0xFFu);
-                const int J = w1 - w0;
-                sumJ += w0 + w1;
-                const uint32_t joff = ent >> 16;
-                if (J != 0 && joff > (uint32_t)(i * Mh)) {  // each edge once (j > i)
-                    const uint32_t Y0 = lds32(t.sp, qbase + joff + 4 * g4);
-                    const uint32_t Y1 = lds32(t.sp, qbase + NMh + joff + 4 * g4);
-                    eterm += (long long)J * (8 - 2 * (long long)(popc(X0 ^ Y0) + popc(X1 ^ Y1)));
-                }
+                const uint32_t joff = qbase + (ent >> 16) + 4u * (uint32_t)g4;
+                A0 += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, joff));
+                A1 += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, joff + NMh));
+                sumJ += (int)((ent & 0xFFu) + ((ent >> 8) & 0xFFu));  // |J| of the edge
             }
-            const int h = hval + sumJ;
-            eterm += (long long)h * (2 * (long long)(popc(X0) + popc(X1)) - 8);
-            ee += eterm;
+            const uint32_t bias = t.bias[i];
+            const uint32_t G0 = (A0 << 1) + bias, G1 = (A1 << 1) + bias;
+            const int hF = (int)(bias & 0xFFu) + sumJ - 2 * F;  // h - F
+            // 2E over the eight slices: sum_b (2 x_b - 1) (g_b - F + h)
+            const int dot = (int)__builtin_amdgcn_udot4(X0, G0, __builtin_amdgcn_udot4(X1, G1, 0u, false), false);
+            const int gs = (int)__builtin_amdgcn_udot4(0x01010101u, G0,
+                                                       __builtin_amdgcn_udot4(0x01010101u, G1, 0u, false), false);
+            const int pc = (int)(popc(X0) + popc(X1));
+            e2 += 2 * dot + 2 * hF * pc - gs - 8 * hF;
         }
+        long long ee = e2, cc = c1;
         ee = wave_sum(ee);
         cc = wave_sum(cc);
         if (wpr == 1) {
             if (lane == 0) {
-                st.E[d.rep_base + tile.c0 + q] = ee;
+                st.E[d.rep_base + tile.c0 + q] = ee / 2;
                 st.C[d.rep_base + tile.c0 + q] = cc;
             }
         } else if (lane == 0) {
@@ -532,7 +563,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                 ee += t.red[2 * w];
                 cc += t.red[2 * w + 1];
             }
-            st.E[d.rep_base + tile.c0 + grp] = ee;
+            st.E[d.rep_base + tile.c0 + grp] = ee / 2;
             st.C[d.rep_base + tile.c0 + grp] = cc;
         }
     }
@@ -549,6 +580,38 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 // (read in phase 1).  LDS rows, per replica and parity plane, hold ng + 1 words:
 //   plane 0: slots 0..ng-1 = groups g0..g0+ng-1, slot ng = group g0+ng (mod G4)
 //   plane 1: slot 0 = group g0-1 (mod G4), slots 1..ng = groups g0..g0+ng-1
+
+// A thread's position (x, y, z) in a linear walk over [z][y][x] (x < nx, y < ny) that
+// advances by a fixed stride per step, with carries instead of divisions.
+struct Walk3 {
+    int x, y, z, sx, sy, sz, nx, ny;
+    __device__ __forceinline__ Walk3(int start, int stride, int nx_, int ny_) : nx(nx_), ny(ny_)
+    {
+        x = start % nx;
+        const int r = start / nx;
+        y = r % ny;
+        z = r / ny;
+        sx = stride % nx;
+        const int rs = stride / nx;
+        sy = rs % ny;
+        sz = rs / ny;
+    }
+    __device__ __forceinline__ void step()
+    {
+        x += sx;
+        int c = 0;
+        if (x >= nx) {
+            x -= nx;
+            c = 1;
+        }
+        y += sy + c;
+        z += sz;
+        if (y >= ny) {
+            y -= ny;
+            ++z;
+        }
+    }
+};
 
 struct BlockLds {
     uint8_t *sp;       // P replicas x 2 planes x N rows x (ng + 1) words
@@ -681,19 +744,13 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
 
     // stage: both planes of the block (+ halos), rows, biases, colour lists, rung tables
     const int slots = ng + 1;
-    const int words = P * 2 * N * slots;
-    for (int w = tid; w < words; w += nt) {
-        const int s = w % slots;
-        const int rowi = w / slots;  // (q, pl, i)
-        const int i = rowi % N;
-        const int qp = rowi / N;
-        const int pl = qp & 1;
-        const int q = qp >> 1;
+    for (Walk3 wk(tid, nt, slots, N); wk.z < 2 * P; wk.step()) {  // (slot, site, q * 2 + plane)
+        const int s = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
         const int grp = block_slot_group(pl, s, g0, ng, G4);
         const uint32_t *src = reinterpret_cast<const uint32_t *>(
             st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
             (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh + 4 * grp);
-        reinterpret_cast<uint32_t *>(t.sp)[w] = *src;
+        reinterpret_cast<uint32_t *>(t.sp)[(wk.z * N + i) * slots + s] = *src;
     }
     for (int e = tid; e < N * d.D; e += nt) t.ent[e] = st.ent[d.ent_base + e];
     for (int i = tid; i < N; i += nt) t.bias[i] = st.bias[d.site_base + i];
@@ -766,11 +823,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
 
     // write back the phase's own groups
     const int p = L.phase;
-    for (int w = tid; w < P * N * ng; w += nt) {
-        const int lg = w % ng;
-        const int qi = w / ng;
-        const int i = qi % N;
-        const int q = qi / N;
+    for (Walk3 wk(tid, nt, ng, N); wk.z < P; wk.step()) {  // (group, site, replica)
+        const int lg = wk.x, i = wk.y, q = wk.z;
         const uint32_t v = lds32(t.sp, (uint32_t)q * 2u * N * 4u * slots + (uint32_t)p * N * 4u * slots +
                                            (uint32_t)i * 4u * slots + 4u * (uint32_t)(lg + p));
         *reinterpret_cast<uint32_t *>(st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
