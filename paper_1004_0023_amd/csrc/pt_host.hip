@@ -819,7 +819,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     rc = build_tiles(c, opt->tile_replicas, opt->tile_bytes);
     if (rc) return cleanup(rc);
     if (opt->tile_replicas == 0 && opt->tile_bytes == 0 && opt->block_threads == 0) {
-        for (int tb : {16 * 1024, 32 * 1024, 64 * 1024, 128 * 1024})
+        for (int tb : {8 * 1024, 16 * 1024, 32 * 1024, 64 * 1024, 128 * 1024})
             for (int th : {256, 512, 1024}) c->cand.emplace_back(tb, th);
         c->cand_ms.assign(c->cand.size(), 0.0);
         c->tuning = true;
