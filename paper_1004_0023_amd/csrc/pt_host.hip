@@ -667,6 +667,8 @@ int check_inst(pt_ctx *c, int32_t inst)
 
 }  // namespace
 
+int ptq::report_error(int code, const char *msg) { return fail(code, msg); }
+
 extern "C" {
 
 int pt_workspace_bytes(const pt_instance *inst, int32_t n_inst, const pt_options *opt,

@@ -33,6 +33,9 @@ hipError_t launch_advance(const DevState &st, int32_t n_inst, uint32_t t_add, hi
 hipError_t launch_threshold_eval(const double *dS, uint32_t *out, int32_t n, hipStream_t s);
 hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes);
 
+// Record msg as the calling thread's last error (pt_last_error) and return code.
+int report_error(int code, const char *msg);
+
 // LDS bytes a tile of P replicas of instance d needs in its sweep kernel.
 int32_t sweep_tile_lds_bytes(const InstDesc &d, int32_t n_adj, int32_t P);
 // LDS bytes of a slice-block tile: P replicas, ng four-slice groups per parity.

@@ -14,9 +14,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+#include <string>
+
 #include "../../include/ptqmc.h"
+#include "pt_internal.h"
 
 namespace {
+
+// PT_OK, or PT_EHIP with the HIP error recorded as the last error
+int launched(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return PT_OK;
+    return ptq::report_error(PT_EHIP, (std::string(what) + ": " + hipGetErrorString(e)).c_str());
+}
 
 constexpr int kIn = 32, kH = 128, kOut = 64;
 constexpr int kW1 = 0, kB1 = kW1 + kH * kIn, kW2 = kB1 + kH, kB2 = kW2 + kH * kH,
@@ -180,30 +191,34 @@ size_t pt_mlp_workspace_bytes(int32_t batch)
 int pt_mlp_forward(const float *params, const float *x, float *logits, int32_t batch,
                    void *workspace, void *stream)
 {
-    if (!params || !x || !logits || !workspace || batch < 1) return PT_EINVAL;
+    if (!params || !x || !logits || !workspace)
+        return ptq::report_error(PT_EINVAL, "pt_mlp_forward: null pointer");
+    if (batch < 1) return ptq::report_error(PT_EINVAL, "pt_mlp_forward: batch < 1");
     hipStream_t s = (hipStream_t)stream;
     const Acts a = carve(workspace, batch);
-    if (forward(s, params, x, a, logits, batch) != hipSuccess) return PT_EHIP;
-    return PT_OK;
+    return launched(forward(s, params, x, a, logits, batch), "pt_mlp_forward");
 }
 
 int pt_mlp_loss_grad(const float *params, const float *x, const float *target, int32_t batch,
                      int32_t loss_kind, float *grads, float *loss, void *workspace, void *stream)
 {
-    if (!params || !x || !target || !grads || !loss || !workspace || batch < 1) return PT_EINVAL;
-    if (loss_kind != PT_MLP_LOSS_SOFTMAX && loss_kind != PT_MLP_LOSS_SIGMOID) return PT_EINVAL;
+    if (!params || !x || !target || !grads || !loss || !workspace)
+        return ptq::report_error(PT_EINVAL, "pt_mlp_loss_grad: null pointer");
+    if (batch < 1) return ptq::report_error(PT_EINVAL, "pt_mlp_loss_grad: batch < 1");
+    if (loss_kind != PT_MLP_LOSS_SOFTMAX && loss_kind != PT_MLP_LOSS_SIGMOID)
+        return ptq::report_error(PT_EINVAL, "pt_mlp_loss_grad: unknown loss kind");
     hipStream_t s = (hipStream_t)stream;
     const Acts a = carve(workspace, batch);
     const float *P = params;
     float *G = grads;
     const int B = batch;
-    if (forward(s, P, x, a, a.z3, B) != hipSuccess) return PT_EHIP;
+    hipError_t e = forward(s, P, x, a, a.z3, B);
+    if (e != hipSuccess) return launched(e, "pt_mlp_loss_grad");
     if (loss_kind == PT_MLP_LOSS_SOFTMAX)
         hipLaunchKernelGGL(softmax_xent_kernel, dim3(B), dim3(64), 0, s, a.z3, target, a.dz3, a.loss, B);
     else
         hipLaunchKernelGGL(sigmoid_xent_kernel, dim3(B), dim3(64), 0, s, a.z3, target, a.dz3, a.loss, B);
-    if (hipGetLastError() != hipSuccess) return PT_EHIP;
-    hipError_t e = hipSuccess;
+    e = hipGetLastError();
     // layer 3: dW3[o][k] = sum_b dz3[b][o] h2[b][k]; db3; dz2 = (dz3 W3) * [h2 > 0]
     if (!e) e = gemm(s, a.dz3, 1, kOut, a.h2, kH, 1, G + kW3, kH, kOut, kH, B, nullptr, 0, nullptr);
     if (!e) { hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(kOut), 0, s, a.dz3, G + kB3, B, kOut); e = hipGetLastError(); }
@@ -217,23 +232,20 @@ int pt_mlp_loss_grad(const float *params, const float *x, const float *target, i
     if (!e) { hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(kH), 0, s, a.dz1, G + kB1, B, kH); e = hipGetLastError(); }
     // loss[0] = sum over the batch of the per-sample cross entropies
     if (!e) { hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(1), 0, s, a.loss, loss, B, 1); e = hipGetLastError(); }
-    return e == hipSuccess ? PT_OK : PT_EHIP;
+    return launched(e, "pt_mlp_loss_grad");
 }
 
 int pt_mlp_adam(float *params, const float *grads, float *m, float *v, int32_t n, float lr,
                 float beta1, float beta2, float eps, int32_t step, void *stream)
 {
-    if (!params || !grads || !m || !v || n < 1 || step < 1) return PT_EINVAL;
-    float c1 = 1.f, c2 = 1.f, p1 = 1.f, p2 = 1.f;
-    for (int i = 0; i < step; ++i) {
-        p1 *= beta1;
-        p2 *= beta2;
-    }
-    c1 = 1.f - p1;
-    c2 = 1.f - p2;
+    if (!params || !grads || !m || !v) return ptq::report_error(PT_EINVAL, "pt_mlp_adam: null pointer");
+    if (n < 1 || step < 1) return ptq::report_error(PT_EINVAL, "pt_mlp_adam: n < 1 or step < 1");
+    // bias corrections 1 - beta^step
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
     hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                        params, grads, m, v, n, lr, beta1, beta2, eps, c1, c2);
-    return hipGetLastError() == hipSuccess ? PT_OK : PT_EHIP;
+    return launched(hipGetLastError(), "pt_mlp_adam");
 }
 
 }  // extern "C"

@@ -111,3 +111,21 @@ def test_field_bound_rejected():
                            np.full(8, 127, np.int8), np.full(9, 127, np.int8), 2, [1.0, 2.0], 1.0)]
     rc, _, msg = _ws_bytes(big, ptqmc)
     assert rc == ptqmc.PT_EINVAL and "1023" in msg
+
+
+def test_network_entry_points_reject_bad_arguments():
+    """The ladder-network entry points validate their arguments on the host and record the
+    reason as the last error (no device work is queued)."""
+    ptqmc = _lib()
+    L = ptqmc.lib()
+    assert L.pt_mlp_param_count() == 28992
+    assert L.pt_mlp_workspace_bytes(0) == 0 and L.pt_mlp_workspace_bytes(256) > 0
+    rc = L.pt_mlp_forward(None, None, None, 4, None, None)
+    assert rc == ptqmc.PT_EINVAL and "null pointer" in L.pt_last_error().decode()
+    one = C.c_void_p(8)  # never dereferenced: the batch check fails first
+    rc = L.pt_mlp_forward(one, one, one, 0, one, None)
+    assert rc == ptqmc.PT_EINVAL and "batch" in L.pt_last_error().decode()
+    rc = L.pt_mlp_loss_grad(one, one, one, 4, 7, one, one, one, None)
+    assert rc == ptqmc.PT_EINVAL and "loss kind" in L.pt_last_error().decode()
+    rc = L.pt_mlp_adam(one, one, one, one, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None)
+    assert rc == ptqmc.PT_EINVAL and "step" in L.pt_last_error().decode()
