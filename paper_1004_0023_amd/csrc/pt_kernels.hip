@@ -476,74 +476,77 @@ __device__ __forceinline__ void fast_dispatch(const SweepLaunch &L, const InstDe
     }
 }
 
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) sweep_fast_kernel(SweepLaunch L)
+// E_cl and C of every replica of a fast tile from its final spins.  Per site and group of
+// eight slices (two words, one per parity) the byte field g = f + F = 2 A + bias is formed
+// as in the sweep, and 2E over the eight slices is sum_b (2 x_b - 1)(g_b - F + h), taken with
+// two v_dot4_u32_u8; h - F = bias - 2F + sum |J|, and each entry's two weight bytes sum to
+// its |J|.  C comes from popcounts of x xor (x shifted one slice in time).  Replicas are
+// dealt to groups of waves (one wave each when the tile has at least as many replicas as
+// the workgroup has waves), so the reductions need at most one workgroup barrier.
+template <int DT>
+__device__ __forceinline__ void fast_energy(const DevState &st, const InstDesc &d, const Tile &tile,
+                                            const TileLds &t)
 {
-    extern __shared__ __align__(16) char lds[];
-    const DevState &st = L.st;
-    const Tile tile = st.tiles[L.tile0 + blockIdx.x];
-    const int n = tile.inst;
-    const InstDesc d = st.inst[n];
-    TileLds t = carve(lds, d, 0, tile.P);
-    stage_common(st, d, n, tile, t, 0);
-    const uint64_t t0 = st.ctr[n].t;
-    __syncthreads();
-
-    if (L.lane_words == 2 && d.G4 >= 2)
-        fast_dispatch<2>(L, d, tile, t, t0);
-    else
-        fast_dispatch<1>(L, d, tile, t, t0);
-
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int N = d.N, Mh = d.Mh, G4 = d.G4, D = d.D, F = d.F;
+    const int N = d.N, Mh = d.Mh, G4 = d.G4, F = d.F;
+    const int D = (DT > 0) ? DT : d.D;
     const uint32_t RSq = (uint32_t)rep_lds_bytes(d), NMh = (uint32_t)(N * Mh);
     const int lgG4 = ilog2(G4);
-
-    // E_cl and C of every replica of the tile from its final spins.  Replicas are dealt to
-    // groups of waves (one wave each when the tile has at least as many replicas as the
-    // workgroup has waves), so the reductions need no workgroup barrier per replica.
     const int lane = tid & (kWave - 1), wid = tid / kWave, nw = nt / kWave;
-    const int wpr = nw > tile.P ? nw / tile.P : 1;   // waves per replica (powers of two)
+    const int wpr = nw > tile.P ? nw / tile.P : 1;   // waves per replica
     const int ngroups = nw / wpr;
     const int grp = wid / wpr, sub = wid - grp * wpr;
     for (int q = grp; q < tile.P; q += ngroups) {
         // per lane in 32 bits (a replica of the fast path holds at most 2^14 items of
-        // eight slices, each contributing |2E| <= 8 * (4F + 2F) and |C| <= 8)
+        // eight slices, each contributing |2E| <= 8 * 6F and |C| <= 8)
         int e2 = 0, c1 = 0;
         const uint32_t qbase = (uint32_t)q * RSq;
         for (int it = sub * kWave + lane; it < N * G4; it += wpr * kWave) {
             const int i = it >> lgG4;
             const int g4 = it & (G4 - 1);
-            const uint32_t row = (uint32_t)(i * Mh + 4 * g4);
-            const uint32_t X0 = lds32(t.sp, qbase + row);
-            const uint32_t X1 = lds32(t.sp, qbase + NMh + row);
-            const uint32_t X0n = lds32(t.sp, qbase + (uint32_t)(i * Mh + 4 * ((g4 + 1) & (G4 - 1))));
+            const uint32_t row = qbase + (uint32_t)(i * Mh);
+            const uint32_t X0 = lds32(t.sp, row + 4u * (uint32_t)g4);
+            const uint32_t X1 = lds32(t.sp, row + NMh + 4u * (uint32_t)g4);
+            const uint32_t X0n = lds32(t.sp, row + 4u * (uint32_t)((g4 + 1) & (G4 - 1)));
             // time bonds (2m, 2m+1) and (2m+1, 2m+2): 8 per group
             const int dis_t = (int)(popc(X0 ^ X1) + popc(X1 ^ __builtin_amdgcn_alignbyte(X0n, X0, 1)));
             c1 += 8 - 2 * dis_t;
-            // the sweep's byte field: g = f + F = 2 * (weighted aligned neighbours) + bias
             const uint32_t *er = t.ent + i * D;
-            uint32_t A0 = 0, A1 = 0;
-            int sumJ = 0;
-            for (int e = 0; e < D; ++e) {
-                const uint32_t ent = er[e];
-                const uint32_t joff = qbase + (ent >> 16) + 4u * (uint32_t)g4;
-                A0 += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, joff));
-                A1 += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, joff + NMh));
-                sumJ += (int)((ent & 0xFFu) + ((ent >> 8) & 0xFFu));  // |J| of the edge
+            const uint32_t nb = qbase + 4u * (uint32_t)g4;
+            uint32_t A0 = 0, A1 = 0, sumJ = 0;
+            if constexpr (DT > 0) {
+                uint32_t ents[DT], y0[DT], y1[DT];
+#pragma unroll
+                for (int e = 0; e < DT; ++e) ents[e] = er[e];
+#pragma unroll
+                for (int e = 0; e < DT; ++e) {
+                    y0[e] = lds32(t.sp, nb + (ents[e] >> 16));
+                    y1[e] = lds32(t.sp, nb + (ents[e] >> 16) + NMh);
+                }
+#pragma unroll
+                for (int e = 0; e < DT; ++e) {
+                    A0 += __builtin_amdgcn_perm(0u, ents[e], y0[e]);
+                    A1 += __builtin_amdgcn_perm(0u, ents[e], y1[e]);
+                    sumJ = __builtin_amdgcn_udot4(ents[e], 0x00000101u, sumJ, false);
+                }
+            } else {
+                for (int e = 0; e < D; ++e) {
+                    const uint32_t ent = er[e];
+                    A0 += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, nb + (ent >> 16)));
+                    A1 += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, nb + (ent >> 16) + NMh));
+                    sumJ = __builtin_amdgcn_udot4(ent, 0x00000101u, sumJ, false);
+                }
             }
             const uint32_t bias = t.bias[i];
             const uint32_t G0 = (A0 << 1) + bias, G1 = (A1 << 1) + bias;
-            const int hF = (int)(bias & 0xFFu) + sumJ - 2 * F;  // h - F
-            // 2E over the eight slices: sum_b (2 x_b - 1) (g_b - F + h)
+            const int hF = (int)(bias & 0xFFu) + (int)sumJ - 2 * F;  // h - F
             const int dot = (int)__builtin_amdgcn_udot4(X0, G0, __builtin_amdgcn_udot4(X1, G1, 0u, false), false);
             const int gs = (int)__builtin_amdgcn_udot4(0x01010101u, G0,
                                                        __builtin_amdgcn_udot4(0x01010101u, G1, 0u, false), false);
             const int pc = (int)(popc(X0) + popc(X1));
             e2 += 2 * dot + 2 * hF * pc - gs - 8 * hF;
         }
-        long long ee = e2, cc = c1;
-        ee = wave_sum(ee);
-        cc = wave_sum(cc);
+        long long ee = wave_sum((long long)e2), cc = wave_sum((long long)c1);
         if (wpr == 1) {
             if (lane == 0) {
                 st.E[d.rep_base + tile.c0 + q] = ee / 2;
@@ -566,6 +569,36 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             st.E[d.rep_base + tile.c0 + grp] = ee / 2;
             st.C[d.rep_base + tile.c0 + grp] = cc;
         }
+    }
+}
+
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) sweep_fast_kernel(SweepLaunch L)
+{
+    extern __shared__ __align__(16) char lds[];
+    const DevState &st = L.st;
+    const Tile tile = st.tiles[L.tile0 + blockIdx.x];
+    const int n = tile.inst;
+    const InstDesc d = st.inst[n];
+    TileLds t = carve(lds, d, 0, tile.P);
+    stage_common(st, d, n, tile, t, 0);
+    const uint64_t t0 = st.ctr[n].t;
+    __syncthreads();
+
+    if (L.lane_words == 2 && d.G4 >= 2)
+        fast_dispatch<2>(L, d, tile, t, t0);
+    else
+        fast_dispatch<1>(L, d, tile, t, t0);
+
+    switch (d.D) {
+    case 1: fast_energy<1>(st, d, tile, t); break;
+    case 2: fast_energy<2>(st, d, tile, t); break;
+    case 3: fast_energy<3>(st, d, tile, t); break;
+    case 4: fast_energy<4>(st, d, tile, t); break;
+    case 5: fast_energy<5>(st, d, tile, t); break;
+    case 6: fast_energy<6>(st, d, tile, t); break;
+    case 7: fast_energy<7>(st, d, tile, t); break;
+    case 8: fast_energy<8>(st, d, tile, t); break;
+    default: fast_energy<0>(st, d, tile, t); break;
     }
     write_back(st, d, tile, t);
 }
