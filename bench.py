@@ -22,6 +22,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -105,11 +106,21 @@ def cpu_baseline(insts, seed, k, budget_s=2.0, max_threads=16):
     for th in pool:
         th.join()
     dt = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": sum(flips) / dt, "unit": "spin-flip attempts/s", "cores": threads,
             "kind": "oracle",
             "sample": f"instances 0..{threads - 1} of the workload, one per host thread, whole "
                       f"cycles of {k} sweeps + exchange for about {budget_s:.0f} s each; "
-                      f"{sum(flips):.3e} attempts in {dt:.1f} s wall"}
+                      f"{sum(flips):.3e} attempts in {dt:.1f} s wall; host {model}, "
+                      f"{ncpu} CPUs available"}
 
 
 def traffic_per_launch():
@@ -177,14 +188,23 @@ def main():
     s.sync()
     s.timing_reset()
     torch.cuda.synchronize()
+    # the K steps run as five equal segments, each closed by a synchronisation, so the
+    # spread of the rate is visible; the reported value is all K steps over the whole time
+    n_seg = 5 if steps >= 5 else 1
+    bounds = [steps * j // n_seg for j in range(n_seg + 1)]
+    seg_s = []
     t0 = time.perf_counter()
-    s.run(steps)
-    s.sync()
+    for j in range(n_seg):
+        ts = time.perf_counter()
+        s.run(bounds[j + 1] - bounds[j])
+        s.sync()
+        seg_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     info = s.info()
     flips_per_step = k * int(info["flips_per_sweep"])
     value = steps * flips_per_step / elapsed
+    seg_rates = [(bounds[j + 1] - bounds[j]) * flips_per_step / seg_s[j] for j in range(n_seg)]
     # One sweep call (k sweeps of every replica) is timed with HIP events on the
     # library's stream.  It runs as one launch per occupancy class of whole-replica
     # tiles, or as two launches per sweep when replicas are split into slice blocks; the
@@ -222,6 +242,10 @@ def main():
                    "exchange_kernel_ms": info["exchange_ms"] / max(1, info["exchange_launches"]),
                    "sweep_kernel_flips_per_s": flips_per_step / avg_sweep_s if avg_sweep_s else None,
                    "sweep_launches_per_step": launches_per_call,
+                   "segment_rates": {"segments": n_seg,
+                                     "mean": statistics.mean(seg_rates),
+                                     "std": statistics.pstdev(seg_rates),
+                                     "median": statistics.median(seg_rates)},
                    "mean_launch_ms": launch_s * 1e3, "ops_per_launch": ops_launch},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak,

@@ -777,15 +777,65 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
 
     // stage: both planes of the block (+ halos), rows, biases, colour lists, rung tables
     const int slots = ng + 1;
-    for (Walk3 wk(tid, nt, slots, N); wk.z < 2 * P; wk.step()) {  // (slot, site, q * 2 + plane)
-        const int s = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
-        const int grp = block_slot_group(pl, s, g0, ng, G4);
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(
-            st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
-            (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh + 4 * grp);
-        reinterpret_cast<uint32_t *>(t.sp)[(wk.z * N + i) * slots + s] = *src;
+    uint32_t *sp32 = reinterpret_cast<uint32_t *>(t.sp);
+    if ((ng & 3) == 0) {
+        // interior groups of a row are 16-byte aligned and contiguous in device memory:
+        // 16-byte loads, four row pieces per thread in flight before the LDS stores
+        const int nv = ng >> 2;
+        for (Walk3 wk(tid, nt, nv + 1, N); wk.z < 2 * P;) {  // (piece, site, q * 2 + plane)
+            uint4 val[4];
+            int dst[4], kind[4];  // kind: 0 none, 1 four interior words, 2 halo word
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                kind[u] = 0;
+                if (wk.z < 2 * P) {
+                    const int v = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
+                    const uint8_t *row = st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
+                                         (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh;
+                    const int lrow = (wk.z * N + i) * slots;
+                    if (v < nv) {
+                        val[u] = *reinterpret_cast<const uint4 *>(row + 4 * (g0 + 4 * v));
+                        dst[u] = lrow + 4 * v + pl;  // plane 1 holds its halo in slot 0
+                        kind[u] = 1;
+                    } else {
+                        const int grp = block_slot_group(pl, pl == 0 ? ng : 0, g0, ng, G4);
+                        val[u].x = *reinterpret_cast<const uint32_t *>(row + 4 * grp);
+                        dst[u] = lrow + (pl == 0 ? ng : 0);
+                        kind[u] = 2;
+                    }
+                    wk.step();
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (kind[u] == 0) continue;
+                sp32[dst[u]] = val[u].x;
+                if (kind[u] == 1) {
+                    sp32[dst[u] + 1] = val[u].y;
+                    sp32[dst[u] + 2] = val[u].z;
+                    sp32[dst[u] + 3] = val[u].w;
+                }
+            }
+        }
+    } else {
+        for (Walk3 wk(tid, nt, slots, N); wk.z < 2 * P; wk.step()) {  // (slot, site, q * 2 + plane)
+            const int s = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
+            const int grp = block_slot_group(pl, s, g0, ng, G4);
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(
+                st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
+                (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh + 4 * grp);
+            sp32[(wk.z * N + i) * slots + s] = *src;
+        }
     }
-    for (int e = tid; e < N * d.D; e += nt) t.ent[e] = st.ent[d.ent_base + e];
+    for (int base = tid; base < N * d.D; base += 4 * nt) {  // neighbour rows, 4 loads in flight
+        uint32_t e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (base + u * nt < N * d.D) e[u] = st.ent[d.ent_base + base + u * nt];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (base + u * nt < N * d.D) t.ent[base + u * nt] = e[u];
+    }
     for (int i = tid; i < N; i += nt) t.bias[i] = st.bias[d.site_base + i];
     for (int i = tid; i < N; i += nt) t.csite[i] = st.csite[d.site_base + i];
     for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
@@ -854,14 +904,24 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
         }
     }
 
-    // write back the phase's own groups
+    // write back the phase's own groups (16-byte stores when the block has whole vectors)
     const int p = L.phase;
-    for (Walk3 wk(tid, nt, ng, N); wk.z < P; wk.step()) {  // (group, site, replica)
-        const int lg = wk.x, i = wk.y, q = wk.z;
-        const uint32_t v = lds32(t.sp, (uint32_t)q * 2u * N * 4u * slots + (uint32_t)p * N * 4u * slots +
-                                           (uint32_t)i * 4u * slots + 4u * (uint32_t)(lg + p));
-        *reinterpret_cast<uint32_t *>(st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
-                                      (int64_t)p * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + lg)) = v;
+    if ((ng & 3) == 0) {
+        for (Walk3 wk(tid, nt, ng >> 2, N); wk.z < P; wk.step()) {  // (vector, site, replica)
+            const int v = wk.x, i = wk.y, q = wk.z;
+            const int w = ((q * 2 + p) * N + i) * slots + 4 * v + p;
+            const uint4 val = make_uint4(sp32[w], sp32[w + 1], sp32[w + 2], sp32[w + 3]);
+            *reinterpret_cast<uint4 *>(st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
+                                       (int64_t)p * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + 4 * v)) = val;
+        }
+    } else {
+        for (Walk3 wk(tid, nt, ng, N); wk.z < P; wk.step()) {  // (group, site, replica)
+            const int lg = wk.x, i = wk.y, q = wk.z;
+            const uint32_t v = lds32(t.sp, (uint32_t)q * 2u * N * 4u * slots + (uint32_t)p * N * 4u * slots +
+                                               (uint32_t)i * 4u * slots + 4u * (uint32_t)(lg + p));
+            *reinterpret_cast<uint32_t *>(st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
+                                          (int64_t)p * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + lg)) = v;
+        }
     }
 }
 
