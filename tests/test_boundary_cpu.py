@@ -129,3 +129,21 @@ def test_network_entry_points_reject_bad_arguments():
     assert rc == ptqmc.PT_EINVAL and "loss kind" in L.pt_last_error().decode()
     rc = L.pt_mlp_adam(one, one, one, one, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None)
     assert rc == ptqmc.PT_EINVAL and "step" in L.pt_last_error().decode()
+
+
+def test_empty_batch_and_size_limits_rejected():
+    """An empty batch, and instances past the ABI's size limits, are refused before any
+    device work, with the reason."""
+    ptqmc = _lib()
+    L = ptqmc.lib()
+    opt = ptqmc._Options(1, 1, 0, 0, 0, 0, 0)
+    nb = C.c_size_t(0)
+    rc = L.pt_workspace_bytes(None, 0, C.byref(opt), C.byref(nb))
+    assert rc == ptqmc.PT_EINVAL and "at least one instance" in L.pt_last_error().decode()
+    rng = np.random.default_rng(9)
+    big_m = W.random_small_instance(rng, 3, 4096, 2, d=2)
+    rc, nbytes, _ = _ws_bytes([big_m], ptqmc)
+    assert rc == 0 and nbytes >= 2 * 3 * 4096          # M = 4096 is the largest accepted
+    too_m = W.random_small_instance(rng, 3, 4098, 2, d=2)
+    rc, _, msg = _ws_bytes([too_m], ptqmc)
+    assert rc == ptqmc.PT_EINVAL and "M must be <= 4096" in msg

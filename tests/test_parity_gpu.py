@@ -309,3 +309,33 @@ def test_config4_lattice_one_cycle(ptqmc):
         ref = oracle.OracleChain(inst, seed)
         ref.run(10, 1)
         assert_same(s, 0, ref, "config4")
+
+
+def test_maximum_sizes(ptqmc):
+    """The largest slice count (M = 4096), a large whole-replica tile (N = 4095 at M = 8,
+    about 90 KiB of LDS) and a replica whose rows need offsets beyond 16 bits (N = 4096,
+    M = 64, run as slice blocks) reproduce the oracle."""
+    rng = np.random.default_rng([1004, 25])
+    insts = [W.random_small_instance(rng, 3, 4096, 2, d=2, name="m4096"),
+             W.random_small_instance(rng, 4095, 8, 2, d=2, name="n4095"),
+             W.random_small_instance(rng, 4096, 64, 2, d=3, name="wide_rows")]
+    seed = 0x3A5
+    k, cycles = 2, 3
+    say("case: maximum sizes (M=4096; N=4095 at M=8; N=4096 at M=64 in slice blocks)")
+    refs = oracle_batch(insts, seed, k, cycles)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k) as s:
+        s.run(cycles)
+        assert s.info()["block_tiles"] > 0
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], "max sizes")
+
+
+def test_replica_too_large_is_refused(ptqmc):
+    """A replica that no kernel can hold in one workgroup's LDS is refused at pt_init with
+    the reason, and nothing is left allocated."""
+    rng = np.random.default_rng([1004, 26])
+    inst = W.random_small_instance(rng, 65535, 2, 2, d=2, name="too_large")
+    say("case: N=65535, M=2 replica refused")
+    with pytest.raises(ptqmc.PTError) as ei:
+        ptqmc.Sampler([inst], 1, sweeps_per_exchange=1)
+    assert ei.value.code == ptqmc.PT_EINVAL and "does not fit" in str(ei.value)

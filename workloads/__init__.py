@@ -154,23 +154,29 @@ def greedy_colouring(n: int, edges: np.ndarray) -> np.ndarray:
     """Deterministic proper colouring by DSatur (Brelaz): repeatedly colour the uncoloured
     vertex with the most distinct neighbour colours (ties: higher degree, then lower
     label) with the smallest free colour.  Fewer colours mean fewer update classes per
-    sweep.  Returns uint8 [n]."""
+    sweep.  The next vertex comes from a max-heap on that key with stale entries skipped,
+    O((n + edges) log n).  Returns uint8 [n]."""
+    import heapq
     adj = [[] for _ in range(n)]
     for a, b in edges:
         adj[int(a)].append(int(b))
         adj[int(b)].append(int(a))
     col = np.full(n, -1, dtype=np.int64)
     sat = [set() for _ in range(n)]
-    uncoloured = set(range(n))
-    while uncoloured:
-        v = max(uncoloured, key=lambda u: (len(sat[u]), len(adj[u]), -u))
+    heap = [(0, -len(adj[u]), u) for u in range(n)]
+    heapq.heapify(heap)
+    while heap:
+        neg_sat, _, v = heapq.heappop(heap)
+        if col[v] >= 0 or -neg_sat != len(sat[v]):
+            continue  # coloured already, or an entry from before v's saturation grew
         c = 0
         while c in sat[v]:
             c += 1
         col[v] = c
-        uncoloured.discard(v)
         for u in adj[v]:
-            sat[u].add(c)
+            if col[u] < 0 and c not in sat[u]:
+                sat[u].add(c)
+                heapq.heappush(heap, (-len(sat[u]), -len(adj[u]), u))
     if n and col.max() > 255:
         raise ValueError("more than 256 colours")
     return col.astype(np.uint8)
