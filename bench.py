@@ -207,14 +207,14 @@ def main():
     seg_rates = [(bounds[j + 1] - bounds[j]) * flips_per_step / seg_s[j] for j in range(n_seg)]
     # One sweep call (k sweeps of every replica) is timed with HIP events on the
     # library's stream.  It runs as one launch per occupancy class of whole-replica
-    # tiles, or as two launches per sweep when replicas are split into slice blocks; the
+    # tiles, or as one launch per sweep when replicas are split into slice blocks; the
     # roofline is quoted per launch of the dominant kernel, the call's algorithmic work
     # and event time divided by its launch count, so the mean launch duration is the one
     # a kernel trace reports.
     avg_sweep_s = info["sweep_ms"] / max(1, info["sweep_launches"]) / 1e3
     blocked = info["block_tiles"] > 0
     kernel = "sweep_block_kernel" if blocked else "sweep_fast_kernel"
-    launches_per_call = 2 * k if blocked else max(1, info["sweep_groups"])
+    launches_per_call = k if blocked else max(1, info["sweep_groups"])
     ops_call = 0.0
     for inst in insts:
         ops_call += k * inst.flips_per_sweep * ops_per_flip(2.0 * inst.n_edges / inst.N)

@@ -67,7 +67,10 @@ extern "C" {
 
 /* spin encodings (the trajectory is identical under every encoding) */
 #define PT_INT8 0       /* one byte per spin                                                */
-#define PT_BITPACK32 1  /* 32 replicas per uint32 word: bit (c mod 32) of word c/32 at (k, i) */
+#define PT_BITPACK32 1  /* 32 replicas per uint32 word: bit (c mod 32) of word c/32 at (k, i);
+                           declared for the interface, not built: pt_init refuses it with
+                           PT_EINVAL (packing 32 replicas per word divides the independent
+                           work items by 32, which the GPU cannot spare at these sizes) */
 
 /* round-trip labels */
 #define PT_LABEL_NONE 0
@@ -80,8 +83,8 @@ extern "C" {
 #define PT_FLAG_INJECT_LAUNCH_OOR_ONCE 0x4u /* test hook: the first sweep launch is treated
                                              as out of resources, exercising the fallback */
 #define PT_FLAG_SLICE_BLOCKS 0x8u  /* split every replica that could use them into slice
-                                      blocks (one launch per parity phase), as replicas
-                                      too large for one workgroup's LDS always are      */
+                                      blocks (one launch per sweep), as replicas too
+                                      large for one workgroup's LDS always are          */
 #define PT_FLAG_FOUR_SLICE_LANES 0x10u /* fast path: one four-slice word per lane instead
                                           of two (same chain; a measurement and test hook) */
 
@@ -149,7 +152,7 @@ typedef struct {
     int64_t exchange_launches;
     int32_t sweep_groups;             /* launches of whole-replica tiles per sweep call:
                                          one per occupancy class of the tiles          */
-    int32_t block_tiles;              /* slice-block tiles (two launches per sweep)    */
+    int32_t block_tiles;              /* slice-block tiles (one launch per sweep)      */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

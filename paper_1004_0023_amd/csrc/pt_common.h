@@ -143,6 +143,9 @@ struct Tile {
     int32_t kind;  // TileKind: which sweep kernel runs it
     int32_t g0;    // slice-block tiles: first four-slice group of the block
     int32_t ng;    // slice-block tiles: groups in the block (a power of two)
+    int32_t hb;    // slice-block tiles: word offset of the block's boundary record
+    int32_t prev;  // slice-block tiles: tile index of the block before / after it in the
+    int32_t next;  //   same replica (cyclically; itself when one block covers the replica)
 };
 
 struct Counters {
@@ -168,6 +171,10 @@ struct DevState {
     const double *dK;         // per pair: K_r - K_{r+1}
     const Tile *tiles;
     const int32_t *rep_inst;  // global replica -> instance
+    // slice-block boundary records, two buffers of halo_words words: for each block, its
+    // first group of parity 0 and of parity 1 and its last group of parity 1 (N words each)
+    uint32_t *halo;
+    int64_t halo_words;
     // mutable state
     uint8_t *spins;
     int64_t *E;       // per replica slot

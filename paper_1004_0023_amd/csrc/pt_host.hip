@@ -59,10 +59,11 @@ struct Plan {
     std::vector<int32_t> n_adj;  // per instance
     int64_t total_reps = 0, total_pairs = 0, spin_bytes = 0;
     int64_t max_tiles = 0;  // tile slots: one per (replica, four-slice group) at most
+    int64_t halo_words = 0; // one buffer of slice-block boundary records, at most
     uint64_t flips_per_sweep = 0;
     // byte offsets in the workspace
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
-        o_repinst;
+        o_repinst, o_halo;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr;
@@ -128,7 +129,10 @@ void build_table(uint32_t *out, int F, int M, double b, double K)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
+// LDS of one gfx950 workgroup; instances whose whole replicas exceed it run as slice blocks
+constexpr int32_t kLdsPerWorkgroup = 163840;
+
+int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, Plan &P)
 {
     if (!inst || n_inst < 1) return fail(PT_EINVAL, "need at least one instance");
     P = Plan();
@@ -235,6 +239,14 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
         for (int c = 0; c < in.R; ++c) P.rep_inst.push_back(n);
         P.n_adj.push_back(2 * in.n_edges);
         P.max_tiles += (int64_t)in.R * std::max(1, d.G4);
+        if (d.fast) {
+            // boundary records for slice blocks: three N-word rows per block, at most one
+            // block per four-slice group, for every instance that may run as blocks
+            const int lgMh_n = 31 - __builtin_clz((unsigned)d.Mh);
+            const bool may_block = d.ent_sh != lgMh_n || (flags & PT_FLAG_SLICE_BLOCKS) ||
+                                   sweep_tile_lds_bytes(d, 2 * in.n_edges, 1) > kLdsPerWorkgroup;
+            if (may_block) P.halo_words += 3ll * in.N * in.R * std::max(1, d.G4);
+        }
         P.flips_per_sweep += (uint64_t)in.R * in.N * in.M;
         rep += in.R;
         pair += in.R - 1;
@@ -271,6 +283,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, Plan &P)
     P.o_dK = take(P.dK.size() * 8);
     P.o_tiles = take((size_t)P.max_tiles * sizeof(Tile));
     P.o_repinst = take((size_t)rep * 4);
+    P.o_halo = take((size_t)P.halo_words * 2 * 4);
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
     P.o_E = take((size_t)rep * 8);
@@ -387,8 +400,14 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
             if (block_tile_lds_bytes(d, 1, ng) > c->lds_limit)
                 return fail(PT_EINVAL, "instance " + std::to_string(n) +
                                            ": even one slice group does not fit in LDS");
-            for (int c0 = 0; c0 < d.R; ++c0)
-                for (int g0 = 0; g0 < d.G4; g0 += ng) block.push_back(Tile{n, c0, 1, kTileBlock, g0, ng});
+            for (int c0 = 0; c0 < d.R; ++c0) {
+                const int first = (int)block.size(), nb = d.G4 / ng;
+                for (int k = 0; k < nb; ++k) {
+                    // prev/next are indices within the block list here, made global below
+                    block.push_back(Tile{n, c0, 1, kTileBlock, k * ng, ng, 0,
+                                         first + (k + nb - 1) % nb, first + (k + 1) % nb});
+                }
+            }
             lds_b = std::max(lds_b, block_tile_lds_bytes(d, 1, ng));
             continue;
         }
@@ -427,6 +446,18 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
     std::stable_sort(generic.begin(), generic.end(), bigger);
     if ((int64_t)(fast.size() + generic.size() + block.size()) > P.max_tiles)
         return fail(PT_ESTATE, "internal: more tiles than reserved tile slots");
+    // slice blocks: global neighbour indices and boundary-record offsets
+    const int block0 = (int)(fast.size() + generic.size());
+    int64_t hb = 0;
+    for (Tile &t : block) {
+        t.prev += block0;
+        t.next += block0;
+        t.hb = (int32_t)hb;
+        hb += 3ll * P.desc[t.inst].N;
+    }
+    if (hb > P.halo_words || hb > 0x7fffffff)
+        return fail(PT_EINVAL, "slice blocks need more boundary records than were reserved "
+                               "(the device's LDS is smaller than the library assumes)");
     c->tiles = fast;
     c->tiles.insert(c->tiles.end(), generic.begin(), generic.end());
     c->tiles.insert(c->tiles.end(), block.begin(), block.end());
@@ -561,18 +592,18 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps)
                 e = launch_sweep(L, g.kind, c->stream);
                 if (e != hipSuccess) break;
             }
-            // slice blocks: one launch per parity phase of every sweep
+            // slice blocks: boundary records of the current state (and E_cl, C cleared),
+            // then one launch per sweep
             L.tile0 = c->n_fast_tiles + c->n_generic_tiles;
             L.n_tiles = c->n_block_tiles;
             L.lds_bytes = c->lds_block;
-            for (int sw = 0; sw < n_sweeps && e == hipSuccess && L.n_tiles > 0; ++sw)
-                for (int ph = 0; ph < 2 && e == hipSuccess; ++ph) {
-                    L.phase = ph;
-                    L.sweep_off = sw;
-                    L.first = (sw == 0 && ph == 0);
-                    L.last = (sw == n_sweeps - 1 && ph == 1);
-                    e = launch_sweep(L, kTileBlock, c->stream);
-                }
+            if (e == hipSuccess && L.n_tiles > 0) e = launch_block_prepare(L, c->stream);
+            for (int sw = 0; sw < n_sweeps && e == hipSuccess && L.n_tiles > 0; ++sw) {
+                L.sweep_off = sw;
+                L.first = (sw == 0);
+                L.last = (sw == n_sweeps - 1);
+                e = launch_sweep(L, kTileBlock, c->stream);
+            }
         }
         if (e == hipSuccess) {
             if (timing) {
@@ -676,7 +707,7 @@ int pt_workspace_bytes(const pt_instance *inst, int32_t n_inst, const pt_options
 {
     if (!bytes || !opt) return fail(PT_EINVAL, "null argument");
     Plan P;
-    int rc = make_plan(inst, n_inst, P);
+    int rc = make_plan(inst, n_inst, opt->flags, P);
     if (rc) return rc;
     *bytes = P.total_bytes;
     return PT_OK;
@@ -698,7 +729,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
         return fail(PT_EINVAL, "tile_replicas and tile_bytes must be >= 0");
     pt_ctx *c = new (std::nothrow) pt_ctx();
     if (!c) return fail(PT_ENOMEM, "host allocation failed");
-    int rc = make_plan(inst, n_inst, c->plan);
+    int rc = make_plan(inst, n_inst, opt->flags, c->plan);
     if (rc) {
         delete c;
         return rc;
@@ -779,6 +810,8 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.att = (uint64_t *)(w + P.o_att);
     st.ctr = (Counters *)(w + P.o_ctr);
     st.rep_inst = (const int32_t *)(w + P.o_repinst);
+    st.halo = (uint32_t *)(w + P.o_halo);
+    st.halo_words = P.halo_words;
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;

@@ -13,10 +13,9 @@ struct SweepLaunch {
     int32_t n_tiles;
     int32_t block_threads;
     int32_t lds_bytes;
-    // slice-block tiles: one parity phase of sweep t + sweep_off per launch
-    int32_t phase;
+    // slice-block tiles: sweep t + sweep_off per launch
     int32_t sweep_off;
-    int32_t first;         // first launch of a pt_sweep call: clear E_cl, C
+    int32_t first;         // first launch of a pt_sweep call
     int32_t last;          // last launch: accumulate E_cl, C
     int32_t lane_words;    // fast tiles: four-slice words per lane (2 needs G4 >= 2)
 };
@@ -27,6 +26,9 @@ hipError_t launch_init_spins(const DevState &st, int32_t n_reps, uint32_t key0, 
                              hipStream_t s);
 hipError_t launch_energy(const DevState &st, int32_t rep_first, int32_t n_reps, hipStream_t s);
 hipError_t launch_sweep(const SweepLaunch &L, int kind, hipStream_t s);
+// Before the slice-block launches of a call: boundary records of the current spins into
+// buffer (t mod 2), E_cl and C of the blocked replicas cleared.
+hipError_t launch_block_prepare(const SweepLaunch &L, hipStream_t s);
 hipError_t launch_exchange(const DevState &st, int32_t n_inst, uint32_t key0, uint32_t key1,
                            uint32_t t_add, hipStream_t s);
 hipError_t launch_advance(const DevState &st, int32_t n_inst, uint32_t t_add, hipStream_t s);

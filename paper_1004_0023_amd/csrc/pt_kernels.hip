@@ -2,17 +2,20 @@
 //
 //   init_spins     initial spins from INIT-domain Philox words
 //   energy         E_cl and C of replicas from their spins in device memory
-//   sweep_fast     n Metropolis sweeps of a tile of replicas held in LDS: one lane per
-//                  (site, four same-parity slices), byte-SWAR local fields (v_perm per
-//                  neighbour), one Philox call per lane and class; then E_cl and C
-//   sweep_generic  the same chain for any shape (odd slice groups, M = 1, large fields),
-//                  one byte at a time
+//   sweep_fast     n Metropolis sweeps of a tile of whole replicas held in LDS: one lane
+//                  per (site, two words of four same-parity slices), byte-SWAR local
+//                  fields (v_perm per neighbour), one Philox call per word and class;
+//                  then E_cl and C from the byte field with v_dot4
+//   sweep_block    one parity phase of one sweep of slice blocks of replicas too large
+//                  for one workgroup's LDS (or whose rows need offsets beyond 16 bits)
+//   sweep_generic  the same chain for any other shape (slice groups that are not a power
+//                  of two, M = 1, large fields), one byte at a time
 //   exchange       one even/odd replica-exchange step per instance (one workgroup each)
 //   advance        t += n
 //
-// Both sweep kernels visit colour classes (slice parity p, spatial colour g) in order;
-// a class is an independent set, so its sites are updated in parallel and the result
-// is independent of the launch shape.
+// The sweep kernels visit colour classes (slice parity p, spatial colour g) in order; a
+// class is an independent set, so its sites are updated in parallel and the result is
+// independent of the launch shape.
 #include "pt_internal.h"
 
 #pragma clang fp contract(off)
@@ -605,14 +608,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 
 // ------------------------------------------------------------------ slice-block sweep
 //
-// A replica too large for one workgroup's LDS is split into blocks of ng four-slice
-// groups (both parities).  One launch runs one parity phase p of one sweep for every
-// block.  Parity-p attempts read only the other parity in time, which no block changes
-// during phase p, so each block needs one halo group of the other parity: the group
-// before its range in parity 1 (read in phase 0) and the group after it in parity 0
-// (read in phase 1).  LDS rows, per replica and parity plane, hold ng + 1 words:
-//   plane 0: slots 0..ng-1 = groups g0..g0+ng-1, slot ng = group g0+ng (mod G4)
-//   plane 1: slot 0 = group g0-1 (mod G4), slots 1..ng = groups g0..g0+ng-1
+// A replica too large for one workgroup's LDS (or whose rows need offsets beyond 16 bits)
+// is split into blocks of ng four-slice groups of both parities.  One launch runs one whole
+// sweep of every block.  Parity-0 attempts read only parity 1 in time and parity-1 attempts
+// only parity 0, so a sweep of groups [g0, g0+ng) needs:
+//   phase 0 over groups [g0, g0+ng], one group more than the block owns: that extra group
+//     is the next block's first group, recomputed here from the same draws and the same
+//     pre-sweep values, hence bit-identical to what that block computes;
+//   phase 1 over [g0, g0+ng), whose time neighbours are parity-0 groups [g0, g0+ng].
+// The halos (parity-1 groups g0-1 and g0+ng, parity-0 group g0+ng) belong to the
+// neighbouring blocks, which write their groups back during the same launch, so they are
+// read from boundary records instead: at the end of sweep t each block records its first
+// group of both parities and its last group of parity 1 in buffer (t+1) mod 2, and sweep t
+// reads its neighbours' records from buffer t mod 2 (filled from the spins before the
+// first sweep of a call).  Slot s of a row stands for group g0 - 1 + s (mod G4); a block
+// owns slots 1..ng.  Parity-1 rows hold slots 0..ng+1 (ng + 2 words); parity-0 rows hold
+// slots 1..ng+1 (ng + 1 words), slot 0 of parity 0 being never read.
 
 // A thread's position (x, y, z) in a linear walk over [z][y][x] (x < nx, y < ny) that
 // advances by a fixed stride per step, with carries instead of divisions.
@@ -647,7 +658,7 @@ struct Walk3 {
 };
 
 struct BlockLds {
-    uint8_t *sp;       // P replicas x 2 planes x N rows x (ng + 1) words
+    uint8_t *sp;       // P replicas x (N rows of ng + 1 words, N rows of ng + 2 words)
     uint32_t *ent;     // N * D entries
     uint32_t *bias;    // N
     uint16_t *csite;   // N
@@ -660,7 +671,7 @@ __host__ __device__ __forceinline__ int64_t block_offsets(const InstDesc &d, int
                                                           int64_t o[7])
 {
     int64_t x = 0;
-    o[0] = x; x = a16(x + (int64_t)P * 2 * d.N * (ng + 1) * 4);
+    o[0] = x; x = a16(x + (int64_t)P * d.N * (2 * ng + 3) * 4);
     o[1] = x; x = a16(x + (int64_t)d.N * d.D * 4);
     o[2] = x; x = a16(x + (int64_t)d.N * 4);
     o[3] = x; x = a16(x + (int64_t)d.N * 2);
@@ -670,61 +681,68 @@ __host__ __device__ __forceinline__ int64_t block_offsets(const InstDesc &d, int
     return x;
 }
 
-// Global four-slice group held by LDS slot s of plane pl in a block starting at g0.
-__device__ __forceinline__ int block_slot_group(int pl, int s, int g0, int ng, int G4)
+// Global four-slice group held by LDS slot s of a block starting at g0.
+__device__ __forceinline__ int block_slot_group(int s, int g0, int G4)
 {
-    const int g = (pl == 0) ? g0 + s : g0 + s - 1;
-    return (g + G4) & (G4 - 1);
+    return (g0 - 1 + s + G4) & (G4 - 1);
 }
 
-template <int DT>
-__device__ __forceinline__ void block_item(const SweepLaunch &L, const InstDesc &d,
-                                           const BlockLds &t, int n, uint32_t tt, uint32_t c0,
-                                           int p, int i, int q, int lg, int g0, int ng)
+// Per-launch constants of a block tile.
+struct BlockArgs {
+    uint32_t key0, key1, tt, n, c0;
+    uint32_t RS[2];       // bytes of one LDS row of parity 0 (ng + 1 words) and 1 (ng + 2)
+    uint32_t base[2];     // start of each parity's rows within a replica
+    uint32_t QS;          // bytes of one replica
+    uint32_t sel_x;       // v_perm selector: x -> x * (2F + 1)
+    int G4, g0, esh, tbl_words;
+};
+
+// LDS byte offset of slot s of site i's row of parity p in replica q.
+__device__ __forceinline__ uint32_t block_at(const BlockArgs &a, int p, int q, int i, int s)
 {
-    const int D = (DT > 0) ? DT : d.D;
-    const uint32_t RS = 4u * (uint32_t)(ng + 1);             // row stride, bytes
-    const uint32_t PL = (uint32_t)d.N * RS;                  // plane stride
-    const uint32_t qbase = (uint32_t)q * 2u * PL;
-    const uint32_t own_slot = (uint32_t)(lg + p) * 4u;       // plane 1 is shifted by one slot
-    const uint32_t nb_base = qbase + (uint32_t)p * PL + own_slot;
-    const uint32_t own = nb_base + (uint32_t)i * RS;
-    const uint32_t oth_row = qbase + (uint32_t)(p ^ 1) * PL + (uint32_t)i * RS;
+    return (uint32_t)q * a.QS + a.base[p] + __umul24((uint32_t)i, a.RS[p]) + 4u * (uint32_t)(s - 1 + p);
+}
+
+// One lane's update of site i, replica q, the group in slot s of parity PAR: four
+// Metropolis attempts served by one Philox call.
+template <int DT, int PAR>
+__device__ __forceinline__ void block_item(const BlockArgs &a, const BlockLds &t, int D, int i,
+                                           int q, int s)
+{
+    const uint32_t nb_base = block_at(a, PAR, q, 0, s);
+    const uint32_t own = nb_base + __umul24((uint32_t)i, a.RS[PAR]);
+    const uint32_t oth = block_at(a, PAR ^ 1, q, i, s);
     const uint32_t X = lds32(t.sp, own);
+    const uint32_t Wc = lds32(t.sp, oth);
     uint32_t T;
-    if (p == 0) {
-        const uint32_t Wc = lds32(t.sp, oth_row + 4u * (uint32_t)(lg + 1));
-        const uint32_t Wp = lds32(t.sp, oth_row + 4u * (uint32_t)lg);
-        T = __builtin_amdgcn_alignbyte(Wc, Wp, 3) + Wc;
-    } else {
-        const uint32_t Wc = lds32(t.sp, oth_row + 4u * (uint32_t)lg);
-        const uint32_t Wn = lds32(t.sp, oth_row + 4u * (uint32_t)(lg + 1));
-        T = __builtin_amdgcn_alignbyte(Wn, Wc, 1) + Wc;
-    }
-    // the entry holds j << ent_sh; a block row is RS bytes
-    const int esh = d.ent_sh;
+    if constexpr (PAR == 0)
+        T = __builtin_amdgcn_alignbyte(Wc, lds32(t.sp, oth - 4u), 3) + Wc;
+    else
+        T = __builtin_amdgcn_alignbyte(lds32(t.sp, oth + 4u), Wc, 1) + Wc;
+    // the entry holds j << esh in its top half; a block row is RS bytes
     const uint32_t *er = t.ent + i * D;
+    const int shift = 16 + a.esh;
     uint32_t acc = 0;
-    if (DT > 0) {
-        uint32_t ents[DT > 0 ? DT : 1], ws[DT > 0 ? DT : 1];
+    if constexpr (DT > 0) {
+        uint32_t ents[DT], ws[DT];
 #pragma unroll
         for (int e = 0; e < DT; ++e) ents[e] = er[e];
 #pragma unroll
-        for (int e = 0; e < DT; ++e) ws[e] = lds32(t.sp, nb_base + ((ents[e] >> 16) >> esh) * RS);
+        for (int e = 0; e < DT; ++e) ws[e] = lds32(t.sp, nb_base + __umul24(ents[e] >> shift, a.RS[PAR]));
 #pragma unroll
         for (int e = 0; e < DT; ++e) acc += __builtin_amdgcn_perm(0u, ents[e], ws[e]);
     } else {
         for (int e = 0; e < D; ++e) {
             const uint32_t ent = er[e];
-            acc += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, nb_base + ((ent >> 16) >> esh) * RS));
+            acc += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, nb_base + __umul24(ent >> shift, a.RS[PAR])));
         }
     }
-    const Words4 u = philox10(spin_ctr0(i, p, d.G4, g0 + lg), tt, c0 + (uint32_t)q, (uint32_t)n,
-                              L.key0, L.key1);
-    const uint32_t sel_x = (uint32_t)(2 * d.F + 1) << 8;
-    const uint32_t V = __builtin_amdgcn_perm(0u, sel_x, X) + (acc << 1) + t.bias[i];
+    const int g = block_slot_group(s, a.g0, a.G4);
+    const Words4 u = philox10((uint32_t)(2 * i + PAR) * (uint32_t)a.G4 + (uint32_t)g, a.tt,
+                              a.c0 + (uint32_t)q, a.n, a.key0, a.key1);
+    const uint32_t V = __builtin_amdgcn_perm(0u, a.sel_x, X) + (acc << 1) + t.bias[i];
     const uint32_t IDX = V + (V << 1) + T;
-    const uint32_t *tb = t.tbl + q * d.tbl_words;
+    const uint32_t *tb = t.tbl + q * a.tbl_words;
     uint32_t flip = 0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -734,25 +752,72 @@ __device__ __forceinline__ void block_item(const SweepLaunch &L, const InstDesc 
     *reinterpret_cast<uint32_t *>(t.sp + own) = X ^ flip;
 }
 
-template <int DT>
-__device__ __forceinline__ void block_phase(const SweepLaunch &L, const InstDesc &d,
-                                            const Tile &tile, const BlockLds &t, uint32_t tt)
+// All colour classes of parity PAR over slots 1..ns (phase 0: ns = ng + 1; phase 1: ng).
+// Each thread keeps one (replica, slot) pair and strides over the sites of a class.
+template <int DT, int PAR>
+__device__ __forceinline__ void block_phase(const BlockArgs &a, const InstDesc &d, const Tile &tile,
+                                            const BlockLds &t, int ns)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int lgng = ilog2(tile.ng);
-    const int lgL = ilog2(tile.P) + lgng;
-    const int Lmask = (1 << lgL) - 1;
-    const int p = L.phase;
-    for (int g = 0; g < d.n_colors; ++g) {
-        const int s0 = t.coff[g];
-        const int items = (t.coff[g + 1] - s0) << lgL;
-        for (int it = tid; it < items; it += nt) {
-            const int r = it & Lmask;
-            block_item<DT>(L, d, t, tile.inst, tt, (uint32_t)tile.c0, p, t.csite[s0 + (it >> lgL)],
-                           r >> lgng, r & (tile.ng - 1), tile.g0, tile.ng);
+    const int D = (DT > 0) ? DT : d.D;
+    const int lanes = tile.P * ns;  // per site
+    if (lanes <= nt) {
+        const int r = tid % lanes;
+        const int q = r / ns, sl = 1 + r - q * ns;
+        const int sstep = nt / lanes;
+        const int s_first = (tid < sstep * lanes) ? tid / lanes : (1 << 30);
+        for (int g = 0; g < d.n_colors; ++g) {
+            const int s1 = t.coff[g + 1];
+            for (int si = t.coff[g] + s_first; si < s1; si += sstep)
+                block_item<DT, PAR>(a, t, D, t.csite[si], q, sl);
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        for (int g = 0; g < d.n_colors; ++g) {
+            const int s0 = t.coff[g];
+            const int items = (t.coff[g + 1] - s0) * lanes;
+            for (int it = tid; it < items; it += nt) {
+                const int si = it / lanes, r = it - si * lanes;
+                const int q = r / ns;
+                block_item<DT, PAR>(a, t, D, t.csite[s0 + si], q, 1 + r - q * ns);
+            }
+            __syncthreads();
+        }
     }
+}
+
+template <int DT>
+__device__ __forceinline__ void block_sweep(const BlockArgs &a, const InstDesc &d, const Tile &tile,
+                                            const BlockLds &t)
+{
+    block_phase<DT, 0>(a, d, tile, t, tile.ng + 1);
+    block_phase<DT, 1>(a, d, tile, t, tile.ng);
+}
+
+// Before the first slice-block launch of a call: every block's boundary record of the
+// current spins into buffer (t mod 2), and E_cl, C of its replica cleared by the block at
+// g0 = 0 (the blocks add their partial sums on the call's last launch).  One workgroup per
+// block.
+__global__ void block_prepare_kernel(SweepLaunch L)
+{
+    const DevState &st = L.st;
+    const Tile tile = st.tiles[L.tile0 + blockIdx.x];
+    const InstDesc d = st.inst[tile.inst];
+    const int N = d.N, ng = tile.ng, g0 = tile.g0;
+    uint32_t *rec = st.halo + (int64_t)(st.ctr[tile.inst].t & 1) * st.halo_words + tile.hb;
+    const uint8_t *rep = st.spins + d.spin_base + (int64_t)tile.c0 * d.rep_bytes;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const uint8_t *r0 = rep + (int64_t)i * d.Mh;
+        const uint8_t *r1 = rep + (int64_t)N * d.Mh + (int64_t)i * d.Mh;
+        rec[i] = *reinterpret_cast<const uint32_t *>(r0 + 4 * g0);
+        rec[N + i] = *reinterpret_cast<const uint32_t *>(r1 + 4 * g0);
+        rec[2 * N + i] = *reinterpret_cast<const uint32_t *>(r1 + 4 * (g0 + ng - 1));
+    }
+    if (g0 == 0 && threadIdx.x == 0)
+        for (int q = 0; q < tile.P; ++q) {
+            st.E[d.rep_base + tile.c0 + q] = 0;
+            st.C[d.rep_base + tile.c0 + q] = 0;
+        }
 }
 
 __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
@@ -775,56 +840,75 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
     t.tbl = reinterpret_cast<uint32_t *>(lds + o[5]);
     t.red = reinterpret_cast<long long *>(lds + o[6]);
 
-    // stage: both planes of the block (+ halos), rows, biases, colour lists, rung tables
-    const int slots = ng + 1;
+    // stage: the owned groups of both planes from the spins, the halos from the neighbours'
+    // boundary records, then rows, biases, colour lists and rung tables
     uint32_t *sp32 = reinterpret_cast<uint32_t *>(t.sp);
+    const uint64_t tsw = st.ctr[n].t + (uint64_t)L.sweep_off;
+    BlockArgs a;
+    a.key0 = L.key0;
+    a.key1 = L.key1;
+    a.tt = (uint32_t)tsw;
+    a.n = (uint32_t)n;
+    a.c0 = (uint32_t)tile.c0;
+    a.RS[0] = 4u * (uint32_t)(ng + 1);
+    a.RS[1] = 4u * (uint32_t)(ng + 2);
+    a.base[0] = 0;
+    a.base[1] = (uint32_t)N * a.RS[0];
+    a.QS = (uint32_t)N * (a.RS[0] + a.RS[1]);
+    a.sel_x = (uint32_t)(2 * d.F + 1) << 8;
+    a.G4 = G4;
+    a.g0 = g0;
+    a.esh = d.ent_sh;
+    a.tbl_words = d.tbl_words;
+    const uint32_t *rec_in = st.halo + (int64_t)(tsw & 1) * st.halo_words;
     if ((ng & 3) == 0) {
-        // interior groups of a row are 16-byte aligned and contiguous in device memory:
+        // the owned groups of a row are 16-byte aligned and contiguous in device memory:
         // 16-byte loads, four row pieces per thread in flight before the LDS stores
         const int nv = ng >> 2;
-        for (Walk3 wk(tid, nt, nv + 1, N); wk.z < 2 * P;) {  // (piece, site, q * 2 + plane)
+        for (Walk3 wk(tid, nt, nv, N); wk.z < 2 * P;) {  // (vector, site, q * 2 + plane)
             uint4 val[4];
-            int dst[4], kind[4];  // kind: 0 none, 1 four interior words, 2 halo word
+            int dst[4];
+            bool ok[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                kind[u] = 0;
-                if (wk.z < 2 * P) {
+                ok[u] = wk.z < 2 * P;
+                if (ok[u]) {
                     const int v = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
                     const uint8_t *row = st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
                                          (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh;
-                    const int lrow = (wk.z * N + i) * slots;
-                    if (v < nv) {
-                        val[u] = *reinterpret_cast<const uint4 *>(row + 4 * (g0 + 4 * v));
-                        dst[u] = lrow + 4 * v + pl;  // plane 1 holds its halo in slot 0
-                        kind[u] = 1;
-                    } else {
-                        const int grp = block_slot_group(pl, pl == 0 ? ng : 0, g0, ng, G4);
-                        val[u].x = *reinterpret_cast<const uint32_t *>(row + 4 * grp);
-                        dst[u] = lrow + (pl == 0 ? ng : 0);
-                        kind[u] = 2;
-                    }
+                    val[u] = *reinterpret_cast<const uint4 *>(row + 4 * (g0 + 4 * v));
+                    dst[u] = (int)(block_at(a, pl, q, i, 1 + 4 * v) >> 2);
                     wk.step();
                 }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                if (kind[u] == 0) continue;
+                if (!ok[u]) continue;
                 sp32[dst[u]] = val[u].x;
-                if (kind[u] == 1) {
-                    sp32[dst[u] + 1] = val[u].y;
-                    sp32[dst[u] + 2] = val[u].z;
-                    sp32[dst[u] + 3] = val[u].w;
-                }
+                sp32[dst[u] + 1] = val[u].y;
+                sp32[dst[u] + 2] = val[u].z;
+                sp32[dst[u] + 3] = val[u].w;
             }
         }
     } else {
-        for (Walk3 wk(tid, nt, slots, N); wk.z < 2 * P; wk.step()) {  // (slot, site, q * 2 + plane)
-            const int s = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
-            const int grp = block_slot_group(pl, s, g0, ng, G4);
-            const uint32_t *src = reinterpret_cast<const uint32_t *>(
+        for (Walk3 wk(tid, nt, ng, N); wk.z < 2 * P; wk.step()) {  // (group, site, q * 2 + plane)
+            const int lg = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
+            sp32[block_at(a, pl, q, i, 1 + lg) >> 2] = *reinterpret_cast<const uint32_t *>(
                 st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
-                (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh + 4 * grp);
-            sp32[(wk.z * N + i) * slots + s] = *src;
+                (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + lg));
+        }
+    }
+    {
+        // halos: parity 1 slot 0 <- previous block's last parity-1 group; parity 1 slot ng+1
+        // and parity 0 slot ng+1 <- next block's first groups (P = 1 for slice blocks)
+        const Tile tp = st.tiles[tile.prev], tn = st.tiles[tile.next];
+        for (int i = tid; i < N; i += nt) {
+            const uint32_t h1p = rec_in[tp.hb + 2 * N + i];
+            const uint32_t h0n = rec_in[tn.hb + i];
+            const uint32_t h1n = rec_in[tn.hb + N + i];
+            sp32[block_at(a, 1, 0, i, 0) >> 2] = h1p;
+            sp32[block_at(a, 1, 0, i, ng + 1) >> 2] = h1n;
+            sp32[block_at(a, 0, 0, i, ng + 1) >> 2] = h0n;
         }
     }
     for (int base = tid; base < N * d.D; base += 4 * nt) {  // neighbour rows, 4 loads in flight
@@ -840,39 +924,30 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
     for (int i = tid; i < N; i += nt) t.csite[i] = st.csite[d.site_base + i];
     for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
     stage_tables(st, d, tile.c0, P, t.tbl);
-    if (L.first && g0 == 0)
-        for (int q = tid; q < P; q += nt) {
-            st.E[d.rep_base + tile.c0 + q] = 0;
-            st.C[d.rep_base + tile.c0 + q] = 0;
-        }
-    const uint32_t tt = (uint32_t)(st.ctr[n].t + (uint64_t)L.sweep_off);
     __syncthreads();
 
     switch (d.D) {
-    case 1: block_phase<1>(L, d, tile, t, tt); break;
-    case 2: block_phase<2>(L, d, tile, t, tt); break;
-    case 3: block_phase<3>(L, d, tile, t, tt); break;
-    case 4: block_phase<4>(L, d, tile, t, tt); break;
-    case 5: block_phase<5>(L, d, tile, t, tt); break;
-    case 6: block_phase<6>(L, d, tile, t, tt); break;
-    case 7: block_phase<7>(L, d, tile, t, tt); break;
-    case 8: block_phase<8>(L, d, tile, t, tt); break;
-    default: block_phase<0>(L, d, tile, t, tt); break;
+    case 1: block_sweep<1>(a, d, tile, t); break;
+    case 2: block_sweep<2>(a, d, tile, t); break;
+    case 3: block_sweep<3>(a, d, tile, t); break;
+    case 4: block_sweep<4>(a, d, tile, t); break;
+    case 5: block_sweep<5>(a, d, tile, t); break;
+    case 6: block_sweep<6>(a, d, tile, t); break;
+    case 7: block_sweep<7>(a, d, tile, t); break;
+    case 8: block_sweep<8>(a, d, tile, t); break;
+    default: block_sweep<0>(a, d, tile, t); break;
     }
 
-    // partial E_cl and C of the block's slices after the last phase of the call
+    // partial E_cl and C of the block's owned slices after the last sweep of the call
     if (L.last) {
         const int D = d.D, F = d.F;
-        const uint32_t RS = 4u * (uint32_t)slots, PL = (uint32_t)N * RS;
         for (int q = 0; q < P; ++q) {
             long long ee = 0, cc = 0;
-            const uint32_t qbase = (uint32_t)q * 2u * PL;
-            for (int it = tid; it < N * ng; it += nt) {
-                const int i = it / ng;
-                const int lg = it - i * ng;
-                const uint32_t X0 = lds32(t.sp, qbase + (uint32_t)i * RS + 4u * lg);
-                const uint32_t X1 = lds32(t.sp, qbase + PL + (uint32_t)i * RS + 4u * (lg + 1));
-                const uint32_t X0n = lds32(t.sp, qbase + (uint32_t)i * RS + 4u * (lg + 1));
+            for (Walk3 wk(tid, nt, ng, N); wk.z < 1; wk.step()) {  // (owned group, site)
+                const int lg = wk.x, i = wk.y;
+                const uint32_t X0 = lds32(t.sp, block_at(a, 0, q, i, lg + 1));
+                const uint32_t X1 = lds32(t.sp, block_at(a, 1, q, i, lg + 1));
+                const uint32_t X0n = lds32(t.sp, block_at(a, 0, q, i, lg + 2));
                 const uint32_t dis_t = popc(X0 ^ X1) + popc(X1 ^ __builtin_amdgcn_alignbyte(X0n, X0, 1));
                 cc += 8 - 2 * (long long)dis_t;
                 const int hval = (int)(t.bias[i] & 0xFFu) - F;
@@ -883,10 +958,10 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
                     const int w0 = (int)(ent & 0xFFu), w1 = (int)((ent >> 8) & 0xFFu);
                     const int J = w1 - w0;
                     sumJ += w0 + w1;
-                    const uint32_t j = (ent >> 16) >> d.ent_sh;
-                    if (J != 0 && j > (uint32_t)i) {
-                        const uint32_t Y0 = lds32(t.sp, qbase + j * RS + 4u * lg);
-                        const uint32_t Y1 = lds32(t.sp, qbase + PL + j * RS + 4u * (lg + 1));
+                    const int j = (int)((ent >> 16) >> d.ent_sh);
+                    if (J != 0 && j > i) {
+                        const uint32_t Y0 = lds32(t.sp, block_at(a, 0, q, j, lg + 1));
+                        const uint32_t Y1 = lds32(t.sp, block_at(a, 1, q, j, lg + 1));
                         eterm += (long long)J * (8 - 2 * (long long)(popc(X0 ^ Y0) + popc(X1 ^ Y1)));
                     }
                 }
@@ -904,24 +979,29 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
         }
     }
 
-    // write back the phase's own groups (16-byte stores when the block has whole vectors)
-    const int p = L.phase;
+    // write back the owned groups of both parities (16-byte stores for whole vectors)
     if ((ng & 3) == 0) {
-        for (Walk3 wk(tid, nt, ng >> 2, N); wk.z < P; wk.step()) {  // (vector, site, replica)
-            const int v = wk.x, i = wk.y, q = wk.z;
-            const int w = ((q * 2 + p) * N + i) * slots + 4 * v + p;
+        for (Walk3 wk(tid, nt, ng >> 2, N); wk.z < 2 * P; wk.step()) {  // (vector, site, q * 2 + plane)
+            const int v = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
+            const int w = (int)(block_at(a, pl, q, i, 1 + 4 * v) >> 2);
             const uint4 val = make_uint4(sp32[w], sp32[w + 1], sp32[w + 2], sp32[w + 3]);
             *reinterpret_cast<uint4 *>(st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
-                                       (int64_t)p * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + 4 * v)) = val;
+                                       (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + 4 * v)) = val;
         }
     } else {
-        for (Walk3 wk(tid, nt, ng, N); wk.z < P; wk.step()) {  // (group, site, replica)
-            const int lg = wk.x, i = wk.y, q = wk.z;
-            const uint32_t v = lds32(t.sp, (uint32_t)q * 2u * N * 4u * slots + (uint32_t)p * N * 4u * slots +
-                                               (uint32_t)i * 4u * slots + 4u * (uint32_t)(lg + p));
+        for (Walk3 wk(tid, nt, ng, N); wk.z < 2 * P; wk.step()) {  // (group, site, q * 2 + plane)
+            const int lg = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
             *reinterpret_cast<uint32_t *>(st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
-                                          (int64_t)p * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + lg)) = v;
+                                          (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + lg)) =
+                sp32[block_at(a, pl, q, i, 1 + lg) >> 2];
         }
+    }
+    // boundary records for the next sweep: first group of both parities, last of parity 1
+    uint32_t *rec_out = st.halo + (int64_t)((tsw + 1) & 1) * st.halo_words + tile.hb;
+    for (int i = tid; i < N; i += nt) {
+        rec_out[i] = sp32[block_at(a, 0, 0, i, 1) >> 2];
+        rec_out[N + i] = sp32[block_at(a, 1, 0, i, 1) >> 2];
+        rec_out[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
     }
 }
 
@@ -1152,6 +1232,13 @@ hipError_t launch_sweep(const SweepLaunch &L, int kind, hipStream_t s)
         hipLaunchKernelGGL(sweep_block_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
     else
         hipLaunchKernelGGL(sweep_generic_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_prepare(const SweepLaunch &L, hipStream_t s)
+{
+    if (L.n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(block_prepare_kernel, dim3(L.n_tiles), dim3(256), 0, s, L);
     return hipGetLastError();
 }
 
