@@ -600,7 +600,6 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps)
             if (e == hipSuccess && L.n_tiles > 0) e = launch_block_prepare(L, c->stream);
             for (int sw = 0; sw < n_sweeps && e == hipSuccess && L.n_tiles > 0; ++sw) {
                 L.sweep_off = sw;
-                L.first = (sw == 0);
                 L.last = (sw == n_sweeps - 1);
                 e = launch_sweep(L, kTileBlock, c->stream);
             }

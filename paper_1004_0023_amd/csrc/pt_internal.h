@@ -15,8 +15,7 @@ struct SweepLaunch {
     int32_t lds_bytes;
     // slice-block tiles: sweep t + sweep_off per launch
     int32_t sweep_off;
-    int32_t first;         // first launch of a pt_sweep call
-    int32_t last;          // last launch: accumulate E_cl, C
+    int32_t last;          // last launch of a pt_sweep call: accumulate E_cl, C
     int32_t lane_words;    // fast tiles: four-slice words per lane (2 needs G4 >= 2)
 };
 
