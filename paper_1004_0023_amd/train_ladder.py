@@ -43,7 +43,7 @@ SEED0 = 0x10040023_00000000 + CONFIG_ID
 DATA = os.path.join(HERE, "data")
 SCAN_FILE = os.path.join(DATA, "ladder_scan.npz")
 MODEL_FILE = os.path.join(DATA, "ladder_mlp.npz")
-REPORT_FILE = os.path.join(ROOT, "profiles", "ladder_eval.json")
+REPORT_FILE = os.path.join(DATA, "ladder_eval.json")
 
 
 def log(msg):
