@@ -175,7 +175,11 @@ int pt_sweep(pt_ctx *ctx, int32_t n_sweeps);
 /* One replica-exchange step of every instance (e += 1). */
 int pt_exchange(pt_ctx *ctx);
 
-/* n_cycles x (sweeps_per_exchange sweeps, then one exchange step). */
+/* n_cycles x (sweeps_per_exchange sweeps, then one exchange step), the same chain as
+ * pt_sweep(k) + pt_exchange() per cycle (Figure 6's loop).  Cycles are replayed from a HIP
+ * graph; for batches of at most 64 tiles each cycle is a single set of launches in which
+ * the workgroup that finishes an instance's last tile runs that instance's exchange step
+ * (per-instance completion counts), larger batches launch the exchange separately. */
 int pt_run(pt_ctx *ctx, int32_t n_cycles);
 
 /* Wait for all work queued on the context's stream. */

@@ -175,6 +175,9 @@ struct DevState {
     // first group of parity 0 and of parity 1 and its last group of parity 1 (N words each)
     uint32_t *halo;
     int64_t halo_words;
+    // per instance: tiles of one sweep call, and tiles that finished the current call
+    const int32_t *itiles;
+    uint32_t *icount;
     // mutable state
     uint8_t *spins;
     int64_t *E;       // per replica slot

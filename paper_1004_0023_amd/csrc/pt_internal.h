@@ -16,6 +16,10 @@ struct SweepLaunch {
     // slice-block tiles: sweep t + sweep_off per launch
     int32_t sweep_off;
     int32_t last;          // last launch of a pt_sweep call: accumulate E_cl, C
+    // a PT cycle: the tile that completes an instance's sweeps runs its exchange step
+    int32_t fuse_exchange;
+    uint32_t swap_key0, swap_key1;
+    uint32_t t_add;        // sweeps of the call (the exchange advances t by this)
     int32_t lane_words;    // fast tiles: four-slice words per lane (2 needs G4 >= 2)
 };
 

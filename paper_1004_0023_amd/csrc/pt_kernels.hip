@@ -285,6 +285,97 @@ __device__ __forceinline__ void write_back(const DevState &st, const InstDesc &d
                       (int)(rep_lds_bytes(d) / 4), (d.N * d.M + 3) / 4);
 }
 
+// ------------------------------------------------------------------ exchange step
+
+// One even/odd exchange step of instance n by the calling workgroup (any size): pairs,
+// FP64 D, SWAP-domain draws, label swap, statistics, round-trip labels, per-rung visit
+// counts and accumulators; then e += 1 and t += t_add.
+__device__ void exchange_instance(const DevState &st, int n, uint32_t key0, uint32_t key1,
+                                  uint32_t t_add)
+{
+    const InstDesc d = st.inst[n];
+    const int R = d.R;
+    const int base = d.rep_base;
+    const int pb = d.pair_base;
+    const uint64_t e = st.ctr[n].e;
+    const int par = (int)(e & 1u);
+    for (int j = threadIdx.x;; j += blockDim.x) {
+        const int r = par + 2 * j;
+        if (r + 1 >= R) break;
+        const int x = st.replica_of[base + r];
+        const int y = st.replica_of[base + r + 1];
+        const double dE = (double)(st.E[base + x] - st.E[base + y]);
+        const double dC = (double)(st.C[base + x] - st.C[base + y]);
+        const double D = st.db[pb + r] * dE - st.dK[pb + r] * dC;
+        const uint32_t thr = threshold(-D);
+        const uint32_t u = philox10((uint32_t)r, (uint32_t)e, 0u, (uint32_t)n, key0, key1).w[0];
+        st.att[pb + r] += 1;
+        if (u <= thr) {
+            st.replica_of[base + r] = y;
+            st.replica_of[base + r + 1] = x;
+            st.rung_of[base + y] = r;
+            st.rung_of[base + x] = r + 1;
+            st.acc[pb + r] += 1;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int cold = st.replica_of[base];
+        const int hot = st.replica_of[base + R - 1];
+        const int lc = st.label[base + cold];
+        if (lc == 2) {
+            st.rt[base + cold] += 1;
+            st.label[base + cold] = 1;
+        } else if (lc == 0) {
+            st.label[base + cold] = 1;
+        }
+        if (st.label[base + hot] == 1) st.label[base + hot] = 2;
+    }
+    __syncthreads();  // labels are final
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        const int c = st.replica_of[base + r];
+        const int lab = st.label[base + c];
+        if (lab == 1) st.nup[base + r] += 1;
+        if (lab == 2) st.ndown[base + r] += 1;
+        const long long E = st.E[base + c];
+        const long long C = st.C[base + c];
+        st.sumE[base + r] += E;
+        st.sumC[base + r] += C;
+        st.sumE2[base + r] += E * E;
+        st.sumC2[base + r] += C * C;
+    }
+    if (threadIdx.x == 0) {
+        st.ctr[n].e = e + 1;
+        st.ctr[n].n_acc += 1;
+        st.ctr[n].t += t_add;
+    }
+}
+
+
+// End of a tile in a PT cycle: count the tile for its instance and, in the workgroup that
+// completes the instance, run the instance's exchange step.  Every tile's spins and
+// energies are written before its count (agent-scope release), and the completing
+// workgroup acquires them before it reads the energies; nothing ever waits on another
+// workgroup.  The completing workgroup also clears the count for the next call.  flag: one
+// word of the tile's LDS scratch (no static LDS, which would add to every tile's footprint).
+__device__ __forceinline__ void finish_tile(const SweepLaunch &L, const DevState &st, int n,
+                                            long long *flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t before = atomicAdd(&st.icount[n], 1u);
+        const int done = (before + 1u == (uint32_t)st.itiles[n]) ? 1 : 0;
+        if (done) st.icount[n] = 0;
+        *flag = done;
+    }
+    __syncthreads();
+    if (*flag) {
+        __threadfence();
+        exchange_instance(st, n, L.swap_key0, L.swap_key1, L.t_add);
+    }
+}
+
 // ------------------------------------------------------------------ fast sweep
 
 __device__ __forceinline__ uint32_t lds32(const uint8_t *base, uint32_t byte_off)
@@ -575,6 +666,7 @@ __device__ __forceinline__ void fast_energy(const DevState &st, const InstDesc &
     }
 }
 
+template <bool FUSE>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) sweep_fast_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
@@ -604,6 +696,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     default: fast_energy<0>(st, d, tile, t); break;
     }
     write_back(st, d, tile, t);
+    if constexpr (FUSE) finish_tile(L, st, n, t.red);
 }
 
 // ------------------------------------------------------------------ slice-block sweep
@@ -820,6 +913,7 @@ __global__ void block_prepare_kernel(SweepLaunch L)
         }
 }
 
+template <bool FUSE>
 __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
@@ -1003,6 +1097,8 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
         rec_out[N + i] = sp32[block_at(a, 1, 0, i, 1) >> 2];
         rec_out[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
     }
+    if constexpr (FUSE)
+        if (L.last) finish_tile(L, st, n, t.red);
 }
 
 // ------------------------------------------------------------------ generic sweep
@@ -1014,6 +1110,7 @@ __device__ __forceinline__ int lds_x(const uint8_t *rep, const InstDesc &d, int 
     return rep[p * d.N * d.Mh + i * d.Mh + m];
 }
 
+template <bool FUSE>
 __global__ void __launch_bounds__(1024) sweep_generic_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
@@ -1097,69 +1194,14 @@ __global__ void __launch_bounds__(1024) sweep_generic_kernel(SweepLaunch L)
         }
     }
     write_back(st, d, tile, t);
+    if constexpr (FUSE) finish_tile(L, st, n, t.red);
 }
 
 // ------------------------------------------------------------------ exchange
 
 __global__ void exchange_kernel(DevState st, uint32_t key0, uint32_t key1, uint32_t t_add)
 {
-    const int n = blockIdx.x;
-    const InstDesc d = st.inst[n];
-    const int R = d.R;
-    const int base = d.rep_base;
-    const int pb = d.pair_base;
-    const uint64_t e = st.ctr[n].e;
-    const int par = (int)(e & 1u);
-    for (int j = threadIdx.x;; j += blockDim.x) {
-        const int r = par + 2 * j;
-        if (r + 1 >= R) break;
-        const int x = st.replica_of[base + r];
-        const int y = st.replica_of[base + r + 1];
-        const double dE = (double)(st.E[base + x] - st.E[base + y]);
-        const double dC = (double)(st.C[base + x] - st.C[base + y]);
-        const double D = st.db[pb + r] * dE - st.dK[pb + r] * dC;
-        const uint32_t thr = threshold(-D);
-        const uint32_t u = philox10((uint32_t)r, (uint32_t)e, 0u, (uint32_t)n, key0, key1).w[0];
-        st.att[pb + r] += 1;
-        if (u <= thr) {
-            st.replica_of[base + r] = y;
-            st.replica_of[base + r + 1] = x;
-            st.rung_of[base + y] = r;
-            st.rung_of[base + x] = r + 1;
-            st.acc[pb + r] += 1;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int cold = st.replica_of[base];
-        const int hot = st.replica_of[base + R - 1];
-        const int lc = st.label[base + cold];
-        if (lc == 2) {
-            st.rt[base + cold] += 1;
-            st.label[base + cold] = 1;
-        } else if (lc == 0) {
-            st.label[base + cold] = 1;
-        }
-        if (st.label[base + hot] == 1) st.label[base + hot] = 2;
-    }
-    __syncthreads();  // labels are final
-    for (int r = threadIdx.x; r < R; r += blockDim.x) {
-        const int c = st.replica_of[base + r];
-        const int lab = st.label[base + c];
-        if (lab == 1) st.nup[base + r] += 1;
-        if (lab == 2) st.ndown[base + r] += 1;
-        const long long E = st.E[base + c];
-        const long long C = st.C[base + c];
-        st.sumE[base + r] += E;
-        st.sumC[base + r] += C;
-        st.sumE2[base + r] += E * E;
-        st.sumC2[base + r] += C * C;
-    }
-    if (threadIdx.x == 0) {
-        st.ctr[n].e = e + 1;
-        st.ctr[n].n_acc += 1;
-        st.ctr[n].t += t_add;
-    }
+    exchange_instance(st, blockIdx.x, key0, key1, t_add);
 }
 
 __global__ void advance_kernel(DevState st, int32_t n_inst, uint32_t t_add)
@@ -1194,18 +1236,23 @@ int32_t block_tile_lds_bytes(const InstDesc &d, int32_t P, int32_t ng)
 
 hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes)
 {
-    hipError_t e = hipSuccess;
-    if (block_bytes > 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_block_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, block_bytes);
-    if (e != hipSuccess) return e;
-    if (fast_bytes > 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_fast_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, fast_bytes);
-    if (e == hipSuccess && generic_bytes > 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_generic_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, generic_bytes);
-    return e;
+    const struct {
+        const void *fn;
+        int32_t bytes;
+    } k[] = {
+        {reinterpret_cast<const void *>(&sweep_block_kernel<false>), block_bytes},
+        {reinterpret_cast<const void *>(&sweep_block_kernel<true>), block_bytes},
+        {reinterpret_cast<const void *>(&sweep_fast_kernel<false>), fast_bytes},
+        {reinterpret_cast<const void *>(&sweep_fast_kernel<true>), fast_bytes},
+        {reinterpret_cast<const void *>(&sweep_generic_kernel<false>), generic_bytes},
+        {reinterpret_cast<const void *>(&sweep_generic_kernel<true>), generic_bytes},
+    };
+    for (const auto &x : k) {
+        if (x.bytes <= 0) continue;
+        const hipError_t e = hipFuncSetAttribute(x.fn, hipFuncAttributeMaxDynamicSharedMemorySize, x.bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_init_spins(const DevState &st, int32_t n_reps, uint32_t key0, uint32_t key1,
@@ -1226,12 +1273,24 @@ hipError_t launch_energy(const DevState &st, int32_t rep_first, int32_t n_reps, 
 hipError_t launch_sweep(const SweepLaunch &L, int kind, hipStream_t s)
 {
     if (L.n_tiles <= 0) return hipSuccess;
-    if (kind == kTileFast)
-        hipLaunchKernelGGL(sweep_fast_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
-    else if (kind == kTileBlock)
-        hipLaunchKernelGGL(sweep_block_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
-    else
-        hipLaunchKernelGGL(sweep_generic_kernel, dim3(L.n_tiles), dim3(L.block_threads), L.lds_bytes, s, L);
+    const dim3 grid(L.n_tiles), block(L.block_threads);
+    const bool fuse = L.fuse_exchange != 0;
+    if (kind == kTileFast) {
+        if (fuse)
+            hipLaunchKernelGGL(sweep_fast_kernel<true>, grid, block, L.lds_bytes, s, L);
+        else
+            hipLaunchKernelGGL(sweep_fast_kernel<false>, grid, block, L.lds_bytes, s, L);
+    } else if (kind == kTileBlock) {
+        if (fuse)
+            hipLaunchKernelGGL(sweep_block_kernel<true>, grid, block, L.lds_bytes, s, L);
+        else
+            hipLaunchKernelGGL(sweep_block_kernel<false>, grid, block, L.lds_bytes, s, L);
+    } else {
+        if (fuse)
+            hipLaunchKernelGGL(sweep_generic_kernel<true>, grid, block, L.lds_bytes, s, L);
+        else
+            hipLaunchKernelGGL(sweep_generic_kernel<false>, grid, block, L.lds_bytes, s, L);
+    }
     return hipGetLastError();
 }
 
