@@ -17,11 +17,13 @@ every lambda.  The network's 64 outputs are logits of lambda at the knots
 u_j = j/63, interpolated linearly to the rungs.
 
 Training data.  For each training instance the sampler itself measures replica round
-trips per sweep under a small set of constant lambda; the target lambda is the maximiser
-of a quadratic fitted to those rates (the best measured candidate when the fit is not
-concave), clipped to the scanned range.  The network (32 -> 128 -> 128 -> 64 FP32,
+trips per sweep under linear profiles lambda(u) = clip(a + s (u - 1/2), 0, 1): a small
+set of levels a for each of a few slopes s.  Per slope, the best level is the maximiser
+of a quadratic fitted to the measured rates (the best measured level when the fit is
+not concave), clipped to the scanned range; the target profile is the slope whose
+fitted peak is higher, at its best level.  The network (32 -> 128 -> 128 -> 64 FP32,
 trained with the library's own kernels, per-output logistic cross entropy) maps
-instance features to that target at every knot.
+instance features to that profile at the knots.
 """
 from __future__ import annotations
 
@@ -33,7 +35,8 @@ import numpy as np
 
 N_FEATURES = 32
 N_KNOTS = 64
-SCAN_LAMBDAS = (0.1, 0.2, 0.3, 0.4, 0.55)
+SCAN_LAMBDAS = (0.1, 0.2, 0.3, 0.4, 0.55)   # profile levels a
+SCAN_SLOPES = (0.0, 0.25)                   # profile slopes s
 
 
 # ----------------------------------------------------------------------------- features
@@ -89,6 +92,13 @@ def knots_to_rungs(lam_knots: Sequence[float], R: int) -> np.ndarray:
     return np.interp(np.arange(R) / (R - 1), np.arange(n) / (n - 1), lam_knots)
 
 
+def profile(level: float, slope: float, n: int) -> np.ndarray:
+    """The linear profile lambda(u) = clip(level + slope (u - 1/2), 0, 1) at u = j/(n-1),
+    j = 0 .. n-1 (the rungs of an n-rung ladder, or the knots when n = N_KNOTS)."""
+    u = np.arange(n) / (n - 1)
+    return np.clip(level + slope * (u - 0.5), 0.0, 1.0)
+
+
 def coupling_ladder(inst, lam) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """(T, b, K) of the geometric-temperature ladder with Trotter-coupling mixing lam
     (a scalar or one value per rung)."""
@@ -107,18 +117,37 @@ def with_ladder(inst, lam):
     return dataclasses.replace(inst, b=b, K=K, T=T)
 
 
-def target_lambda(rates: Sequence[float], lams: Sequence[float] = SCAN_LAMBDAS) -> float:
-    """The lambda that maximises a least-squares quadratic through (lams, rates), clipped
-    to the scanned range; the best scanned lambda when the fit is not concave."""
+def _quadratic_peak(lams, rates) -> Tuple[float, float]:
+    """(x, y) at the maximum of a least-squares quadratic through (lams, rates), x clipped
+    to the scanned range; the best measured point when the fit is not concave; the
+    middle of the range with rate 0 when nothing was measured."""
     x = np.asarray(lams, dtype=np.float64)
     y = np.asarray(rates, dtype=np.float64)
-    best = float(x[int(np.argmax(y))])
     if not np.any(y > 0):
-        return float(np.median(x))
-    a, b_, _ = np.polyfit(x, y, 2)
-    if a >= 0:
-        return best
-    return float(np.clip(-b_ / (2 * a), x.min(), x.max()))
+        return float(np.median(x)), 0.0
+    best = int(np.argmax(y))
+    c2, c1, c0 = np.polyfit(x, y, 2)
+    if c2 >= 0:
+        return float(x[best]), float(y[best])
+    xp = float(np.clip(-c1 / (2 * c2), x.min(), x.max()))
+    return xp, float(np.polyval([c2, c1, c0], xp))
+
+
+def target_lambda(rates: Sequence[float], lams: Sequence[float] = SCAN_LAMBDAS) -> float:
+    """The level that maximises a least-squares quadratic through (lams, rates), clipped
+    to the scanned range; the best scanned level when the fit is not concave."""
+    return _quadratic_peak(lams, rates)[0]
+
+
+def target_profile(rates, lams: Sequence[float] = SCAN_LAMBDAS,
+                   slopes: Sequence[float] = SCAN_SLOPES) -> Tuple[float, float]:
+    """(level, slope) of the target profile from rates[slope][level]: for each slope the
+    quadratic peak over the levels; the slope whose fitted peak is highest wins (the
+    first of equal peaks)."""
+    rates = np.asarray(rates, dtype=np.float64).reshape(len(slopes), len(lams))
+    peaks = [_quadratic_peak(lams, r) for r in rates]
+    j = int(np.argmax([p[1] for p in peaks]))
+    return peaks[j][0], float(slopes[j])
 
 
 def deo_round_trip_rate(acc: np.ndarray, att: np.ndarray) -> float:
@@ -174,12 +203,14 @@ def evaluate(instances, lams, seed: int, k: int, cycles: int, burn_cycles: int =
     return rt, pred, amin
 
 
-def scan(instances, seed: int, k: int, cycles: int, lams: Sequence[float] = SCAN_LAMBDAS):
-    """Measured round trips per sweep of every instance under each constant lambda:
-    array [len(instances)][len(lams)]."""
+def scan(instances, seed: int, k: int, cycles: int, lams: Sequence[float] = SCAN_LAMBDAS,
+         slope: float = 0.0):
+    """Measured round trips per sweep of every instance under the profiles of each level
+    in lams at one slope: array [len(instances)][len(lams)]."""
     out = np.zeros((len(instances), len(lams)))
     for c, lam in enumerate(lams):
-        rt, _, _ = evaluate(instances, [lam] * len(instances), seed, k, cycles)
+        rt, _, _ = evaluate(instances, [profile(lam, slope, i.R) for i in instances], seed, k,
+                            cycles)
         out[:, c] = rt
     return out
 

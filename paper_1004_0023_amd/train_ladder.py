@@ -1,6 +1,6 @@
 """Generate training data, train and evaluate the ladder network on the GPU.
 
-    python -m paper_1004_0023_amd.train_ladder scan [--from 0 --to 4096]
+    python -m paper_1004_0023_amd.train_ladder scan [--from 0 --to 4096] [--slope S]
     python -m paper_1004_0023_amd.train_ladder fit
     python -m paper_1004_0023_amd.train_ladder eval
 
@@ -9,14 +9,16 @@ d ~ U{4..8}, M in {32,64,128}, R in {16,32,64}, T in [0.1, 3.0], Gamma = 1) from
 own seeds: training instances 0 .. 4095, held-out instances 4096 .. 4351.
 
 scan: the sampler measures round trips per sweep of every training instance under each
-      constant Trotter-coupling mixing lambda (see ladder.py); results accumulate in
-      the scan file, so the scan can be split over several runs.
-fit:  per-instance target lambda from the scan, the same target at all 64 knots; the
-      network is fitted with the library's FP32 kernels and saved.
-eval: held-out instances under the geometric ladder, the learned ladders and the best
-      single constant lambda of the training scan, all for the same number of sweeps;
-      the report gives measured round trips per sweep (with paired bootstrap intervals),
-      swap-rate-predicted round trips and minimum pair acceptance.
+      linear Trotter-coupling mixing profile of the scan grid (levels x slopes, see
+      ladder.py); results accumulate in the scan file and finished cells are skipped,
+      so the scan can be split over several runs.
+fit:  per-instance target profile from the scan, evaluated at the 64 knots; the network
+      is fitted with the library's FP32 kernels and saved.
+eval: held-out instances under the geometric ladder, the learned ladders, the best
+      single constant lambda and the best single profile of the training scan, all for
+      the same number of sweeps; the report gives measured round trips per sweep (with
+      paired bootstrap intervals), swap-rate-predicted round trips and minimum pair
+      acceptance.
 """
 from __future__ import annotations
 
@@ -60,12 +62,28 @@ def heldout(count: int = N_HELD):
 
 
 def load_scan(path: str):
+    """rates[instance][slope][level] (NaN where not yet scanned) and the sweeps per
+    measurement.  A file from before the slope axis holds the slope-0 cells only."""
+    shape = (N_TRAIN, len(L.SCAN_SLOPES), len(L.SCAN_LAMBDAS))
+    rates = np.full(shape, np.nan)
     if not os.path.exists(path):
-        return (np.full((N_TRAIN, len(L.SCAN_LAMBDAS)), np.nan), 0)
+        return rates, 0
     with np.load(path, allow_pickle=False) as f:
         if tuple(f["lams"]) != tuple(L.SCAN_LAMBDAS):
-            raise ValueError(f"{path} was scanned with other lambdas")
-        return f["rates"].copy(), int(f["sweeps"])
+            raise ValueError(f"{path} was scanned with other levels")
+        slopes = tuple(f["slopes"]) if "slopes" in f else (0.0,)
+        stored = f["rates"].reshape(N_TRAIN, len(slopes), len(L.SCAN_LAMBDAS))
+        for j, sl in enumerate(slopes):
+            if sl not in L.SCAN_SLOPES:
+                raise ValueError(f"{path} holds slope {sl}, not one of {L.SCAN_SLOPES}")
+            rates[:, L.SCAN_SLOPES.index(sl)] = stored[:, j]
+        return rates, int(f["sweeps"])
+
+
+def save_scan(path: str, rates: np.ndarray, sweeps: int):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, rates=rates, lams=np.asarray(L.SCAN_LAMBDAS),
+             slopes=np.asarray(L.SCAN_SLOPES), sweeps=np.int64(sweeps))
 
 
 def phase_scan(args):
@@ -73,36 +91,44 @@ def phase_scan(args):
     if sweeps and sweeps != args.scan_sweeps:
         raise ValueError(f"{args.scan_file} holds scans of {sweeps} sweeps")
     cycles = args.scan_sweeps // K
+    slopes = L.SCAN_SLOPES if args.slope is None else (args.slope,)
     t0 = time.time()
-    for off in range(args.idx_from, args.idx_to, args.chunk):
-        n = min(args.chunk, args.idx_to - off)
-        chunk = draw(off, n)
-        rates[off:off + n] = L.scan(chunk, SEED0 + off, K, cycles)
-        os.makedirs(os.path.dirname(args.scan_file), exist_ok=True)
-        np.savez(args.scan_file, rates=rates, lams=np.asarray(L.SCAN_LAMBDAS),
-                 sweeps=np.int64(args.scan_sweeps))
-        log(f"scanned instances {off}..{off + n - 1} ({time.time() - t0:.0f} s); "
-            f"mean rates {np.round(rates[off:off + n].mean(0) * 1e4, 3)} x1e-4")
+    for sl in slopes:
+        j = L.SCAN_SLOPES.index(sl)
+        for off in range(args.idx_from, args.idx_to, args.chunk):
+            n = min(args.chunk, args.idx_to - off)
+            if np.all(np.isfinite(rates[off:off + n, j])):
+                continue
+            rates[off:off + n, j] = L.scan(draw(off, n), SEED0 + off, K, cycles, slope=sl)
+            save_scan(args.scan_file, rates, args.scan_sweeps)
+            log(f"slope {sl}: scanned instances {off}..{off + n - 1} ({time.time() - t0:.0f} s); "
+                f"mean rates {np.round(rates[off:off + n, j].mean(0) * 1e4, 3)} x1e-4")
 
 
 def targets_from_scan(rates: np.ndarray) -> np.ndarray:
-    return np.array([L.target_lambda(r) for r in rates])
+    """Per instance (level, slope) of the target profile."""
+    return np.array([L.target_profile(r) for r in rates])
 
 
 def phase_fit(args):
     rates, sweeps = load_scan(args.scan_file)
     if np.isnan(rates).any():
         raise ValueError(f"{args.scan_file} is incomplete")
-    lam = targets_from_scan(rates)
-    log(f"targets: mean {lam.mean():.3f}, std {lam.std():.3f} from {sweeps}-sweep scans")
+    tgt = targets_from_scan(rates)
+    log(f"targets from {sweeps}-sweep scans: level mean {tgt[:, 0].mean():.3f} "
+        f"std {tgt[:, 0].std():.3f}; slope counts "
+        f"{ {float(sl): int((tgt[:, 1] == sl).sum()) for sl in L.SCAN_SLOPES} }")
     feats = np.stack([L.features(i) for i in draw(0, N_TRAIN)])
-    Q = np.repeat(lam[:, None], L.N_KNOTS, axis=1)
+    Q = np.stack([L.profile(a, sl, L.N_KNOTS) for a, sl in tgt])
     model = L.train(feats, Q, steps=args.steps, log=log)
     os.makedirs(os.path.dirname(args.model), exist_ok=True)
     model.save(args.model)
-    pred = model.knots(draw(0, N_TRAIN)).mean(axis=1)
-    log(f"saved {args.model}; train fit: rms(pred - target) {np.sqrt(((pred - lam) ** 2).mean()):.4f}, "
-        f"corr {np.corrcoef(pred, lam)[0, 1]:.3f}")
+    pred = model.knots(draw(0, N_TRAIN))
+    lvl, q_lvl = pred.mean(axis=1), Q.mean(axis=1)
+    log(f"saved {args.model}; train fit: rms(pred - target) over knots "
+        f"{np.sqrt(((pred - Q) ** 2).mean()):.4f}, corr of mean level "
+        f"{np.corrcoef(lvl, q_lvl)[0, 1]:.3f}, mean slope (last - first knot) "
+        f"{(pred[:, -1] - pred[:, 0]).mean():.3f} vs target {(Q[:, -1] - Q[:, 0]).mean():.3f}")
 
 
 def paired(a, b, rng):
@@ -115,8 +141,10 @@ def paired(a, b, rng):
 
 def phase_eval(args):
     rates, sweeps = load_scan(args.scan_file)
-    best_c = int(np.argmax(np.nanmean(rates, axis=0)))
-    lam_const = float(L.SCAN_LAMBDAS[best_c])
+    mean = np.nanmean(rates, axis=0)                         # [slope][level]
+    lam_const = float(L.SCAN_LAMBDAS[int(np.argmax(mean[L.SCAN_SLOPES.index(0.0)]))])
+    j_s, j_l = np.unravel_index(int(np.argmax(mean)), mean.shape)
+    best_profile = (float(L.SCAN_LAMBDAS[j_l]), float(L.SCAN_SLOPES[j_s]))
     model = L.LadderModel.load(args.model)
     held = heldout(args.heldout)
     cycles = args.eval_sweeps // K
@@ -126,8 +154,10 @@ def phase_eval(args):
         "geometric": L.evaluate(held, [0.0] * len(held), seed, K, cycles),
         "learned": L.evaluate(held, model.rung_lambdas(held), seed, K, cycles),
         "best_constant": L.evaluate(held, [lam_const] * len(held), seed, K, cycles),
+        "best_profile": L.evaluate(held, [L.profile(*best_profile, i.R) for i in held], seed,
+                                   K, cycles),
     }
-    log(f"evaluated {len(held)} held-out instances x 3 ladders x {cycles * K} sweeps "
+    log(f"evaluated {len(held)} held-out instances x {len(runs)} ladders x {cycles * K} sweeps "
         f"in {time.time() - t0:.0f} s")
     rng = np.random.default_rng(1)
 
@@ -135,19 +165,24 @@ def phase_eval(args):
         return {str(R): float(a[[i.R == R for i in held]].mean()) for R in (16, 32, 64)}
 
     rt = {k: v[0] for k, v in runs.items()}
-    lam_learned = model.knots(held).mean(axis=1)
+    kn = model.knots(held)
+    lam_learned = kn.mean(axis=1)
     report = {
         "train_instances": N_TRAIN, "heldout_instances": len(held),
-        "scan_lambdas": list(L.SCAN_LAMBDAS), "scan_sweeps": sweeps,
+        "scan_lambdas": list(L.SCAN_LAMBDAS), "scan_slopes": list(L.SCAN_SLOPES),
+        "scan_sweeps": sweeps, "scan_mean_rates": mean.tolist(),
         "sweeps_per_instance": cycles * K, "sweeps_per_exchange": K,
         "best_constant_lambda": lam_const,
+        "best_profile": {"level": best_profile[0], "slope": best_profile[1]},
         "learned_lambda": {"mean": float(lam_learned.mean()), "min": float(lam_learned.min()),
-                           "max": float(lam_learned.max())},
+                           "max": float(lam_learned.max()),
+                           "slope_last_minus_first_knot": float((kn[:, -1] - kn[:, 0]).mean())},
         "measured_round_trips_per_sweep": {
             **{k: float(v.mean()) for k, v in rt.items()},
             "by_R": {k: by_R(v) for k, v in rt.items()},
             "learned_vs_geometric": paired(rt["learned"], rt["geometric"], rng),
-            "learned_vs_best_constant": paired(rt["learned"], rt["best_constant"], rng)},
+            "learned_vs_best_constant": paired(rt["learned"], rt["best_constant"], rng),
+            "learned_vs_best_profile": paired(rt["learned"], rt["best_profile"], rng)},
         "predicted_round_trips_per_exchange": {k: float(v[1].mean()) for k, v in runs.items()},
         "min_pair_acceptance": {k: float(v[2].mean()) for k, v in runs.items()},
         "count_by_R": {str(R): int(sum(i.R == R for i in held)) for R in (16, 32, 64)},
@@ -164,6 +199,8 @@ def main(argv=None):
     ap.add_argument("--from", dest="idx_from", type=int, default=0)
     ap.add_argument("--to", dest="idx_to", type=int, default=N_TRAIN)
     ap.add_argument("--chunk", type=int, default=512)
+    ap.add_argument("--slope", type=float, default=None,
+                    help="scan only this slope of the grid (default: every slope)")
     ap.add_argument("--scan-sweeps", type=int, default=40000)
     ap.add_argument("--eval-sweeps", type=int, default=100000)
     ap.add_argument("--heldout", type=int, default=N_HELD)

@@ -100,11 +100,42 @@ def test_model_save_load(tmp_path):
         assert np.array_equal(a, b)
 
 
+def test_profile():
+    # the knots of a linear profile, clipped to [0, 1]
+    assert np.allclose(L.profile(0.3, 0.25, 5), [0.175, 0.2375, 0.3, 0.3625, 0.425])
+    assert np.array_equal(L.profile(0.9, 0.5, 3), [0.65, 0.9, 1.0])
+    assert np.array_equal(L.profile(0.05, 0.4, 3), [0.0, 0.05, 0.25])
+    # slope 0 is the constant ladder bit for bit, so the slope-0 scan is the constant scan
+    i = W.config3_instance(3, config=5)
+    assert np.array_equal(L.coupling_ladder(i, L.profile(0.3, 0.0, i.R))[2],
+                          L.coupling_ladder(i, 0.3)[2])
+    # the profile at the knots interpolates to the profile at the rungs
+    for R in (16, 33, 64):
+        assert np.allclose(L.knots_to_rungs(L.profile(0.3, 0.25, L.N_KNOTS), R),
+                           L.profile(0.3, 0.25, R), atol=1e-12)
+
+
+def test_target_profile():
+    lams = np.array(L.SCAN_LAMBDAS)
+    flat = -(lams - 0.33) ** 2 + 1.0
+    # the slope whose fitted peak is higher wins, at its own best level
+    a, s = L.target_profile([flat, -(lams - 0.21) ** 2 + 1.5])
+    assert abs(a - 0.21) < 1e-9 and s == L.SCAN_SLOPES[1]
+    a, s = L.target_profile([flat, -(lams - 0.21) ** 2 + 0.5])
+    assert abs(a - 0.33) < 1e-9 and s == L.SCAN_SLOPES[0]
+    # the fitted peak, not the best measured point, decides
+    a, s = L.target_profile([[1.0, 2.0, 2.9, 3.0, 1.0], [1.0, 2.9, 2.95, 2.9, 1.0]])
+    assert s == L.SCAN_SLOPES[1]
+    # equal peaks: the first slope
+    assert L.target_profile([flat, flat])[1] == L.SCAN_SLOPES[0]
+
+
 def test_stored_scan_and_model_files():
     with np.load(os.path.join(DATA, "ladder_scan.npz"), allow_pickle=False) as f:
         assert tuple(f["lams"]) == tuple(L.SCAN_LAMBDAS)
+        assert tuple(f["slopes"]) == tuple(L.SCAN_SLOPES)
         rates = f["rates"]
-        assert rates.shape == (4096, len(L.SCAN_LAMBDAS))
+        assert rates.shape == (4096, len(L.SCAN_SLOPES), len(L.SCAN_LAMBDAS))
         assert np.all(np.isfinite(rates)) and np.all(rates >= 0)
     path = os.path.join(DATA, "ladder_mlp.npz")
     if not os.path.exists(path):
