@@ -790,10 +790,14 @@ struct BlockArgs {
     int G4, g0, esh, tbl_words;
 };
 
-// LDS byte offset of slot s of site i's row of parity p in replica q.
+// LDS byte offset of slot s of site i's row of parity p in replica q.  The per-parity
+// constants are chosen with selects: an index into the two-element arrays by a run-time
+// parity would place the arguments in scratch memory.
 __device__ __forceinline__ uint32_t block_at(const BlockArgs &a, int p, int q, int i, int s)
 {
-    return (uint32_t)q * a.QS + a.base[p] + __umul24((uint32_t)i, a.RS[p]) + 4u * (uint32_t)(s - 1 + p);
+    const uint32_t base = p ? a.base[1] : a.base[0];
+    const uint32_t rs = p ? a.RS[1] : a.RS[0];
+    return (uint32_t)q * a.QS + base + __umul24((uint32_t)i, rs) + 4u * (uint32_t)(s - 1 + p);
 }
 
 // One lane's update of site i, replica q, the group in slot s of parity PAR: four
@@ -891,10 +895,23 @@ __device__ __forceinline__ void block_sweep(const BlockArgs &a, const InstDesc &
 // current spins into buffer (t mod 2), and E_cl, C of its replica cleared by the block at
 // g0 = 0 (the blocks add their partial sums on the call's last launch).  One workgroup per
 // block.
+// Workgroups go to the XCDs (each with its own L2 cache) round robin by index.  The slice
+// blocks of one replica share every cache line of its spin rows (a block owns a few words
+// of each row), so consecutive tiles are kept on one XCD: index b runs tile
+// (b mod X) * q + b / X for b < X * q, q = n / X, and the tail keeps its index.  The map is
+// a bijection for any X; on a device with another XCD count only the locality is lost.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n / kXcds;
+    if (b >= kXcds * q) return b;
+    return (b % kXcds) * q + b / kXcds;
+}
+
 __global__ void block_prepare_kernel(SweepLaunch L)
 {
     const DevState &st = L.st;
-    const Tile tile = st.tiles[L.tile0 + blockIdx.x];
+    const Tile tile = st.tiles[L.tile0 + xcd_tile(blockIdx.x, gridDim.x)];
     const InstDesc d = st.inst[tile.inst];
     const int N = d.N, ng = tile.ng, g0 = tile.g0;
     uint32_t *rec = st.halo + (int64_t)(st.ctr[tile.inst].t & 1) * st.halo_words + tile.hb;
@@ -913,12 +930,135 @@ __global__ void block_prepare_kernel(SweepLaunch L)
         }
 }
 
+// Stage a slice block into LDS: the owned groups of both planes from the spins (16-byte
+// pieces when VEC, i.e. ng is a multiple of 4), the halos from the neighbours' boundary
+// records, then rows, biases, colour lists and the rung table (a slice block holds one
+// replica).
+template <bool VEC>
+__device__ __forceinline__ void block_stage(const DevState &st, const InstDesc &d, const Tile &tile,
+                                            const BlockArgs &a, const BlockLds &t,
+                                            const uint32_t *rec_in)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int P = tile.P, ng = tile.ng, g0 = tile.g0, N = d.N;
+    uint32_t *sp32 = reinterpret_cast<uint32_t *>(t.sp);
+    const uint8_t *rep0 = st.spins + d.spin_base + (int64_t)tile.c0 * d.rep_bytes;
+    const Tile tp = st.tiles[tile.prev], tn = st.tiles[tile.next];
+    const int ND = N * d.D, tw = d.tbl_words;
+    const uint32_t *tbl_src = st.tbl + d.tbl_base + (int64_t)st.rung_of[d.rep_base + tile.c0] * tw;
+
+    // Staging is bound by device-memory latency, not bandwidth: the first round of every
+    // stream (owned groups, halos, neighbour rows, biases, colour lists, rung table) is
+    // loaded before any of it is stored, so the workgroup waits for memory about once.
+    // Halos: parity 1 slot 0 <- previous block's last parity-1 group; parity 1 slot ng+1
+    // and parity 0 slot ng+1 <- next block's first groups (P = 1 for slice blocks).
+    constexpr int kEnt0 = 8;   // neighbour-row words per thread in the first round
+    const int nv = VEC ? ng >> 2 : ng;
+    Walk3 wk(tid, nt, nv, N);  // (vector or group, site, q * 2 + plane)
+    uint4 val[4];
+    int dst[4];
+    bool ok[4];
+    auto load_owned = [&]() {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ok[u] = wk.z < 2 * P;
+            if (ok[u]) {
+                const int v = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
+                const uint8_t *row = rep0 + (int64_t)q * d.rep_bytes + (int64_t)pl * N * d.Mh +
+                                     (int64_t)i * d.Mh;
+                if constexpr (VEC) {
+                    val[u] = *reinterpret_cast<const uint4 *>(row + 4 * (g0 + 4 * v));
+                    dst[u] = (int)(block_at(a, pl, q, i, 1 + 4 * v) >> 2);
+                } else {
+                    val[u].x = *reinterpret_cast<const uint32_t *>(row + 4 * (g0 + v));
+                    dst[u] = (int)(block_at(a, pl, q, i, 1 + v) >> 2);
+                }
+                wk.step();
+            }
+        }
+    };
+    auto store_owned = [&]() {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!ok[u]) continue;
+            sp32[dst[u]] = val[u].x;
+            if constexpr (VEC) {
+                sp32[dst[u] + 1] = val[u].y;
+                sp32[dst[u] + 2] = val[u].z;
+                sp32[dst[u] + 3] = val[u].w;
+            }
+        }
+    };
+    load_owned();
+    const bool row0 = tid < N;
+    uint32_t h1p = 0, h0n = 0, h1n = 0, bias0 = 0, tbl0 = 0;
+    uint16_t cs0 = 0;
+    int32_t co0 = 0;
+    if (row0) {
+        h1p = rec_in[tp.hb + 2 * N + tid];
+        h0n = rec_in[tn.hb + tid];
+        h1n = rec_in[tn.hb + N + tid];
+        bias0 = st.bias[d.site_base + tid];
+        cs0 = st.csite[d.site_base + tid];
+    }
+    uint32_t e0[kEnt0];
+#pragma unroll
+    for (int u = 0; u < kEnt0; ++u)
+        if (tid + u * nt < ND) e0[u] = st.ent[d.ent_base + tid + u * nt];
+    if (tid <= d.n_colors) co0 = st.cls_off[d.cls_base + tid];
+    if (tid < tw) tbl0 = tbl_src[tid];
+
+    store_owned();
+    if (row0) {
+        sp32[block_at(a, 1, 0, tid, 0) >> 2] = h1p;
+        sp32[block_at(a, 1, 0, tid, ng + 1) >> 2] = h1n;
+        sp32[block_at(a, 0, 0, tid, ng + 1) >> 2] = h0n;
+        t.bias[tid] = bias0;
+        t.csite[tid] = cs0;
+    }
+#pragma unroll
+    for (int u = 0; u < kEnt0; ++u)
+        if (tid + u * nt < ND) t.ent[tid + u * nt] = e0[u];
+    if (tid <= d.n_colors) t.coff[tid] = co0;
+    if (tid < tw) t.tbl[tid] = tbl0;
+
+    // the remaining rounds, if any
+    while (wk.z < 2 * P) {
+        load_owned();
+        store_owned();
+    }
+    for (int i = tid + nt; i < N; i += nt) {
+        const uint32_t x1p = rec_in[tp.hb + 2 * N + i];
+        const uint32_t x0n = rec_in[tn.hb + i];
+        const uint32_t x1n = rec_in[tn.hb + N + i];
+        sp32[block_at(a, 1, 0, i, 0) >> 2] = x1p;
+        sp32[block_at(a, 1, 0, i, ng + 1) >> 2] = x1n;
+        sp32[block_at(a, 0, 0, i, ng + 1) >> 2] = x0n;
+        t.bias[i] = st.bias[d.site_base + i];
+        t.csite[i] = st.csite[d.site_base + i];
+    }
+    for (int base = tid + kEnt0 * nt; base < ND; base += 4 * nt) {
+        uint32_t e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (base + u * nt < ND) e[u] = st.ent[d.ent_base + base + u * nt];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (base + u * nt < ND) t.ent[base + u * nt] = e[u];
+    }
+    for (int g = tid + nt; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
+    for (int k = tid + nt; k < tw; k += nt) t.tbl[k] = tbl_src[k];
+}
+
+// Eight waves per SIMD bound the registers (at most 64 VGPRs and few enough SGPRs) so that
+// two 1024-thread workgroups fit on a compute unit when their LDS does: without it the
+// kernel takes over 100 SGPRs, seven waves per SIMD, and one such workgroup per unit.
 template <bool FUSE>
-__global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) sweep_block_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
-    const Tile tile = st.tiles[L.tile0 + blockIdx.x];
+    const Tile tile = st.tiles[L.tile0 + xcd_tile(blockIdx.x, gridDim.x)];
     const int n = tile.inst;
     const InstDesc d = st.inst[n];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -934,8 +1074,6 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
     t.tbl = reinterpret_cast<uint32_t *>(lds + o[5]);
     t.red = reinterpret_cast<long long *>(lds + o[6]);
 
-    // stage: the owned groups of both planes from the spins, the halos from the neighbours'
-    // boundary records, then rows, biases, colour lists and rung tables
     uint32_t *sp32 = reinterpret_cast<uint32_t *>(t.sp);
     const uint64_t tsw = st.ctr[n].t + (uint64_t)L.sweep_off;
     BlockArgs a;
@@ -955,69 +1093,10 @@ __global__ void __launch_bounds__(1024) sweep_block_kernel(SweepLaunch L)
     a.esh = d.ent_sh;
     a.tbl_words = d.tbl_words;
     const uint32_t *rec_in = st.halo + (int64_t)(tsw & 1) * st.halo_words;
-    if ((ng & 3) == 0) {
-        // the owned groups of a row are 16-byte aligned and contiguous in device memory:
-        // 16-byte loads, four row pieces per thread in flight before the LDS stores
-        const int nv = ng >> 2;
-        for (Walk3 wk(tid, nt, nv, N); wk.z < 2 * P;) {  // (vector, site, q * 2 + plane)
-            uint4 val[4];
-            int dst[4];
-            bool ok[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                ok[u] = wk.z < 2 * P;
-                if (ok[u]) {
-                    const int v = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
-                    const uint8_t *row = st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
-                                         (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh;
-                    val[u] = *reinterpret_cast<const uint4 *>(row + 4 * (g0 + 4 * v));
-                    dst[u] = (int)(block_at(a, pl, q, i, 1 + 4 * v) >> 2);
-                    wk.step();
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (!ok[u]) continue;
-                sp32[dst[u]] = val[u].x;
-                sp32[dst[u] + 1] = val[u].y;
-                sp32[dst[u] + 2] = val[u].z;
-                sp32[dst[u] + 3] = val[u].w;
-            }
-        }
-    } else {
-        for (Walk3 wk(tid, nt, ng, N); wk.z < 2 * P; wk.step()) {  // (group, site, q * 2 + plane)
-            const int lg = wk.x, i = wk.y, pl = wk.z & 1, q = wk.z >> 1;
-            sp32[block_at(a, pl, q, i, 1 + lg) >> 2] = *reinterpret_cast<const uint32_t *>(
-                st.spins + d.spin_base + (int64_t)(tile.c0 + q) * d.rep_bytes +
-                (int64_t)pl * N * d.Mh + (int64_t)i * d.Mh + 4 * (g0 + lg));
-        }
-    }
-    {
-        // halos: parity 1 slot 0 <- previous block's last parity-1 group; parity 1 slot ng+1
-        // and parity 0 slot ng+1 <- next block's first groups (P = 1 for slice blocks)
-        const Tile tp = st.tiles[tile.prev], tn = st.tiles[tile.next];
-        for (int i = tid; i < N; i += nt) {
-            const uint32_t h1p = rec_in[tp.hb + 2 * N + i];
-            const uint32_t h0n = rec_in[tn.hb + i];
-            const uint32_t h1n = rec_in[tn.hb + N + i];
-            sp32[block_at(a, 1, 0, i, 0) >> 2] = h1p;
-            sp32[block_at(a, 1, 0, i, ng + 1) >> 2] = h1n;
-            sp32[block_at(a, 0, 0, i, ng + 1) >> 2] = h0n;
-        }
-    }
-    for (int base = tid; base < N * d.D; base += 4 * nt) {  // neighbour rows, 4 loads in flight
-        uint32_t e[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (base + u * nt < N * d.D) e[u] = st.ent[d.ent_base + base + u * nt];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (base + u * nt < N * d.D) t.ent[base + u * nt] = e[u];
-    }
-    for (int i = tid; i < N; i += nt) t.bias[i] = st.bias[d.site_base + i];
-    for (int i = tid; i < N; i += nt) t.csite[i] = st.csite[d.site_base + i];
-    for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
-    stage_tables(st, d, tile.c0, P, t.tbl);
+    if ((ng & 3) == 0)
+        block_stage<true>(st, d, tile, a, t, rec_in);
+    else
+        block_stage<false>(st, d, tile, a, t, rec_in);
     __syncthreads();
 
     switch (d.D) {

@@ -271,8 +271,8 @@ def test_config3_full_batch_sampled(ptqmc):
 
 @pytest.mark.parametrize("tile_bytes,block_threads", [(0, 256), (4096, 1024)])
 def test_slice_blocks_match_oracle(ptqmc, tile_bytes, block_threads):
-    """Replicas forced into slice blocks (one launch per parity phase, halo groups, energy
-    partial sums) reproduce the oracle's trajectory."""
+    """Replicas forced into slice blocks (one launch per sweep, halos from boundary
+    records, energy partial sums) reproduce the oracle's trajectory."""
     insts = fast_batch() + [W.config1()]
     seed = 0xB10C
     k, cycles = 3, 12
