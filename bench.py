@@ -207,14 +207,18 @@ def main():
     seg_rates = [(bounds[j + 1] - bounds[j]) * flips_per_step / seg_s[j] for j in range(n_seg)]
     # One sweep call (k sweeps of every replica) is timed with HIP events on the
     # library's stream.  It runs as one launch per occupancy class of whole-replica
-    # tiles, or as one launch per sweep when replicas are split into slice blocks; the
-    # roofline is quoted per launch of the dominant kernel, the call's algorithmic work
-    # and event time divided by its launch count, so the mean launch duration is the one
-    # a kernel trace reports.
+    # tiles; replicas split into slice blocks run all k sweeps in one launch when every
+    # block can be resident at once, else one launch per sweep.  The roofline is quoted
+    # per launch of the dominant kernel, the call's algorithmic work and event time
+    # divided by its launch count, so the mean launch duration is the one a kernel trace
+    # reports.
     avg_sweep_s = info["sweep_ms"] / max(1, info["sweep_launches"]) / 1e3
     blocked = info["block_tiles"] > 0
     kernel = "sweep_block_kernel" if blocked else "sweep_fast_kernel"
-    launches_per_call = k if blocked else max(1, info["sweep_groups"])
+    if blocked:
+        launches_per_call = 1 if info["block_resident"] else k
+    else:
+        launches_per_call = max(1, info["sweep_groups"])
     ops_call = 0.0
     for inst in insts:
         ops_call += k * inst.flips_per_sweep * ops_per_flip(2.0 * inst.n_edges / inst.N)
@@ -242,6 +246,7 @@ def main():
                    "exchange_kernel_ms": info["exchange_ms"] / max(1, info["exchange_launches"]),
                    "sweep_kernel_flips_per_s": flips_per_step / avg_sweep_s if avg_sweep_s else None,
                    "sweep_launches_per_step": launches_per_call,
+                   "block_resident": bool(info["block_resident"]) if blocked else None,
                    "segment_rates": {"segments": n_seg,
                                      "mean": statistics.mean(seg_rates),
                                      "std": statistics.pstdev(seg_rates),

@@ -46,6 +46,9 @@
  * thread-local message for the last failure on the calling thread.  A context is used
  * by one host thread at a time.  All calls that launch work are asynchronous on the
  * context's stream; pt_observables, pt_get_spins, pt_save and pt_sync synchronise it.
+ * Those four also return PT_ESTATE if, since the last of them, a slice-block launch
+ * with resident blocks gave up waiting for a neighbouring block (its waits are bounded
+ * so that every launch ends; the chain state is then not the sampler's).
  */
 #ifndef PTQMC_H
 #define PTQMC_H
@@ -83,10 +86,13 @@ extern "C" {
 #define PT_FLAG_INJECT_LAUNCH_OOR_ONCE 0x4u /* test hook: the first sweep launch is treated
                                              as out of resources, exercising the fallback */
 #define PT_FLAG_SLICE_BLOCKS 0x8u  /* split every replica that could use them into slice
-                                      blocks (one launch per sweep), as replicas too
-                                      large for one workgroup's LDS always are          */
+                                      blocks, as replicas too large for one workgroup's
+                                      LDS always are                                   */
 #define PT_FLAG_FOUR_SLICE_LANES 0x10u /* fast path: one four-slice word per lane instead
                                           of two (same chain; a measurement and test hook) */
+#define PT_FLAG_BLOCK_LAUNCH_PER_SWEEP 0x20u /* slice blocks: one launch per sweep even when
+                                          all blocks could be resident at once (same
+                                          chain; a measurement and test hook)          */
 
 typedef struct pt_ctx pt_ctx;
 
@@ -152,7 +158,11 @@ typedef struct {
     int64_t exchange_launches;
     int32_t sweep_groups;             /* launches of whole-replica tiles per sweep call:
                                          one per occupancy class of the tiles          */
-    int32_t block_tiles;              /* slice-block tiles (one launch per sweep)      */
+    int32_t block_tiles;              /* slice-block tiles                             */
+    int32_t block_resident;           /* 1: the last slice-block sweep call ran as one
+                                         launch with every block resident (halos passed
+                                         between blocks in device memory); 0: one launch
+                                         per sweep                                      */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

@@ -178,6 +178,10 @@ struct DevState {
     // per instance: tiles of one sweep call, and tiles that finished the current call
     const int32_t *itiles;
     uint32_t *icount;
+    // resident slice blocks: sweeps each block has published in the current call (one per
+    // block tile), and a sticky error word (nonzero: a wait gave up)
+    int32_t *prog;
+    uint32_t *err;
     // mutable state
     uint8_t *spins;
     int64_t *E;       // per replica slot

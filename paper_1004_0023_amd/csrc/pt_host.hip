@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -63,7 +64,7 @@ struct Plan {
     uint64_t flips_per_sweep = 0;
     // byte offsets in the workspace
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
-        o_repinst, o_halo, o_itiles, o_icount;
+        o_repinst, o_halo, o_itiles, o_icount, o_prog, o_err;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr;
@@ -286,6 +287,8 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, Plan &P)
     P.o_halo = take((size_t)P.halo_words * 2 * 4);
     P.o_itiles = take((size_t)n_inst * 4);
     P.o_icount = take((size_t)n_inst * 4);  // zero in the uploaded image
+    P.o_prog = take((size_t)P.max_tiles * 4);
+    P.o_err = take(4);                       // zero in the uploaded image
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
     P.o_E = take((size_t)rep * 8);
@@ -332,6 +335,10 @@ struct pt_ctx {
     std::vector<Tile> tiles;   // fast-kernel tiles, then generic ones, then slice blocks
     int n_fast_tiles = 0, n_generic_tiles = 0, n_block_tiles = 0;
     int lds_block = 0;
+    // resident slice blocks: compute-unit occupancy for (block threads, block LDS)
+    std::pair<int, int> resident_key{-1, -1};
+    int resident_per_cu = 0;
+    int block_persistent = 0;   // the last slice-block call ran as one resident launch
     int block_threads = 256;
     int tile_bytes = 0;        // target spin bytes per tile in use
     // self-tuning: candidate (tile bytes, threads) shapes timed on the first sweep launches
@@ -570,6 +577,40 @@ std::vector<LaunchGroup> launch_groups(const pt_ctx *c)
     return out;
 }
 
+// Whether the resident slice-block kernel can hold every block tile at once with the
+// current block size: the grid must fit the compute units' occupancy, or the blocks that
+// wait for their neighbours could wait for blocks that never start.
+hipError_t blocks_resident(pt_ctx *c, bool &resident)
+{
+    resident = false;
+    if (c->opt.flags & PT_FLAG_BLOCK_LAUNCH_PER_SWEEP) return hipSuccess;
+    if (c->resident_key != std::make_pair(c->block_threads, c->lds_block)) {
+        int32_t per_cu = 0;
+        const hipError_t e = block_resident_per_cu(c->block_threads, c->lds_block, &per_cu);
+        if (e != hipSuccess) return e;
+        c->resident_key = std::make_pair(c->block_threads, c->lds_block);
+        c->resident_per_cu = per_cu;
+    }
+    resident = (int64_t)c->n_block_tiles <= (int64_t)c->resident_per_cu * c->cus;
+    return hipSuccess;
+}
+
+// Wait for the stream, then fail if a resident slice-block launch gave up a wait (the
+// error word is cleared; the chain state after such a launch is not the sampler's).
+int sync_and_check(pt_ctx *c)
+{
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, c->ws + c->plan.o_err, 4, hipMemcpyDeviceToHost));
+    if (err != 0) {
+        const uint32_t zero = 0;
+        HIP_TRY(hipMemcpy(c->ws + c->plan.o_err, &zero, 4, hipMemcpyHostToDevice));
+        return fail(PT_ESTATE, "a resident slice-block launch waited too long for its "
+                               "neighbouring blocks; the state is inconsistent");
+    }
+    return PT_OK;
+}
+
 // n_sweeps sweeps of every tile; with fuse_exchange the tile that completes an instance
 // then runs the instance's exchange step (a PT cycle in one set of launches).
 int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
@@ -609,7 +650,8 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
                 ++queued;
             }
             // slice blocks: boundary records of the current state (and E_cl, C cleared),
-            // then one launch per sweep
+            // then all sweeps in one launch when every block can be resident at once,
+            // else one launch per sweep
             L.tile0 = c->n_fast_tiles + c->n_generic_tiles;
             L.n_tiles = c->n_block_tiles;
             L.lds_bytes = c->lds_block;
@@ -617,11 +659,24 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
                 e = launch_block_prepare(L, c->stream);
                 if (e == hipSuccess) ++queued;
             }
-            for (int sw = 0; sw < n_sweeps && e == hipSuccess && L.n_tiles > 0; ++sw) {
-                L.sweep_off = sw;
-                L.last = (sw == n_sweeps - 1);
-                e = launch_sweep(L, kTileBlock, c->stream);
-                if (e == hipSuccess) ++queued;
+            if (e == hipSuccess && L.n_tiles > 0) {
+                bool resident = false;
+                e = blocks_resident(c, resident);
+                c->block_persistent = resident ? 1 : 0;
+                if (e == hipSuccess && resident) {
+                    L.persist = 1;
+                    L.sweep_off = 0;
+                    L.last = 1;
+                    e = launch_sweep(L, kTileBlock, c->stream);
+                    if (e == hipSuccess) ++queued;
+                } else {
+                    for (int sw = 0; sw < n_sweeps && e == hipSuccess; ++sw) {
+                        L.sweep_off = sw;
+                        L.last = (sw == n_sweeps - 1);
+                        e = launch_sweep(L, kTileBlock, c->stream);
+                        if (e == hipSuccess) ++queued;
+                    }
+                }
             }
         }
         if (e == hipSuccess) {
@@ -846,6 +901,8 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.halo_words = P.halo_words;
     st.itiles = (const int32_t *)(w + P.o_itiles);
     st.icount = (uint32_t *)(w + P.o_icount);
+    st.prog = (int32_t *)(w + P.o_prog);
+    st.err = (uint32_t *)(w + P.o_err);
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;
@@ -969,8 +1026,7 @@ int pt_run(pt_ctx *c, int32_t n_cycles)
 int pt_sync(pt_ctx *c)
 {
     if (!c) return fail(PT_EINVAL, "null context");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    return PT_OK;
+    return sync_and_check(c);
 }
 
 int pt_observables(pt_ctx *c, int32_t inst, pt_obs *o)
@@ -1004,7 +1060,7 @@ int pt_observables(pt_ctx *c, int32_t inst, pt_obs *o)
     if ((rc = get(o->nup, P.o_nup + (size_t)b * 8, (size_t)R * 8))) return rc;
     if ((rc = get(o->ndown, P.o_ndown + (size_t)b * 8, (size_t)R * 8))) return rc;
     if ((rc = get(&ctr, P.o_ctr + (size_t)inst * sizeof(Counters), sizeof(Counters)))) return rc;
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    if ((rc = sync_and_check(c))) return rc;
     if (o->label)
         for (int r = 0; r < R; ++r) o->label[r] = (int8_t)label[r];
     o->t = ctr.t;
@@ -1030,7 +1086,7 @@ int pt_get_spins(pt_ctx *c, int32_t inst, int8_t *out)
     std::vector<uint8_t> buf((size_t)d.R * d.rep_bytes);
     HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + c->plan.o_spins + d.spin_base, buf.size(),
                            hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    if ((rc = sync_and_check(c))) return rc;
     for (int r = 0; r < d.R; ++r)
         for (int k = 0; k < d.M; ++k)
             for (int i = 0; i < d.N; ++i)
@@ -1075,7 +1131,8 @@ int pt_save(pt_ctx *c, void *buf, size_t *len)
     std::memcpy(buf, &h, sizeof h);
     HIP_TRY(hipMemcpyAsync((char *)buf + sizeof h, c->ws + c->plan.o_state, c->plan.state_bytes,
                            hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int rc = sync_and_check(c);
+    if (rc) return rc;
     *len = need;
     return PT_OK;
 }
@@ -1125,6 +1182,7 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->exchange_launches = c->exch_n;
     o->sweep_groups = (int32_t)launch_groups(c).size();
     o->block_tiles = c->n_block_tiles;
+    o->block_resident = c->block_persistent;
     return PT_OK;
 }
 

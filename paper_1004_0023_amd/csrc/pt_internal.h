@@ -21,6 +21,7 @@ struct SweepLaunch {
     uint32_t swap_key0, swap_key1;
     uint32_t t_add;        // sweeps of the call (the exchange advances t by this)
     int32_t lane_words;    // fast tiles: four-slice words per lane (2 needs G4 >= 2)
+    int32_t persist;       // slice blocks: one launch of n_sweeps sweeps, all blocks resident
 };
 
 // Each returns the hipError_t of the launch itself (asynchronous execution errors
@@ -37,6 +38,9 @@ hipError_t launch_exchange(const DevState &st, int32_t n_inst, uint32_t key0, ui
 hipError_t launch_advance(const DevState &st, int32_t n_inst, uint32_t t_add, hipStream_t s);
 hipError_t launch_threshold_eval(const double *dS, uint32_t *out, int32_t n, hipStream_t s);
 hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes);
+// Slice-block workgroups of `threads` threads and `lds_bytes` of LDS that one compute unit
+// holds at once in the resident (persistent) block kernel.
+hipError_t block_resident_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu);
 
 // Record msg as the calling thread's last error (pt_last_error) and return code.
 int report_error(int code, const char *msg);

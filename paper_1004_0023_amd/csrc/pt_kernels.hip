@@ -891,10 +891,6 @@ __device__ __forceinline__ void block_sweep(const BlockArgs &a, const InstDesc &
     block_phase<DT, 1>(a, d, tile, t, tile.ng);
 }
 
-// Before the first slice-block launch of a call: every block's boundary record of the
-// current spins into buffer (t mod 2), and E_cl, C of its replica cleared by the block at
-// g0 = 0 (the blocks add their partial sums on the call's last launch).  One workgroup per
-// block.
 // Workgroups go to the XCDs (each with its own L2 cache) round robin by index.  The slice
 // blocks of one replica share every cache line of its spin rows (a block owns a few words
 // of each row), so consecutive tiles are kept on one XCD: index b runs tile
@@ -908,6 +904,10 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return (b % kXcds) * q + b / kXcds;
 }
 
+// Before the first slice-block launch of a call: every block's boundary record of the
+// current spins into buffer (t mod 2), its progress count zeroed, and E_cl, C of its
+// replica cleared by the block at g0 = 0 (the blocks add their partial sums on the call's
+// last launch).  One workgroup per block, mapped to tiles as in the sweep launches.
 __global__ void block_prepare_kernel(SweepLaunch L)
 {
     const DevState &st = L.st;
@@ -923,6 +923,7 @@ __global__ void block_prepare_kernel(SweepLaunch L)
         rec[N + i] = *reinterpret_cast<const uint32_t *>(r1 + 4 * g0);
         rec[2 * N + i] = *reinterpret_cast<const uint32_t *>(r1 + 4 * (g0 + ng - 1));
     }
+    if (threadIdx.x == 0) st.prog[xcd_tile(blockIdx.x, gridDim.x)] = 0;
     if (g0 == 0 && threadIdx.x == 0)
         for (int q = 0; q < tile.P; ++q) {
             st.E[d.rep_base + tile.c0 + q] = 0;
@@ -1050,15 +1051,56 @@ __device__ __forceinline__ void block_stage(const DevState &st, const InstDesc &
     for (int k = tid + nt; k < tw; k += nt) t.tbl[k] = tbl_src[k];
 }
 
+// Resident slice blocks: wait until both neighbouring blocks have published `need` sweeps
+// (their boundary records of sweep need - 1 are then complete).  Thread 0 polls with
+// relaxed agent-scope loads and takes one acquire fence once both counts are there (an
+// acquire per poll would invalidate the XCD's L2 at every poll).  The wait is bounded,
+// and a block that gives up sets the error word and carries on, so every wave of the
+// launch always exits (the host then reports the call as failed).
+constexpr int kWaitPolls = 1 << 18;
+// s_waitcnt immediate with the vector-memory count 0 and the export and LDS counts at
+// their maxima (no wait on them): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+constexpr int kWaitVmcnt0 = 0x0F70;
+__device__ __forceinline__ void block_wait(const DevState &st, int ip, int in, int need)
+{
+    if (threadIdx.x == 0) {
+        int polls = 0;
+        while (__hip_atomic_load(&st.prog[ip], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need ||
+               __hip_atomic_load(&st.prog[in], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            // once any block has given up, the others stop waiting too
+            if (++polls > kWaitPolls ||
+                __hip_atomic_load(st.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                atomicOr(st.err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
 // Eight waves per SIMD bound the registers (at most 64 VGPRs and few enough SGPRs) so that
 // two 1024-thread workgroups fit on a compute unit when their LDS does: without it the
-// kernel takes over 100 SGPRs, seven waves per SIMD, and one such workgroup per unit.
-template <bool FUSE>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) sweep_block_kernel(SweepLaunch L)
+// kernel takes over 100 SGPRs, seven waves per SIMD, and one such workgroup per unit.  The
+// resident variant (below) is bounded at four: its sweep loop carries more state, and at
+// eight it would spill to scratch memory.
+//
+// PERSIST: one launch runs all n_sweeps sweeps of the call with every block resident (the
+// host launches it only when the device can hold all blocks at once).  The owned groups
+// stay in LDS; after each sweep a block writes its two parity-1 boundary groups to the
+// records of the next sweep and publishes its progress, and before the next sweep it waits
+// for both neighbours and takes their parity-1 groups as its halos.  The parity-0 halo (the
+// next block's first group) needs no exchange: the block recomputes it bit for bit.  The
+// records alternate between two buffers: a neighbour can rewrite a buffer only after it
+// has seen this block's progress of the sweep that read it.
+template <bool FUSE, bool PERSIST>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSIST ? 4 : 8))) sweep_block_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
-    const Tile tile = st.tiles[L.tile0 + xcd_tile(blockIdx.x, gridDim.x)];
+    const int bt = xcd_tile(blockIdx.x, gridDim.x);
+    const Tile tile = st.tiles[L.tile0 + bt];
     const int n = tile.inst;
     const InstDesc d = st.inst[n];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -1099,16 +1141,48 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         block_stage<false>(st, d, tile, a, t, rec_in);
     __syncthreads();
 
-    switch (d.D) {
-    case 1: block_sweep<1>(a, d, tile, t); break;
-    case 2: block_sweep<2>(a, d, tile, t); break;
-    case 3: block_sweep<3>(a, d, tile, t); break;
-    case 4: block_sweep<4>(a, d, tile, t); break;
-    case 5: block_sweep<5>(a, d, tile, t); break;
-    case 6: block_sweep<6>(a, d, tile, t); break;
-    case 7: block_sweep<7>(a, d, tile, t); break;
-    case 8: block_sweep<8>(a, d, tile, t); break;
-    default: block_sweep<0>(a, d, tile, t); break;
+    const int n_sw = PERSIST ? L.n_sweeps : 1;
+    const int ip = tile.prev - L.tile0, in = tile.next - L.tile0;
+    for (int sw = 0; sw < n_sw; ++sw) {
+        if (PERSIST && sw > 0) {
+            block_wait(st, ip, in, sw);
+            const uint32_t *rin = st.halo + (int64_t)((tsw + sw) & 1) * st.halo_words;
+            const int hbp = st.tiles[tile.prev].hb, hbn = st.tiles[tile.next].hb;
+            for (int i = tid; i < N; i += nt) {
+                const uint32_t h1p = rin[hbp + 2 * N + i];
+                const uint32_t h1n = rin[hbn + N + i];
+                sp32[block_at(a, 1, 0, i, 0) >> 2] = h1p;
+                sp32[block_at(a, 1, 0, i, ng + 1) >> 2] = h1n;
+            }
+            a.tt = (uint32_t)(tsw + sw);
+            __syncthreads();
+        }
+        switch (d.D) {
+        case 1: block_sweep<1>(a, d, tile, t); break;
+        case 2: block_sweep<2>(a, d, tile, t); break;
+        case 3: block_sweep<3>(a, d, tile, t); break;
+        case 4: block_sweep<4>(a, d, tile, t); break;
+        case 5: block_sweep<5>(a, d, tile, t); break;
+        case 6: block_sweep<6>(a, d, tile, t); break;
+        case 7: block_sweep<7>(a, d, tile, t); break;
+        case 8: block_sweep<8>(a, d, tile, t); break;
+        default: block_sweep<0>(a, d, tile, t); break;
+        }
+        if (PERSIST && sw + 1 < n_sw) {
+            // the parity-1 boundary groups for the neighbours' next sweep, then progress
+            uint32_t *rout = st.halo + (int64_t)((tsw + sw + 1) & 1) * st.halo_words + tile.hb;
+            for (int i = tid; i < N; i += nt) {
+                rout[N + i] = sp32[block_at(a, 1, 0, i, 1) >> 2];
+                rout[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
+            }
+            // every wave waits for its record stores to reach the L2 (vmcnt 0; a workgroup
+            // release does not wait for them), then one agent-scope release by thread 0 (one
+            // write-back of the XCD's L2) precedes the progress count
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_store(&st.prog[bt], sw + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 
     // partial E_cl and C of the block's owned slices after the last sweep of the call
@@ -1169,12 +1243,14 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                 sp32[block_at(a, pl, q, i, 1 + lg) >> 2];
         }
     }
-    // boundary records for the next sweep: first group of both parities, last of parity 1
-    uint32_t *rec_out = st.halo + (int64_t)((tsw + 1) & 1) * st.halo_words + tile.hb;
-    for (int i = tid; i < N; i += nt) {
-        rec_out[i] = sp32[block_at(a, 0, 0, i, 1) >> 2];
-        rec_out[N + i] = sp32[block_at(a, 1, 0, i, 1) >> 2];
-        rec_out[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
+    // boundary records for the next launch: first group of both parities, last of parity 1
+    if constexpr (!PERSIST) {
+        uint32_t *rec_out = st.halo + (int64_t)((tsw + 1) & 1) * st.halo_words + tile.hb;
+        for (int i = tid; i < N; i += nt) {
+            rec_out[i] = sp32[block_at(a, 0, 0, i, 1) >> 2];
+            rec_out[N + i] = sp32[block_at(a, 1, 0, i, 1) >> 2];
+            rec_out[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
+        }
     }
     if constexpr (FUSE)
         if (L.last) finish_tile(L, st, n, t.red);
@@ -1319,8 +1395,10 @@ hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int3
         const void *fn;
         int32_t bytes;
     } k[] = {
-        {reinterpret_cast<const void *>(&sweep_block_kernel<false>), block_bytes},
-        {reinterpret_cast<const void *>(&sweep_block_kernel<true>), block_bytes},
+        {reinterpret_cast<const void *>(&sweep_block_kernel<false, false>), block_bytes},
+        {reinterpret_cast<const void *>(&sweep_block_kernel<true, false>), block_bytes},
+        {reinterpret_cast<const void *>(&sweep_block_kernel<false, true>), block_bytes},
+        {reinterpret_cast<const void *>(&sweep_block_kernel<true, true>), block_bytes},
         {reinterpret_cast<const void *>(&sweep_fast_kernel<false>), fast_bytes},
         {reinterpret_cast<const void *>(&sweep_fast_kernel<true>), fast_bytes},
         {reinterpret_cast<const void *>(&sweep_generic_kernel<false>), generic_bytes},
@@ -1331,6 +1409,19 @@ hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int3
         const hipError_t e = hipFuncSetAttribute(x.fn, hipFuncAttributeMaxDynamicSharedMemorySize, x.bytes);
         if (e != hipSuccess) return e;
     }
+    return hipSuccess;
+}
+
+hipError_t block_resident_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu)
+{
+    int a = 0, b = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &a, reinterpret_cast<const void *>(&sweep_block_kernel<false, true>), threads, lds_bytes);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &b, reinterpret_cast<const void *>(&sweep_block_kernel<true, true>), threads, lds_bytes);
+    if (e != hipSuccess) return e;
+    *per_cu = a < b ? a : b;
     return hipSuccess;
 }
 
@@ -1360,10 +1451,17 @@ hipError_t launch_sweep(const SweepLaunch &L, int kind, hipStream_t s)
         else
             hipLaunchKernelGGL(sweep_fast_kernel<false>, grid, block, L.lds_bytes, s, L);
     } else if (kind == kTileBlock) {
-        if (fuse)
-            hipLaunchKernelGGL(sweep_block_kernel<true>, grid, block, L.lds_bytes, s, L);
-        else
-            hipLaunchKernelGGL(sweep_block_kernel<false>, grid, block, L.lds_bytes, s, L);
+        if (L.persist) {
+            if (fuse)
+                hipLaunchKernelGGL((sweep_block_kernel<true, true>), grid, block, L.lds_bytes, s, L);
+            else
+                hipLaunchKernelGGL((sweep_block_kernel<false, true>), grid, block, L.lds_bytes, s, L);
+        } else {
+            if (fuse)
+                hipLaunchKernelGGL((sweep_block_kernel<true, false>), grid, block, L.lds_bytes, s, L);
+            else
+                hipLaunchKernelGGL((sweep_block_kernel<false, false>), grid, block, L.lds_bytes, s, L);
+        }
     } else {
         if (fuse)
             hipLaunchKernelGGL(sweep_generic_kernel<true>, grid, block, L.lds_bytes, s, L);

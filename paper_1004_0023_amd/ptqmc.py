@@ -20,6 +20,7 @@ PT_OK, PT_EINVAL, PT_ENOMEM, PT_EHIP, PT_ELAUNCH, PT_ESTATE = 0, -1, -2, -3, -4,
 PT_INT8, PT_BITPACK32 = 0, 1
 PT_FLAG_TIMING, PT_FLAG_NO_GRAPH, PT_FLAG_INJECT_LAUNCH_OOR_ONCE = 0x1, 0x2, 0x4
 PT_FLAG_FOUR_SLICE_LANES = 0x10
+PT_FLAG_BLOCK_LAUNCH_PER_SWEEP = 0x20
 PT_FLAG_SLICE_BLOCKS = 0x8
 LABEL_NONE, LABEL_UP, LABEL_DOWN = 0, 1, 2
 MLP_LOSS_SOFTMAX, MLP_LOSS_SIGMOID = 0, 1
@@ -67,7 +68,7 @@ class _Info(C.Structure):
                 ("flips_per_sweep", C.c_uint64), ("sweep_ms", C.c_double),
                 ("sweep_launches", C.c_int64), ("exchange_ms", C.c_double),
                 ("exchange_launches", C.c_int64), ("sweep_groups", C.c_int32),
-                ("block_tiles", C.c_int32)]
+                ("block_tiles", C.c_int32), ("block_resident", C.c_int32)]
 
 
 _lib = None

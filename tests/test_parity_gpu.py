@@ -269,18 +269,23 @@ def test_config3_full_batch_sampled(ptqmc):
         assert s.info()["sweep_groups"] >= 2
 
 
+@pytest.mark.parametrize("per_sweep", [False, True])
 @pytest.mark.parametrize("tile_bytes,block_threads", [(0, 256), (4096, 1024)])
-def test_slice_blocks_match_oracle(ptqmc, tile_bytes, block_threads):
-    """Replicas forced into slice blocks (one launch per sweep, halos from boundary
-    records, energy partial sums) reproduce the oracle's trajectory."""
+def test_slice_blocks_match_oracle(ptqmc, tile_bytes, block_threads, per_sweep):
+    """Replicas forced into slice blocks reproduce the oracle's trajectory, both with all
+    blocks resident in one launch per call (halos passed between blocks in device memory)
+    and with one launch per sweep (halos from boundary records)."""
     insts = fast_batch() + [W.config1()]
     seed = 0xB10C
     k, cycles = 3, 12
-    say(f"case: slice blocks, tile_bytes={tile_bytes} block_threads={block_threads}")
+    flags = ptqmc.PT_FLAG_SLICE_BLOCKS | (ptqmc.PT_FLAG_BLOCK_LAUNCH_PER_SWEEP if per_sweep else 0)
+    say(f"case: slice blocks, tile_bytes={tile_bytes} block_threads={block_threads} "
+        f"per_sweep={per_sweep}")
     refs = oracle_batch(insts, seed, k, cycles)
     with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_bytes=tile_bytes,
-                       block_threads=block_threads, flags=ptqmc.PT_FLAG_SLICE_BLOCKS) as s:
+                       block_threads=block_threads, flags=flags) as s:
         s.run(cycles)
+        assert s.info()["block_resident"] == (0 if per_sweep else 1)
         for n in range(len(insts)):
             assert_same(s, n, refs[n], "blocks")
 
@@ -297,15 +302,19 @@ def test_config2_slice_blocks(ptqmc):
         assert_same(s, 0, ref, "config2 blocks")
 
 
-def test_config4_lattice_one_cycle(ptqmc):
+@pytest.mark.parametrize("per_sweep", [False, True])
+def test_config4_lattice_one_cycle(ptqmc, per_sweep):
     """The 8x8x16 lattice (N=1024, M=256, R=64): a replica (256 KiB) exceeds one
     workgroup's LDS, so it always runs in slice blocks.  One full cycle (10 sweeps and an
-    exchange) against the oracle."""
+    exchange) against the oracle, with resident blocks and with one launch per sweep."""
     inst = W.config4()
     seed = W.sampler_seed(4)
-    say("case: config 4, 1 cycle of 10 sweeps")
-    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10) as s:
+    flags = ptqmc.PT_FLAG_BLOCK_LAUNCH_PER_SWEEP if per_sweep else 0
+    say(f"case: config 4, 1 cycle of 10 sweeps, per_sweep={per_sweep}")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, tile_bytes=131072,
+                       block_threads=1024, flags=flags) as s:
         s.run(1)
+        assert s.info()["block_resident"] == (0 if per_sweep else 1)
         ref = oracle.OracleChain(inst, seed)
         ref.run(10, 1)
         assert_same(s, 0, ref, "config4")
