@@ -849,18 +849,34 @@ __device__ __forceinline__ void block_item(const BlockArgs &a, const BlockLds &t
     *reinterpret_cast<uint32_t *>(t.sp + own) = X ^ flip;
 }
 
-// All colour classes of parity PAR over slots 1..ns (phase 0: ns = ng + 1; phase 1: ng).
-// Each thread keeps one (replica, slot) pair and strides over the sites of a class.
+// A compile-time int as a value (to instantiate a generic lambda per degree).
+template <int V>
+struct IntC {
+    static constexpr int value = V;
+};
+
+// The slots a phase runs: ns of them, slot s0 + r for r < cut and s0 + r + jump beyond
+// (two runs of consecutive slots).
+struct SlotSet {
+    int s0, ns, cut, jump;
+    __device__ __forceinline__ int at(int r) const { return s0 + r + (r >= cut ? jump : 0); }
+};
+
+// All colour classes of parity PAR over the slots of S (a whole sweep: phase 0 over slots
+// 1..ng+1, phase 1 over 1..ng).  Slots of one parity are independent of each other within
+// a phase, so a phase may be run as several slot sets in any order.  Each thread keeps
+// one (replica, slot) pair and strides over the sites of a class.
 template <int DT, int PAR>
 __device__ __forceinline__ void block_phase(const BlockArgs &a, const InstDesc &d, const Tile &tile,
-                                            const BlockLds &t, int ns)
+                                            const BlockLds &t, const SlotSet &S)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int D = (DT > 0) ? DT : d.D;
+    const int ns = S.ns;
     const int lanes = tile.P * ns;  // per site
     if (lanes <= nt) {
         const int r = tid % lanes;
-        const int q = r / ns, sl = 1 + r - q * ns;
+        const int q = r / ns, sl = S.at(r - q * ns);
         const int sstep = nt / lanes;
         const int s_first = (tid < sstep * lanes) ? tid / lanes : (1 << 30);
         for (int g = 0; g < d.n_colors; ++g) {
@@ -876,7 +892,7 @@ __device__ __forceinline__ void block_phase(const BlockArgs &a, const InstDesc &
             for (int it = tid; it < items; it += nt) {
                 const int si = it / lanes, r = it - si * lanes;
                 const int q = r / ns;
-                block_item<DT, PAR>(a, t, D, t.csite[s0 + si], q, 1 + r - q * ns);
+                block_item<DT, PAR>(a, t, D, t.csite[s0 + si], q, S.at(r - q * ns));
             }
             __syncthreads();
         }
@@ -887,8 +903,28 @@ template <int DT>
 __device__ __forceinline__ void block_sweep(const BlockArgs &a, const InstDesc &d, const Tile &tile,
                                             const BlockLds &t)
 {
-    block_phase<DT, 0>(a, d, tile, t, tile.ng + 1);
-    block_phase<DT, 1>(a, d, tile, t, tile.ng);
+    const int ng = tile.ng;
+    block_phase<DT, 0>(a, d, tile, t, SlotSet{1, ng + 1, ng + 1, 0});
+    block_phase<DT, 1>(a, d, tile, t, SlotSet{1, ng, ng, 0});
+}
+
+// A sweep of a resident block (ng >= 6) ordered so that the exchange with the neighbours
+// overlaps work: phase 0 first over slots 2..ng, which read no halo; then wait_halos()
+// (the neighbours' parity-1 groups of the previous sweep); phase 0 over slots 1 and ng+1;
+// phase 1 over slots 1, 2, ng-1 and ng, which hold the groups the neighbours need; then
+// publish(); and phase 1 over slots 3..ng-2 while the neighbours go on.
+template <int DT, class Wait, class Publish>
+__device__ __forceinline__ void block_sweep_split(const BlockArgs &a, const InstDesc &d,
+                                                  const Tile &tile, const BlockLds &t,
+                                                  Wait &&wait_halos, Publish &&publish)
+{
+    const int ng = tile.ng;
+    block_phase<DT, 0>(a, d, tile, t, SlotSet{2, ng - 1, ng - 1, 0});
+    wait_halos();
+    block_phase<DT, 0>(a, d, tile, t, SlotSet{1, 2, 1, ng - 1});
+    block_phase<DT, 1>(a, d, tile, t, SlotSet{1, 4, 2, ng - 4});
+    publish();
+    block_phase<DT, 1>(a, d, tile, t, SlotSet{3, ng - 4, ng - 4, 0});
 }
 
 // Workgroups go to the XCDs (each with its own L2 cache) round robin by index.  The slice
@@ -1088,12 +1124,14 @@ __device__ __forceinline__ void block_wait(const DevState &st, int ip, int in, i
 //
 // PERSIST: one launch runs all n_sweeps sweeps of the call with every block resident (the
 // host launches it only when the device can hold all blocks at once).  The owned groups
-// stay in LDS; after each sweep a block writes its two parity-1 boundary groups to the
-// records of the next sweep and publishes its progress, and before the next sweep it waits
-// for both neighbours and takes their parity-1 groups as its halos.  The parity-0 halo (the
-// next block's first group) needs no exchange: the block recomputes it bit for bit.  The
-// records alternate between two buffers: a neighbour can rewrite a buffer only after it
-// has seen this block's progress of the sweep that read it.
+// stay in LDS; in each sweep, once its two parity-1 boundary groups are final, a block
+// writes them to the records of the next sweep and publishes its progress, and before the
+// slots next to its edges in the next sweep it waits for both neighbours and takes their
+// parity-1 groups as its halos (with ng >= 6 the interior slots run around these steps,
+// see block_sweep_split).  The parity-0 halo (the next block's first group) needs no
+// exchange: the block recomputes it bit for bit.  The records alternate between two
+// buffers: a neighbour can rewrite a buffer only after it has seen this block's progress
+// of the sweep that read it.
 template <bool FUSE, bool PERSIST>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSIST ? 4 : 8))) sweep_block_kernel(SweepLaunch L)
 {
@@ -1143,46 +1181,68 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
 
     const int n_sw = PERSIST ? L.n_sweeps : 1;
     const int ip = tile.prev - L.tile0, in = tile.next - L.tile0;
-    for (int sw = 0; sw < n_sw; ++sw) {
-        if (PERSIST && sw > 0) {
-            block_wait(st, ip, in, sw);
-            const uint32_t *rin = st.halo + (int64_t)((tsw + sw) & 1) * st.halo_words;
-            const int hbp = st.tiles[tile.prev].hb, hbn = st.tiles[tile.next].hb;
-            for (int i = tid; i < N; i += nt) {
-                const uint32_t h1p = rin[hbp + 2 * N + i];
-                const uint32_t h1n = rin[hbn + N + i];
-                sp32[block_at(a, 1, 0, i, 0) >> 2] = h1p;
-                sp32[block_at(a, 1, 0, i, ng + 1) >> 2] = h1n;
-            }
+    // resident blocks: wait for both neighbours' previous sweep and take their parity-1
+    // boundary groups as halos
+    auto wait_halos = [&](int sw) {
+        block_wait(st, ip, in, sw);
+        const uint32_t *rin = st.halo + (int64_t)((tsw + sw) & 1) * st.halo_words;
+        const int hbp = st.tiles[tile.prev].hb, hbn = st.tiles[tile.next].hb;
+        for (int i = tid; i < N; i += nt) {
+            const uint32_t h1p = rin[hbp + 2 * N + i];
+            const uint32_t h1n = rin[hbn + N + i];
+            sp32[block_at(a, 1, 0, i, 0) >> 2] = h1p;
+            sp32[block_at(a, 1, 0, i, ng + 1) >> 2] = h1n;
+        }
+        __syncthreads();
+    };
+    // resident blocks: the parity-1 boundary groups for the neighbours' next sweep, then
+    // progress.  Every wave waits for its record stores to reach the L2 (vmcnt 0; a
+    // workgroup release does not wait for them), then one agent-scope release by thread 0
+    // (one write-back of the XCD's L2) precedes the progress count.
+    auto publish = [&](int sw) {
+        uint32_t *rout = st.halo + (int64_t)((tsw + sw + 1) & 1) * st.halo_words + tile.hb;
+        for (int i = tid; i < N; i += nt) {
+            rout[N + i] = sp32[block_at(a, 1, 0, i, 1) >> 2];
+            rout[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
+        }
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(&st.prog[bt], sw + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    // the sweep loop, instantiated per degree (the switch stays outside the loop, so only one
+    // degree's phase set-up is live in it)
+    const bool split = PERSIST && ng >= 6;
+    auto sweeps = [&](auto dt) {
+        constexpr int DT = decltype(dt)::value;
+        for (int sw = 0; sw < n_sw; ++sw) {
             a.tt = (uint32_t)(tsw + sw);
-            __syncthreads();
-        }
-        switch (d.D) {
-        case 1: block_sweep<1>(a, d, tile, t); break;
-        case 2: block_sweep<2>(a, d, tile, t); break;
-        case 3: block_sweep<3>(a, d, tile, t); break;
-        case 4: block_sweep<4>(a, d, tile, t); break;
-        case 5: block_sweep<5>(a, d, tile, t); break;
-        case 6: block_sweep<6>(a, d, tile, t); break;
-        case 7: block_sweep<7>(a, d, tile, t); break;
-        case 8: block_sweep<8>(a, d, tile, t); break;
-        default: block_sweep<0>(a, d, tile, t); break;
-        }
-        if (PERSIST && sw + 1 < n_sw) {
-            // the parity-1 boundary groups for the neighbours' next sweep, then progress
-            uint32_t *rout = st.halo + (int64_t)((tsw + sw + 1) & 1) * st.halo_words + tile.hb;
-            for (int i = tid; i < N; i += nt) {
-                rout[N + i] = sp32[block_at(a, 1, 0, i, 1) >> 2];
-                rout[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
+            if (split) {
+                block_sweep_split<DT>(
+                    a, d, tile, t,
+                    [&]() {
+                        if (sw > 0) wait_halos(sw);
+                    },
+                    [&]() {
+                        if (sw + 1 < n_sw) publish(sw);
+                    });
+            } else {
+                if (PERSIST && sw > 0) wait_halos(sw);
+                block_sweep<DT>(a, d, tile, t);
+                if (PERSIST && sw + 1 < n_sw) publish(sw);
             }
-            // every wave waits for its record stores to reach the L2 (vmcnt 0; a workgroup
-            // release does not wait for them), then one agent-scope release by thread 0 (one
-            // write-back of the XCD's L2) precedes the progress count
-            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-            __syncthreads();
-            if (tid == 0)
-                __hip_atomic_store(&st.prog[bt], sw + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
+    };
+    switch (d.D) {
+    case 1: sweeps(IntC<1>{}); break;
+    case 2: sweeps(IntC<2>{}); break;
+    case 3: sweeps(IntC<3>{}); break;
+    case 4: sweeps(IntC<4>{}); break;
+    case 5: sweeps(IntC<5>{}); break;
+    case 6: sweeps(IntC<6>{}); break;
+    case 7: sweeps(IntC<7>{}); break;
+    case 8: sweeps(IntC<8>{}); break;
+    default: sweeps(IntC<0>{}); break;
     }
 
     // partial E_cl and C of the block's owned slices after the last sweep of the call
