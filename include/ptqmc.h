@@ -93,6 +93,10 @@ extern "C" {
 #define PT_FLAG_BLOCK_LAUNCH_PER_SWEEP 0x20u /* slice blocks: one launch per sweep even when
                                           all blocks could be resident at once (same
                                           chain; a measurement and test hook)          */
+#define PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT 0x40u /* test hook: resident slice blocks wait for a
+                                          progress count that never comes, under a tiny
+                                          poll bound, so every wait gives up and the next
+                                          synchronising call returns PT_ESTATE          */
 
 typedef struct pt_ctx pt_ctx;
 

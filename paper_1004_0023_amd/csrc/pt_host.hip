@@ -665,6 +665,10 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
                 c->block_persistent = resident ? 1 : 0;
                 if (e == hipSuccess && resident) {
                     L.persist = 1;
+                    if (c->opt.flags & PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT) {
+                        L.wait_polls = 16;
+                        L.wait_extra = 1 << 30;
+                    }
                     L.sweep_off = 0;
                     L.last = 1;
                     e = launch_sweep(L, kTileBlock, c->stream);

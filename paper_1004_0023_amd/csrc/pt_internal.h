@@ -22,6 +22,10 @@ struct SweepLaunch {
     uint32_t t_add;        // sweeps of the call (the exchange advances t by this)
     int32_t lane_words;    // fast tiles: four-slice words per lane (2 needs G4 >= 2)
     int32_t persist;       // slice blocks: one launch of n_sweeps sweeps, all blocks resident
+    // resident blocks: poll bound of a neighbour wait (0: the kernel's default) and an
+    // amount added to every awaited progress count (0; a test hook sets it so that the
+    // waits run into their bound)
+    int32_t wait_polls, wait_extra;
 };
 
 // Each returns the hipError_t of the launch itself (asynchronous execution errors

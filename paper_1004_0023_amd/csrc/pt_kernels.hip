@@ -1093,18 +1093,19 @@ __device__ __forceinline__ void block_stage(const DevState &st, const InstDesc &
 // acquire per poll would invalidate the XCD's L2 at every poll).  The wait is bounded,
 // and a block that gives up sets the error word and carries on, so every wave of the
 // launch always exits (the host then reports the call as failed).
-constexpr int kWaitPolls = 1 << 18;
+constexpr int kWaitPolls = 1 << 18;  // the host may lower it (SweepLaunch::wait_polls)
 // s_waitcnt immediate with the vector-memory count 0 and the export and LDS counts at
 // their maxima (no wait on them): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
 constexpr int kWaitVmcnt0 = 0x0F70;
-__device__ __forceinline__ void block_wait(const DevState &st, int ip, int in, int need)
+__device__ __forceinline__ void block_wait(const DevState &st, int ip, int in, int need,
+                                           int max_polls)
 {
     if (threadIdx.x == 0) {
         int polls = 0;
         while (__hip_atomic_load(&st.prog[ip], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need ||
                __hip_atomic_load(&st.prog[in], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
             // once any block has given up, the others stop waiting too
-            if (++polls > kWaitPolls ||
+            if (++polls > max_polls ||
                 __hip_atomic_load(st.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                 atomicOr(st.err, 1u);
                 break;
@@ -1184,7 +1185,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
     // resident blocks: wait for both neighbours' previous sweep and take their parity-1
     // boundary groups as halos
     auto wait_halos = [&](int sw) {
-        block_wait(st, ip, in, sw);
+        block_wait(st, ip, in, sw + L.wait_extra, L.wait_polls > 0 ? L.wait_polls : kWaitPolls);
         const uint32_t *rin = st.halo + (int64_t)((tsw + sw) & 1) * st.halo_words;
         const int hbp = st.tiles[tile.prev].hb, hbn = st.tiles[tile.next].hb;
         for (int i = tid; i < N; i += nt) {

@@ -21,6 +21,7 @@ PT_INT8, PT_BITPACK32 = 0, 1
 PT_FLAG_TIMING, PT_FLAG_NO_GRAPH, PT_FLAG_INJECT_LAUNCH_OOR_ONCE = 0x1, 0x2, 0x4
 PT_FLAG_FOUR_SLICE_LANES = 0x10
 PT_FLAG_BLOCK_LAUNCH_PER_SWEEP = 0x20
+PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT = 0x40
 PT_FLAG_SLICE_BLOCKS = 0x8
 LABEL_NONE, LABEL_UP, LABEL_DOWN = 0, 1, 2
 MLP_LOSS_SOFTMAX, MLP_LOSS_SIGMOID = 0, 1

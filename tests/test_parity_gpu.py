@@ -320,6 +320,24 @@ def test_config4_lattice_one_cycle(ptqmc, per_sweep):
         assert_same(s, 0, ref, "config4")
 
 
+def test_resident_block_wait_timeout_is_reported(ptqmc):
+    """Resident slice blocks bound their neighbour waits.  Forced from the host (every
+    block waits for a progress count no block ever publishes, under a poll bound of 16),
+    each wait gives up, every workgroup still exits, and the next synchronising call
+    returns PT_ESTATE once; the error word is then clear."""
+    inst = W.config4()
+    say("case: resident slice blocks, forced wait timeout (config 4, 10 sweeps)")
+    with ptqmc.Sampler([inst], 7, sweeps_per_exchange=10, tile_bytes=131072, block_threads=1024,
+                       flags=ptqmc.PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT | ptqmc.PT_FLAG_NO_GRAPH) as s:
+        s.run(1)
+        with pytest.raises(ptqmc.PTError) as err:
+            s.sync()
+        assert err.value.code == ptqmc.PT_ESTATE
+        assert "waited too long" in str(err.value)
+        assert s.info()["block_resident"] == 1
+        s.sync()  # reported once, then clear
+
+
 def test_maximum_sizes(ptqmc):
     """The largest slice count (M = 4096), a large whole-replica tile (N = 4095 at M = 8,
     about 90 KiB of LDS) and a replica whose rows need offsets beyond 16 bits (N = 4096,
