@@ -1,6 +1,6 @@
 """Benchmark: spin-flip attempts per second of the parallel-tempering sampler on one GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3] [--encoding int8]
 
 A step is one PT cycle over the whole batch: sweeps_per_exchange Metropolis sweeps of
 every replica of every instance (with the energy bookkeeping of each replica), then one
@@ -9,7 +9,8 @@ state is resident in device memory when the timed region starts.  Prints one JSO
 
 The default workload is the batched one (512 instances of uneven size in one launch),
 the configuration whose sweep kernel the roofline target refers to; --config 1, 2 or 4
-selects the single-instance workloads.
+selects the single-instance workloads.  --encoding bitpack keeps 32 replica slots per
+32-bit word (the same chain; one sweep launch per colour class).
 
     python bench.py --copy-calibration BYTES
 
@@ -160,6 +161,7 @@ def main():
     ap.add_argument("--tile-bytes", type=int, default=0)
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0)
+    ap.add_argument("--encoding", choices=["int8", "bitpack"], default="int8")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
@@ -182,8 +184,10 @@ def main():
     steps = args.steps if args.steps is not None else default_steps
     print(f"bench: {desc}; {steps} steps of {k} sweeps + exchange", file=sys.stderr, flush=True)
 
+    encoding = ptqmc.PT_BITPACK32 if args.encoding == "bitpack" else ptqmc.PT_INT8
     s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=ptqmc.PT_FLAG_TIMING,
-                      tile_bytes=args.tile_bytes, block_threads=args.block_threads)
+                      tile_bytes=args.tile_bytes, block_threads=args.block_threads,
+                      encoding=encoding)
     s.run(args.warmup)  # the first launches also tune the launch shape
     s.sync()
     s.timing_reset()
@@ -214,10 +218,16 @@ def main():
     # reports.
     avg_sweep_s = info["sweep_ms"] / max(1, info["sweep_launches"]) / 1e3
     blocked = info["block_tiles"] > 0
-    kernel = "sweep_block_kernel" if blocked else "sweep_fast_kernel"
-    if blocked:
+    packed = encoding == ptqmc.PT_BITPACK32
+    if packed:
+        # one launch per colour class and sweep, plus the two energy launches of the call
+        kernel = "bp_sweep_kernel"
+        launches_per_call = k * max(1, info["class_launches"])
+    elif blocked:
+        kernel = "sweep_block_kernel"
         launches_per_call = 1 if info["block_resident"] else k
     else:
+        kernel = "sweep_fast_kernel"
         launches_per_call = max(1, info["sweep_groups"])
     ops_call = 0.0
     for inst in insts:
@@ -226,6 +236,8 @@ def main():
     launch_s = avg_sweep_s / launches_per_call
     achieved = ops_launch / launch_s / 1e12 if launch_s > 0 else 0.0
     peak = PEAK_INT_OPS / 1e12
+    if packed:
+        desc += "; bit-packed spins (32 replica slots per 32-bit word)"
     out = {
         "metric": "spin-flip attempts/s",
         "value": value,
@@ -237,7 +249,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8",
+        "dtype": "u32" if packed else "u8",
         "data": "synthetic",
         "config": {"workload": desc, "instances": len(insts), "sweeps_per_exchange": k,
                    "flips_per_step": flips_per_step, "tiles": info["n_tiles"],
@@ -246,6 +258,7 @@ def main():
                    "exchange_kernel_ms": info["exchange_ms"] / max(1, info["exchange_launches"]),
                    "sweep_kernel_flips_per_s": flips_per_step / avg_sweep_s if avg_sweep_s else None,
                    "sweep_launches_per_step": launches_per_call,
+                   "encoding": args.encoding,
                    "block_resident": bool(info["block_resident"]) if blocked else None,
                    "segment_rates": {"segments": n_seg,
                                      "mean": statistics.mean(seg_rates),
@@ -254,7 +267,7 @@ def main():
                    "mean_launch_ms": launch_s * 1e3, "ops_per_launch": ops_launch},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak,
-                     "traffic": traffic_per_launch() if args.config == 3 else None,
+                     "traffic": traffic_per_launch() if args.config == 3 and not packed else None,
                      "kernel": kernel},
     }
     s.close()

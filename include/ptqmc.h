@@ -70,10 +70,11 @@ extern "C" {
 
 /* spin encodings (the trajectory is identical under every encoding) */
 #define PT_INT8 0       /* one byte per spin                                                */
-#define PT_BITPACK32 1  /* 32 replicas per uint32 word: bit (c mod 32) of word c/32 at (k, i);
-                           declared for the interface, not built: pt_init refuses it with
-                           PT_EINVAL (packing 32 replicas per word divides the independent
-                           work items by 32, which the GPU cannot spare at these sizes) */
+#define PT_BITPACK32 1  /* 32 replica slots per uint32 word: bit (c mod 32) of word group
+                           c/32 holds slot c's spin at (k, i); device memory 8x smaller.
+                           Each colour class of a sweep is one launch over the batch that
+                           reads and writes the packed words in device memory; the chain
+                           is the same as under PT_INT8                                  */
 
 /* round-trip labels */
 #define PT_LABEL_NONE 0
@@ -167,6 +168,8 @@ typedef struct {
                                          launch with every block resident (halos passed
                                          between blocks in device memory); 0: one launch
                                          per sweep                                      */
+    int32_t class_launches;           /* PT_BITPACK32: sweep launches per sweep (one per
+                                         colour class); 0 under PT_INT8                 */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

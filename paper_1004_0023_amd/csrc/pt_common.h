@@ -132,6 +132,9 @@ struct InstDesc {
     int32_t tbl_words; // words per rung table
     int32_t rep_bytes; // bytes per replica in device memory (N * M rounded up to 16)
     int64_t spin_base; // first spin byte of the instance
+    // bit-packed encoding: word groups ceil(R / 32), words per (group, parity, site) row
+    // (4 * G4), and the instance's first word group in the batch
+    int32_t bp_W, bp_row, bp_wg_base, bp_pad;
 };
 
 enum TileKind { kTileGeneric = 0, kTileFast = 1, kTileBlock = 2 };
@@ -182,6 +185,14 @@ struct DevState {
     // block tile), and a sticky error word (nonzero: a wait gave up)
     int32_t *prog;
     uint32_t *err;
+    // bit-packed encoding: sweep blocks (instance, first item) of every colour, position
+    // blocks (instance, word group, chunk, chunks) for init and energies, per word group
+    // its first position block and their count, and the energy partial sums (per position
+    // block, 32 slots x (2 E_cl, C))
+    const int32_t *bp_sblk;
+    const int32_t *bp_eblk;
+    const int32_t *bp_wg;
+    int64_t *bp_part;
     // mutable state
     uint8_t *spins;
     int64_t *E;       // per replica slot

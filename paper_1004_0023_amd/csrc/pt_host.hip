@@ -60,11 +60,19 @@ struct Plan {
     std::vector<int32_t> n_adj;  // per instance
     int64_t total_reps = 0, total_pairs = 0, spin_bytes = 0;
     int64_t max_tiles = 0;  // tile slots: one per (replica, four-slice group) at most
+    // bit-packed encoding: sweep blocks (n, item0) colour by colour with each colour's
+    // (first block, blocks); position blocks (n, w, chunk, chunks); per word group
+    // (first position block, blocks)
+    int32_t encoding = PT_INT8;
+    std::vector<int32_t> bp_sblk, bp_eblk, bp_wg;
+    std::vector<std::pair<int32_t, int32_t>> bp_colour;
+    int32_t bp_n_eblk = 0;
     int64_t halo_words = 0; // one buffer of slice-block boundary records, at most
     uint64_t flips_per_sweep = 0;
     // byte offsets in the workspace
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
-        o_repinst, o_halo, o_itiles, o_icount, o_prog, o_err;
+        o_repinst, o_halo, o_itiles, o_icount, o_prog, o_err, o_bp_sblk, o_bp_eblk, o_bp_wg,
+        o_bp_part;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr;
@@ -133,12 +141,20 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 // LDS of one gfx950 workgroup; instances whose whole replicas exceed it run as slice blocks
 constexpr int32_t kLdsPerWorkgroup = 163840;
 
-int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, Plan &P)
+// Bit-packed encoding: position blocks per word group (at most this many; each block
+// passes over 64 positions at a time).
+constexpr int32_t kBpMaxChunks = 128;
+constexpr int32_t kBpThreadsHost = 256;
+
+int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t encoding, Plan &P)
 {
     if (!inst || n_inst < 1) return fail(PT_EINVAL, "need at least one instance");
+    if (encoding != PT_INT8 && encoding != PT_BITPACK32) return fail(PT_EINVAL, "unknown encoding");
     P = Plan();
+    P.encoding = encoding;
+    const bool bp = encoding == PT_BITPACK32;
     int64_t rep = 0, pair = 0, adjb = 0, offb = 0, siteb = 0, entb = 0, clsb = 0, tblb = 0,
-            spinb = 0;
+            spinb = 0, wgb = 0;
     for (int n = 0; n < n_inst; ++n) {
         int rc = validate(inst[n], n);
         if (rc) return rc;
@@ -192,6 +208,11 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, Plan &P)
         d.cls_base = (int32_t)clsb;
         d.tbl_base = (int32_t)tblb;
         d.spin_base = spinb;
+        if (bp) {
+            d.bp_W = (in.R + 31) / 32;
+            d.bp_row = 4 * d.G4;
+            d.bp_wg_base = (int32_t)wgb;
+        }
         // sites of each colour, colour by colour
         std::vector<int32_t> cls(in.n_colors + 1, 0);
         for (int i = 0; i < in.N; ++i) cls[in.color[i] + 1]++;
@@ -257,13 +278,54 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, Plan &P)
         entb += d.fast ? (int64_t)in.N * d.D : 0;
         clsb += in.n_colors + 1;
         tblb += (int64_t)in.R * d.tbl_words;
-        spinb += (int64_t)in.R * d.rep_bytes;
+        spinb += bp ? (int64_t)d.bp_W * d.parities * in.N * d.bp_row * 4
+                    : (int64_t)in.R * d.rep_bytes;
+        wgb += d.bp_W;
         if (rep > (1 << 30) || tblb > (1ll << 31) || adjb > (1ll << 31) || entb > (1ll << 31))
             return fail(PT_EINVAL, "batch too large");
     }
     P.total_reps = rep;
     P.total_pairs = pair;
     P.spin_bytes = spinb;
+    if (bp) {
+        // sweep blocks: colour g of every instance that has it, 256 items per block
+        int max_colors = 0;
+        for (const auto &d : P.desc) max_colors = std::max(max_colors, d.n_colors);
+        for (int g = 0; g < max_colors; ++g) {
+            const int32_t first = (int32_t)(P.bp_sblk.size() / 2);
+            for (int n = 0; n < n_inst; ++n) {
+                const InstDesc &d = P.desc[n];
+                if (g >= d.n_colors) continue;
+                const int64_t sg = P.cls_off[d.cls_base + g + 1] - P.cls_off[d.cls_base + g];
+                const int64_t items = (int64_t)d.bp_W * sg * d.G4 * 4;
+                for (int64_t it = 0; it < items; it += kBpThreadsHost) {
+                    P.bp_sblk.push_back(n);
+                    P.bp_sblk.push_back((int32_t)it);
+                }
+                if (items > 0x7fffffff) return fail(PT_EINVAL, "batch too large");
+            }
+            P.bp_colour.emplace_back(first, (int32_t)(P.bp_sblk.size() / 2) - first);
+        }
+        // position blocks of every word group
+        for (int n = 0; n < n_inst; ++n) {
+            const InstDesc &d = P.desc[n];
+            const int64_t Q = (int64_t)d.parities * d.N * d.G4;
+            const int32_t chunks = (int32_t)std::min<int64_t>(kBpMaxChunks, std::max<int64_t>(1, (Q + 63) / 64));
+            for (int w = 0; w < d.bp_W; ++w) {
+                P.bp_wg.push_back((int32_t)(P.bp_eblk.size() / 4));
+                P.bp_wg.push_back(chunks);
+                for (int k = 0; k < chunks; ++k) {
+                    P.bp_eblk.push_back(n);
+                    P.bp_eblk.push_back(w);
+                    P.bp_eblk.push_back(k);
+                    P.bp_eblk.push_back(chunks);
+                }
+            }
+        }
+        P.bp_n_eblk = (int32_t)(P.bp_eblk.size() / 4);
+        if (P.bp_sblk.size() / 2 > 0x7fffffff || P.bp_eblk.size() / 4 > 0x7fffffff)
+            return fail(PT_EINVAL, "batch too large");
+    }
     // layout
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -289,6 +351,10 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, Plan &P)
     P.o_icount = take((size_t)n_inst * 4);  // zero in the uploaded image
     P.o_prog = take((size_t)P.max_tiles * 4);
     P.o_err = take(4);                       // zero in the uploaded image
+    P.o_bp_sblk = take(P.bp_sblk.size() * 4);
+    P.o_bp_eblk = take(P.bp_eblk.size() * 4);
+    P.o_bp_wg = take(P.bp_wg.size() * 4);
+    P.o_bp_part = take((size_t)P.bp_n_eblk * 32 * 2 * 8);
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
     P.o_E = take((size_t)rep * 8);
@@ -611,6 +677,54 @@ int sync_and_check(pt_ctx *c)
     return PT_OK;
 }
 
+// E_cl and C of replicas [rep_first, rep_first + n) from the spins in device memory (the
+// bit-packed encoding recomputes every replica).
+hipError_t energies_from_spins(pt_ctx *c, int rep_first, int n)
+{
+    if (c->plan.encoding == PT_BITPACK32)
+        return launch_bp_energy(c->st, c->plan.bp_n_eblk, (int32_t)c->plan.total_reps, c->stream);
+    return launch_energy(c->st, rep_first, n, c->stream);
+}
+
+// Bit-packed encoding: n_sweeps sweeps as one launch per colour class (parity, colour) of
+// every instance, then E_cl and C of every replica.
+int enqueue_bp_sweep(pt_ctx *c, int n_sweeps)
+{
+    const Plan &P = c->plan;
+    const bool timing = (c->opt.flags & PT_FLAG_TIMING) != 0;
+    int ea = -1, eb = -1;
+    if (timing) {
+        int rc = event_pair(c, ea, eb);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(c->ev_pool[ea], c->stream));
+    }
+    int parities = 1;
+    for (const auto &d : P.desc) parities = std::max(parities, d.parities);
+    BpLaunch L{};
+    L.st = c->st;
+    L.key0 = c->key_flip0;
+    L.key1 = c->key_flip1;
+    for (int sw = 0; sw < n_sweeps; ++sw)
+        for (int p = 0; p < parities; ++p)
+            for (int g = 0; g < (int)P.bp_colour.size(); ++g) {
+                L.sweep_off = sw;
+                L.p = p;
+                L.g = g;
+                L.blk0 = P.bp_colour[g].first;
+                L.n_blocks = P.bp_colour[g].second;  // instances with one parity skip p = 1
+                if (L.n_blocks == 0) continue;
+                const hipError_t e = launch_bp_sweep(L, c->stream);
+                if (e != hipSuccess) return hip_fail(e, "bit-packed sweep launch");
+            }
+    const hipError_t e = energies_from_spins(c, 0, (int)P.total_reps);
+    if (e != hipSuccess) return hip_fail(e, "bit-packed energy launch");
+    if (timing) {
+        HIP_TRY(hipEventRecord(c->ev_pool[eb], c->stream));
+        c->sweep_ev.emplace_back(ea, eb);
+    }
+    return PT_OK;
+}
+
 // n_sweeps sweeps of every tile; with fuse_exchange the tile that completes an instance
 // then runs the instance's exchange step (a PT cycle in one set of launches).
 int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
@@ -718,6 +832,7 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
 int enqueue_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
 {
     if (n_sweeps <= 0) return PT_OK;
+    if (c->plan.encoding == PT_BITPACK32) return enqueue_bp_sweep(c, n_sweeps);
     if (!c->tuning) return enqueue_sweep_once(c, n_sweeps, fuse_exchange);
     const auto shape = c->cand[c->cand_next];
     int rc = build_tiles(c, 0, shape.first);
@@ -774,7 +889,8 @@ constexpr size_t kFuseMaxTiles = 64;
 int enqueue_cycle(pt_ctx *c)
 {
     const int k = c->opt.sweeps_per_exchange;
-    if (c->tiles.size() <= kFuseMaxTiles) return enqueue_sweep(c, k, true);
+    if (c->plan.encoding == PT_INT8 && c->tiles.size() <= kFuseMaxTiles)
+        return enqueue_sweep(c, k, true);
     int rc = enqueue_sweep(c, k, false);
     if (rc) return rc;
     return enqueue_exchange(c, (uint32_t)k);
@@ -798,7 +914,7 @@ int pt_workspace_bytes(const pt_instance *inst, int32_t n_inst, const pt_options
 {
     if (!bytes || !opt) return fail(PT_EINVAL, "null argument");
     Plan P;
-    int rc = make_plan(inst, n_inst, opt->flags, P);
+    int rc = make_plan(inst, n_inst, opt->flags, opt->encoding, P);
     if (rc) return rc;
     *bytes = P.total_bytes;
     return PT_OK;
@@ -812,15 +928,13 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     if (opt->sweeps_per_exchange < 1) return fail(PT_EINVAL, "sweeps_per_exchange must be >= 1");
     if (opt->encoding != PT_INT8 && opt->encoding != PT_BITPACK32)
         return fail(PT_EINVAL, "unknown encoding");
-    if (opt->encoding == PT_BITPACK32)
-        return fail(PT_EINVAL, "PT_BITPACK32 is not built: only PT_INT8 is available");
     if (opt->block_threads < 0 || opt->block_threads > 1024 || (opt->block_threads % 64))
         return fail(PT_EINVAL, "block_threads must be a multiple of 64 in [64, 1024] or 0");
     if (opt->tile_replicas < 0 || opt->tile_bytes < 0)
         return fail(PT_EINVAL, "tile_replicas and tile_bytes must be >= 0");
     pt_ctx *c = new (std::nothrow) pt_ctx();
     if (!c) return fail(PT_ENOMEM, "host allocation failed");
-    int rc = make_plan(inst, n_inst, opt->flags, c->plan);
+    int rc = make_plan(inst, n_inst, opt->flags, opt->encoding, c->plan);
     if (rc) {
         delete c;
         return rc;
@@ -907,6 +1021,10 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.icount = (uint32_t *)(w + P.o_icount);
     st.prog = (int32_t *)(w + P.o_prog);
     st.err = (uint32_t *)(w + P.o_err);
+    st.bp_sblk = (const int32_t *)(w + P.o_bp_sblk);
+    st.bp_eblk = (const int32_t *)(w + P.o_bp_eblk);
+    st.bp_wg = (const int32_t *)(w + P.o_bp_wg);
+    st.bp_part = (int64_t *)(w + P.o_bp_part);
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;
@@ -930,6 +1048,9 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     put(P.o_db, P.db.data(), P.db.size() * 8);
     put(P.o_dK, P.dK.data(), P.dK.size() * 8);
     put(P.o_repinst, P.rep_inst.data(), P.rep_inst.size() * 4);
+    put(P.o_bp_sblk, P.bp_sblk.data(), P.bp_sblk.size() * 4);
+    put(P.o_bp_eblk, P.bp_eblk.data(), P.bp_eblk.size() * 4);
+    put(P.o_bp_wg, P.bp_wg.data(), P.bp_wg.size() * 4);
     for (int n = 0; n < n_inst; ++n) {
         const InstDesc &d = P.desc[n];
         for (int r = 0; r < d.R; ++r) {
@@ -940,15 +1061,23 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     }
     e = hipMemcpyAsync(c->ws, img.data(), P.total_bytes, hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return cleanup(hip_fail(e, "upload"));
-    e = launch_init_spins(st, (int)P.total_reps, c->key_flip0,
-                          c->key_flip1 ^ kDomainInit, c->stream);
-    if (e != hipSuccess) return cleanup(hip_fail(e, "init launch"));
-    e = launch_energy(st, 0, (int)P.total_reps, c->stream);
+    if (P.encoding == PT_BITPACK32) {
+        e = launch_bp_init(st, P.bp_n_eblk, c->key_flip0, c->key_flip1 ^ kDomainInit, c->stream);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "init launch"));
+    } else {
+        e = launch_init_spins(st, (int)P.total_reps, c->key_flip0,
+                              c->key_flip1 ^ kDomainInit, c->stream);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "init launch"));
+    }
+    e = energies_from_spins(c, 0, (int)P.total_reps);
     if (e != hipSuccess) return cleanup(hip_fail(e, "energy launch"));
     c->block_threads = opt->block_threads > 0 ? opt->block_threads : 1024;
-    rc = build_tiles(c, opt->tile_replicas, opt->tile_bytes);
-    if (rc) return cleanup(rc);
-    if (opt->tile_replicas == 0 && opt->tile_bytes == 0 && opt->block_threads == 0) {
+    if (P.encoding == PT_INT8) {
+        rc = build_tiles(c, opt->tile_replicas, opt->tile_bytes);
+        if (rc) return cleanup(rc);
+    }
+    if (P.encoding == PT_INT8 && opt->tile_replicas == 0 && opt->tile_bytes == 0 &&
+        opt->block_threads == 0) {
         for (int tb : {8 * 1024, 16 * 1024, 32 * 1024, 64 * 1024, 128 * 1024})
             for (int th : {256, 512, 1024}) c->cand.emplace_back(tb, th);
         c->cand_ms.assign(c->cand.size(), 0.0);
@@ -1074,6 +1203,18 @@ int pt_observables(pt_ctx *c, int32_t inst, pt_obs *o)
 }
 
 // Device layout of one replica: bytes x = (s + 1)/2 ordered [p][i][m], slice k = 2m + p.
+// Bit-packed encoding: words of an instance, and the word that holds slot r at (k, i).
+static inline int64_t bp_words(const InstDesc &d)
+{
+    return (int64_t)d.bp_W * d.parities * d.N * d.bp_row;
+}
+static inline size_t bp_pos(const InstDesc &d, int r, int k, int i)
+{
+    const int p = (d.M >= 2) ? (k & 1) : 0;
+    const int m = (d.M >= 2) ? (k >> 1) : 0;
+    return (((size_t)(r / 32) * d.parities + p) * d.N + i) * d.bp_row + m;
+}
+
 static inline size_t spin_pos(const InstDesc &d, int k, int i)
 {
     const int p = (d.M >= 2) ? (k & 1) : 0;
@@ -1087,6 +1228,18 @@ int pt_get_spins(pt_ctx *c, int32_t inst, int8_t *out)
     if (rc) return rc;
     if (!out) return fail(PT_EINVAL, "null output");
     const InstDesc &d = c->plan.desc[inst];
+    if (c->plan.encoding == PT_BITPACK32) {
+        std::vector<uint32_t> wb((size_t)bp_words(d));
+        HIP_TRY(hipMemcpyAsync(wb.data(), c->ws + c->plan.o_spins + d.spin_base, wb.size() * 4,
+                               hipMemcpyDeviceToHost, c->stream));
+        if ((rc = sync_and_check(c))) return rc;
+        for (int r = 0; r < d.R; ++r)
+            for (int k = 0; k < d.M; ++k)
+                for (int i = 0; i < d.N; ++i)
+                    out[((size_t)r * d.M + k) * d.N + i] =
+                        (int8_t)(2 * (int)((wb[bp_pos(d, r, k, i)] >> (r & 31)) & 1u) - 1);
+        return PT_OK;
+    }
     std::vector<uint8_t> buf((size_t)d.R * d.rep_bytes);
     HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + c->plan.o_spins + d.spin_base, buf.size(),
                            hipMemcpyDeviceToHost, c->stream));
@@ -1105,17 +1258,30 @@ int pt_set_spins(pt_ctx *c, int32_t inst, const int8_t *in)
     if (rc) return rc;
     if (!in) return fail(PT_EINVAL, "null input");
     const InstDesc &d = c->plan.desc[inst];
-    std::vector<uint8_t> buf((size_t)d.R * d.rep_bytes, 0);
-    for (int r = 0; r < d.R; ++r)
-        for (int k = 0; k < d.M; ++k)
-            for (int i = 0; i < d.N; ++i) {
-                const int8_t v = in[((size_t)r * d.M + k) * d.N + i];
-                if (v != 1 && v != -1) return fail(PT_EINVAL, "spins must be +1 or -1");
-                buf[(size_t)r * d.rep_bytes + spin_pos(d, k, i)] = (uint8_t)((v + 1) / 2);
-            }
-    HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_spins + d.spin_base, buf.data(), buf.size(),
-                           hipMemcpyHostToDevice, c->stream));
-    hipError_t e = launch_energy(c->st, d.rep_base, d.R, c->stream);
+    for (size_t x = 0; x < (size_t)d.R * d.M * d.N; ++x)
+        if (in[x] != 1 && in[x] != -1) return fail(PT_EINVAL, "spins must be +1 or -1");
+    if (c->plan.encoding == PT_BITPACK32) {
+        std::vector<uint32_t> wb((size_t)bp_words(d), 0u);
+        for (int r = 0; r < d.R; ++r)
+            for (int k = 0; k < d.M; ++k)
+                for (int i = 0; i < d.N; ++i)
+                    if (in[((size_t)r * d.M + k) * d.N + i] == 1) wb[bp_pos(d, r, k, i)] |= 1u << (r & 31);
+        HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_spins + d.spin_base, wb.data(), wb.size() * 4,
+                               hipMemcpyHostToDevice, c->stream));
+        // pageable source: the copy has been staged once the stream reaches this point
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<uint8_t> buf((size_t)d.R * d.rep_bytes, 0);
+        for (int r = 0; r < d.R; ++r)
+            for (int k = 0; k < d.M; ++k)
+                for (int i = 0; i < d.N; ++i)
+                    buf[(size_t)r * d.rep_bytes + spin_pos(d, k, i)] =
+                        (uint8_t)((in[((size_t)r * d.M + k) * d.N + i] + 1) / 2);
+        HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_spins + d.spin_base, buf.data(), buf.size(),
+                               hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    hipError_t e = energies_from_spins(c, d.rep_base, d.R);
     if (e != hipSuccess) return hip_fail(e, "energy launch");
     HIP_TRY(hipStreamSynchronize(c->stream));
     return PT_OK;
@@ -1152,8 +1318,11 @@ int pt_load(pt_ctx *c, const void *buf, size_t len)
         h.seed != c->opt.seed || h.flips_per_sweep != c->plan.flips_per_sweep ||
         len != sizeof h + h.state_bytes)
         return fail(PT_ESTATE, "checkpoint belongs to different instances or options");
-    {
-        // every spin byte must be 0 or 1: the kernels index tables with them
+    if (h.encoding != c->opt.encoding)
+        return fail(PT_ESTATE, "checkpoint was written under another spin encoding");
+    if (c->plan.encoding == PT_INT8) {
+        // every spin byte must be 0 or 1: the kernels index tables with them (any bit
+        // pattern is a valid bit-packed state)
         const uint8_t *sp = (const uint8_t *)buf + sizeof h + (c->plan.o_spins - c->plan.o_state);
         for (int64_t b = 0; b < c->plan.spin_bytes; ++b)
             if (sp[b] > 1) return fail(PT_ESTATE, "checkpoint holds invalid spins");
@@ -1187,6 +1356,12 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->sweep_groups = (int32_t)launch_groups(c).size();
     o->block_tiles = c->n_block_tiles;
     o->block_resident = c->block_persistent;
+    o->class_launches = 0;
+    if (c->plan.encoding == PT_BITPACK32) {
+        int parities = 1;
+        for (const auto &d : c->plan.desc) parities = std::max(parities, d.parities);
+        o->class_launches = parities * (int32_t)c->plan.bp_colour.size();
+    }
     return PT_OK;
 }
 

@@ -28,6 +28,14 @@ struct SweepLaunch {
     int32_t wait_polls, wait_extra;
 };
 
+// One colour class (parity p, colour g) of sweep t + sweep_off of every instance in the
+// bit-packed encoding: blocks [blk0, blk0 + n_blocks) of the sweep-block list.
+struct BpLaunch {
+    DevState st;
+    uint32_t key0, key1;
+    int32_t sweep_off, p, g, blk0, n_blocks;
+};
+
 // Each returns the hipError_t of the launch itself (asynchronous execution errors
 // surface at the next synchronisation).
 hipError_t launch_init_spins(const DevState &st, int32_t n_reps, uint32_t key0, uint32_t key1,
@@ -40,6 +48,12 @@ hipError_t launch_block_prepare(const SweepLaunch &L, hipStream_t s);
 hipError_t launch_exchange(const DevState &st, int32_t n_inst, uint32_t key0, uint32_t key1,
                            uint32_t t_add, hipStream_t s);
 hipError_t launch_advance(const DevState &st, int32_t n_inst, uint32_t t_add, hipStream_t s);
+// Bit-packed encoding: initial spins, one colour class of one sweep, and E_cl, C of
+// every replica (n_eblk position blocks, n_reps replica slots).
+hipError_t launch_bp_init(const DevState &st, int32_t n_eblk, uint32_t key0, uint32_t key1,
+                          hipStream_t s);
+hipError_t launch_bp_sweep(const BpLaunch &L, hipStream_t s);
+hipError_t launch_bp_energy(const DevState &st, int32_t n_eblk, int32_t n_reps, hipStream_t s);
 hipError_t launch_threshold_eval(const double *dS, uint32_t *out, int32_t n, hipStream_t s);
 hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes);
 // Slice-block workgroups of `threads` threads and `lds_bytes` of LDS that one compute unit

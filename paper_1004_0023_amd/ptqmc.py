@@ -69,7 +69,8 @@ class _Info(C.Structure):
                 ("flips_per_sweep", C.c_uint64), ("sweep_ms", C.c_double),
                 ("sweep_launches", C.c_int64), ("exchange_ms", C.c_double),
                 ("exchange_launches", C.c_int64), ("sweep_groups", C.c_int32),
-                ("block_tiles", C.c_int32), ("block_resident", C.c_int32)]
+                ("block_tiles", C.c_int32), ("block_resident", C.c_int32),
+                ("class_launches", C.c_int32)]
 
 
 _lib = None

@@ -67,7 +67,7 @@ def _ws_bytes(inst_list, ptqmc, **kw):
         keep += arrs
         recs[n] = ptqmc._Instance(inst.N, inst.M, inst.R, E, inst.n_colors,
                                   *[a.ctypes.data for a in arrs])
-    opt = ptqmc._Options(1, kw.get("k", 1), 0, 0, 0, 0, 0)
+    opt = ptqmc._Options(1, kw.get("k", 1), kw.get("encoding", 0), 0, 0, 0, 0)
     nb = C.c_size_t(0)
     rc = L.pt_workspace_bytes(C.cast(recs, C.c_void_p), len(inst_list), C.byref(opt), C.byref(nb))
     return rc, int(nb.value), L.pt_last_error().decode()
@@ -79,6 +79,21 @@ def test_workspace_size_of_workloads():
     assert rc == 0 and nb > 1024
     rc, nb2, _ = _ws_bytes([W.config2()], ptqmc)
     assert rc == 0 and nb2 > 32 * 64 * 128
+
+
+def test_bitpacked_workspace_is_smaller():
+    """The bit-packed encoding keeps 32 replica slots per word: the config-4 lattice
+    (64 replicas of 1024 x 256 spins, 16 MiB as bytes) needs 2 MiB of spin words, and the
+    workspace shrinks by about that difference; an unknown encoding is refused."""
+    ptqmc = _lib()
+    inst = W.config4()
+    rc8, nb8, _ = _ws_bytes([inst], ptqmc, encoding=ptqmc.PT_INT8)
+    rcb, nbb, _ = _ws_bytes([inst], ptqmc, encoding=ptqmc.PT_BITPACK32)
+    assert rc8 == 0 and rcb == 0
+    spins8, spinsb = 64 * 1024 * 256, 2 * 2 * 1024 * 128 * 4
+    assert nb8 - nbb > 0.9 * (spins8 - spinsb)
+    rc, _, msg = _ws_bytes([inst], ptqmc, encoding=7)
+    assert rc == ptqmc.PT_EINVAL
 
 
 @pytest.mark.parametrize("mutate,needle", [
