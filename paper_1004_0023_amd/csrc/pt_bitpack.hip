@@ -13,14 +13,15 @@
 //   bp_energy_part   E_cl and C partial sums per block of positions
 //   bp_energy_sum    E_cl and C of every replica slot from the partial sums
 //
-// Work items.  A thread serves a quarter j (8 slots) of one word group at one
-// four-slice group; the four quarters of a word are neighbouring lanes and combine their
-// results with lane shuffles, and lane j = 0 writes the word.
-//   sweep:  per instance and colour g, item = ((w * Sg + si) * G4 + g4) * 4 + j for the
-//           si-th of the class's Sg sites; a sweep block is 256 consecutive items.
+// Work items.  A lane serves a part j of one word group at one four-slice group; the lanes
+// of a word are neighbours, combine their results with lane shuffles, and lane j = 0
+// writes the word.
+//   sweep:  per instance and colour g, item = ((w * Sg + si) * G4 + g4) * 8 + j (4 slots
+//           per lane) for the si-th of the class's Sg sites; a sweep block is 256
+//           consecutive items.
 //   init, energy: per (instance, word group) the positions (p, i, g4) in the order
-//           pos = (p * N + i) * G4 + g4, four lanes each; position block `chunk` of
-//           `chunks` takes pos = chunk * 64 + lane / 4 + k * 64 * chunks.
+//           pos = (p * N + i) * G4 + g4, four lanes of 8 slots each; position block
+//           `chunk` of `chunks` takes pos = chunk * 64 + lane / 4 + k * 64 * chunks.
 #include "pt_internal.h"
 
 #pragma clang fp contract(off)
@@ -105,6 +106,27 @@ __global__ void __launch_bounds__(kBpThreads) bp_init_kernel(DevState st, uint32
 
 // ------------------------------------------------------------------ sweep
 
+// OR over the eight lanes of an octet (lanes 8q .. 8q+7); every lane of it must call it.
+__device__ __forceinline__ uint32_t octet_or(uint32_t v)
+{
+    v |= __shfl_xor(v, 1, 64);
+    v |= __shfl_xor(v, 2, 64);
+    v |= __shfl_xor(v, 4, 64);
+    return v;
+}
+
+// Byte spread of 4 bits: bit r of v becomes bit 0 of byte r (v * (1 + 2^7 + 2^14 + 2^21)
+// moves bit r by 7r, and only r = k lands on bit 8k).
+__device__ __forceinline__ uint32_t spread4(uint32_t v)
+{
+    return (v * 0x00204081u) & 0x01010101u;
+}
+
+// One colour class (p, g) of one sweep.  A lane serves kBpSweepLanes-th of a word group
+// (kBpSlots = 4 slots) at one four-slice group: item = ((w * Sg + si) * G4 + g4) * 8 + j,
+// the eight lanes of a word are neighbouring and OR their flip masks together.
+constexpr int kBpSlots = 32 / kBpSweepLanes;
+
 __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
 {
     const DevState &st = L.st;
@@ -117,9 +139,9 @@ __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
     const int Sg = st.cls_off[d.cls_base + g + 1] - cls0;
     const int G4 = d.G4, Mh = d.Mh, F = d.F;
     const int item = blk.y + (int)threadIdx.x;
-    const bool valid = item < d.bp_W * Sg * G4 * 4;  // a whole quad is valid or not
-    const int j = item & 3;
-    int rest = item >> 2;
+    const bool valid = item < d.bp_W * Sg * G4 * kBpSweepLanes;  // a whole octet or none
+    const int j = item % kBpSweepLanes;
+    int rest = item / kBpSweepLanes;
     const int g4 = rest % G4;
     rest /= G4;
     const int si = rest % Sg;
@@ -140,35 +162,57 @@ __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
             for (int b = 0; b < 4; ++b)
                 if (4 * g4 + b < Mh) time_words(orow, o, g4, p, Mh, 4 * g4 + b, tlo[b], thi[b]);
         }
-        // spatial field f = h_i + sum_j J_ij s_j for the 8 slots x 4 slices of this lane:
-        // f = h_i - sum_j J_ij + 2 sum_j J_ij x_j
+        // spatial field f = h_i + sum_j J_ij s_j for the 4 slots x 4 slices of this lane
         const int32_t *off = st.adj_off + d.off_base;
         const int32_t *adj = st.adj + d.adj_base;
-        const int sh = 8 * j;
-        int f[4][8];
-        int base = st.hfield[d.site_base + i];
-        for (int e = off[i]; e < off[i + 1]; ++e) base -= adj[e] >> 16;
+        const int sh = kBpSlots * j;
+        int f[4][kBpSlots];
+        if (F <= 127) {
+            // f = h_i - sum_j |J_ij| + 2 sum_j |J_ij| [x_j == (J_ij > 0)]: the sum runs in
+            // one byte per slot (it is at most F), the lane's 4 slots in one word per slice
+            int base = st.hfield[d.site_base + i];
+            uint32_t acc[4] = {0u, 0u, 0u, 0u};
+            for (int e = off[i]; e < off[i + 1]; ++e) {
+                const int a = adj[e];
+                const int J = a >> 16;
+                const uint32_t aJ = (uint32_t)(J < 0 ? -J : J);
+                const uint32_t neg = J < 0 ? 0xFu : 0u;
+                base -= (int)aJ;
+                const uint4 Y = *reinterpret_cast<const uint4 *>(bp_rowp(st, d, w, p, a & 0xFFFF) + 4 * g4);
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < 4; ++b)
+                    acc[b] += aJ * spread4(((word_of(Y, b) >> sh) & 0xFu) ^ neg);
+            }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) f[b][r] = base;
-        for (int e = off[i]; e < off[i + 1]; ++e) {
-            const int a = adj[e];
-            const int J2 = 2 * (a >> 16);
-            const uint4 Y = *reinterpret_cast<const uint4 *>(bp_rowp(st, d, w, p, a & 0xFFFF) + 4 * g4);
+            for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint32_t y = word_of(Y, b) >> sh;
+                for (int r = 0; r < kBpSlots; ++r) f[b][r] = base + 2 * (int)((acc[b] >> (8 * r)) & 0xFFu);
+        } else {
+            // f = h_i - sum_j J_ij + 2 sum_j J_ij x_j, slot by slot
+            int base = st.hfield[d.site_base + i];
+            for (int e = off[i]; e < off[i + 1]; ++e) base -= adj[e] >> 16;
 #pragma unroll
-                for (int r = 0; r < 8; ++r) f[b][r] += J2 * (int)((y >> r) & 1u);
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int r = 0; r < kBpSlots; ++r) f[b][r] = base;
+            for (int e = off[i]; e < off[i + 1]; ++e) {
+                const int a = adj[e];
+                const int J2 = 2 * (a >> 16);
+                const uint4 Y = *reinterpret_cast<const uint4 *>(bp_rowp(st, d, w, p, a & 0xFFFF) + 4 * g4);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t y = word_of(Y, b) >> sh;
+#pragma unroll
+                    for (int r = 0; r < kBpSlots; ++r) f[b][r] += J2 * (int)((y >> r) & 1u);
+                }
             }
         }
         const uint32_t tt = (uint32_t)(st.ctr[n].t + (uint64_t)L.sweep_off);
         const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)g4;
         const int bstride = 2 * F + 1;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int c = 32 * w + 8 * j + r;
+        for (int r = 0; r < kBpSlots; ++r) {
+            const int c = 32 * w + sh + r;
             if (c >= d.R) break;
             const uint32_t *tb = st.tbl + d.tbl_base + (int64_t)st.rung_of[d.rep_base + c] * d.tbl_words;
             const Words4 u = philox10(ctr0, tt, (uint32_t)c, (uint32_t)n, L.key0, L.key1);
@@ -184,7 +228,7 @@ __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
         }
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) flip[b] = quad_or(flip[b]);
+    for (int b = 0; b < 4; ++b) flip[b] = octet_or(flip[b]);
     if (valid && j == 0 && (flip[0] | flip[1] | flip[2] | flip[3]))
         *reinterpret_cast<uint4 *>(own) = make_uint4(X.x ^ flip[0], X.y ^ flip[1], X.z ^ flip[2], X.w ^ flip[3]);
 }

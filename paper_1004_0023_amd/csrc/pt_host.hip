@@ -297,7 +297,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
                 const InstDesc &d = P.desc[n];
                 if (g >= d.n_colors) continue;
                 const int64_t sg = P.cls_off[d.cls_base + g + 1] - P.cls_off[d.cls_base + g];
-                const int64_t items = (int64_t)d.bp_W * sg * d.G4 * 4;
+                const int64_t items = (int64_t)d.bp_W * sg * d.G4 * kBpSweepLanes;
                 for (int64_t it = 0; it < items; it += kBpThreadsHost) {
                     P.bp_sblk.push_back(n);
                     P.bp_sblk.push_back((int32_t)it);

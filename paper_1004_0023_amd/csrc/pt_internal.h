@@ -28,6 +28,9 @@ struct SweepLaunch {
     int32_t wait_polls, wait_extra;
 };
 
+// Lanes per 32-slot word in the bit-packed sweep (each serves 32 / kBpSweepLanes slots).
+constexpr int kBpSweepLanes = 8;
+
 // One colour class (parity p, colour g) of sweep t + sweep_off of every instance in the
 // bit-packed encoding: blocks [blk0, blk0 + n_blocks) of the sweep-block list.
 struct BpLaunch {
