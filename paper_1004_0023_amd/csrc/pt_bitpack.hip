@@ -166,7 +166,14 @@ __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
         const int32_t *off = st.adj_off + d.off_base;
         const int32_t *adj = st.adj + d.adj_base;
         const int sh = kBpSlots * j;
+        const uint32_t tt = (uint32_t)(st.ctr[n].t + (uint64_t)L.sweep_off);
+        const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)g4;
+        const int bstride = 2 * F + 1;
         int f[4][kBpSlots];
+        // table index (x (2F+1) + f + F) * 3 + tau of every (slice, slot): with F <= 20 it
+        // is below 256 and is formed for the lane's 4 slots at once, one byte each
+        uint32_t idx4[4] = {0u, 0u, 0u, 0u};
+        const bool byte_index = F <= 20;
         if (F <= 127) {
             // f = h_i - sum_j |J_ij| + 2 sum_j |J_ij| [x_j == (J_ij > 0)]: the sum runs in
             // one byte per slot (it is at most F), the lane's 4 slots in one word per slice
@@ -183,10 +190,24 @@ __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
                 for (int b = 0; b < 4; ++b)
                     acc[b] += aJ * spread4(((word_of(Y, b) >> sh) & 0xFu) ^ neg);
             }
+            if (byte_index) {
+                // V = x (2F+1) + f + F = x (2F+1) + (base + F) + 2 acc, with base + F >= 0
+                // (|h_i| + sum_j |J_ij| <= F) and V <= 4F + 1, so no byte carries over
+                const uint32_t bF = (uint32_t)(base + F) * 0x01010101u;
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t xb = spread4((word_of(X, b) >> sh) & 0xFu);
+                    const uint32_t tb4 = (d.M >= 2) ? spread4((tlo[b] >> sh) & 0xFu) + spread4((thi[b] >> sh) & 0xFu)
+                                                    : 0x01010101u;
+                    const uint32_t V = xb * (uint32_t)bstride + bF + 2u * acc[b];
+                    idx4[b] = V * 3u + tb4;
+                }
+            } else {
 #pragma unroll
-                for (int r = 0; r < kBpSlots; ++r) f[b][r] = base + 2 * (int)((acc[b] >> (8 * r)) & 0xFFu);
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int r = 0; r < kBpSlots; ++r) f[b][r] = base + 2 * (int)((acc[b] >> (8 * r)) & 0xFFu);
+            }
         } else {
             // f = h_i - sum_j J_ij + 2 sum_j J_ij x_j, slot by slot
             int base = st.hfield[d.site_base + i];
@@ -207,9 +228,6 @@ __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
                 }
             }
         }
-        const uint32_t tt = (uint32_t)(st.ctr[n].t + (uint64_t)L.sweep_off);
-        const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)g4;
-        const int bstride = 2 * F + 1;
 #pragma unroll
         for (int r = 0; r < kBpSlots; ++r) {
             const int c = 32 * w + sh + r;
@@ -220,9 +238,14 @@ __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 if (4 * g4 + b >= Mh) break;
-                const int x = (int)((word_of(X, b) >> bit) & 1u);
-                const int tau = (d.M >= 2) ? (int)((tlo[b] >> bit) & 1u) + (int)((thi[b] >> bit) & 1u) : 1;
-                const int idx = (x * bstride + f[b][r] + F) * 3 + tau;
+                int idx;
+                if (byte_index) {
+                    idx = (int)((idx4[b] >> (8 * r)) & 0xFFu);
+                } else {
+                    const int x = (int)((word_of(X, b) >> bit) & 1u);
+                    const int tau = (d.M >= 2) ? (int)((tlo[b] >> bit) & 1u) + (int)((thi[b] >> bit) & 1u) : 1;
+                    idx = (x * bstride + f[b][r] + F) * 3 + tau;
+                }
                 if (u.w[b] <= tb[idx]) flip[b] |= 1u << bit;
             }
         }
@@ -324,22 +347,31 @@ __global__ void __launch_bounds__(kBpThreads) bp_energy_part_kernel(DevState st)
     }
 }
 
-__global__ void bp_energy_sum_kernel(DevState st, int32_t n_reps)
+// One wave per replica slot: its lanes stride over the word group's position blocks.
+__global__ void __launch_bounds__(kBpThreads) bp_energy_sum_kernel(DevState st, int32_t n_reps)
 {
-    const int gr = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gr >= n_reps) return;
+    const int gr = blockIdx.x * (kBpThreads / 64) + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (gr >= n_reps) return;  // the whole wave
     const int n = st.rep_inst[gr];
     const InstDesc d = st.inst[n];
     const int c = gr - d.rep_base;
     const int2 wg = reinterpret_cast<const int2 *>(st.bp_wg)[d.bp_wg_base + c / 32];
     long long e2 = 0, cc = 0;
-    for (int b = 0; b < wg.y; ++b) {
+    for (int b = lane; b < wg.y; b += 64) {
         const int64_t at = ((int64_t)(wg.x + b) * 32 + (c & 31)) * 2;
         e2 += st.bp_part[at];
         cc += st.bp_part[at + 1];
     }
-    st.E[gr] = e2 / 2;
-    st.C[gr] = cc;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        e2 += __shfl_xor(e2, o, 64);
+        cc += __shfl_xor(cc, o, 64);
+    }
+    if (lane == 0) {
+        st.E[gr] = e2 / 2;
+        st.C[gr] = cc;
+    }
 }
 
 }  // namespace
@@ -365,7 +397,9 @@ hipError_t launch_bp_energy(const DevState &st, int32_t n_eblk, int32_t n_reps, 
     hipLaunchKernelGGL(bp_energy_part_kernel, dim3(n_eblk), dim3(kBpThreads), 0, s, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bp_energy_sum_kernel, dim3((n_reps + 255) / 256), dim3(256), 0, s, st, n_reps);
+    const int per_block = kBpThreads / 64;
+    hipLaunchKernelGGL(bp_energy_sum_kernel, dim3((n_reps + per_block - 1) / per_block),
+                       dim3(kBpThreads), 0, s, st, n_reps);
     return hipGetLastError();
 }
 

@@ -143,7 +143,7 @@ constexpr int32_t kLdsPerWorkgroup = 163840;
 
 // Bit-packed encoding: position blocks per word group (at most this many; each block
 // passes over 64 positions at a time).
-constexpr int32_t kBpMaxChunks = 128;
+constexpr int32_t kBpMaxChunks = 1024;
 constexpr int32_t kBpThreadsHost = 256;
 
 int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t encoding, Plan &P)
