@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: the oracle is imported by the test-suite, by the smoke
 and by the CPU-baseline leg of the benchmark, never by the product library.  It is an
 independent, slow, obviously-correct statement of what the sampler computes: Philox
 draws, the deterministic exponential, Metropolis single-spin sweeps in colour-class
-order, even/odd replica exchange, round-trip labels and per-rung accumulators.
+order, even/odd replica exchange, round-trip labels and per-rung accumulators
+(including the imaginary-time spin correlations at TAU_LAGS Trotter lags).
 
 The oracle handles one instance at a time; the instance number ``index`` enters every
 random counter, so instance n of a batch is reproduced by passing ``index = n``.
@@ -20,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ptoracle.c")
+TAU_LAGS = 8  # imaginary-time correlation lags per rung (OR_TAU_LAGS)
 _LIB = os.path.join(_HERE, "libptoracle.so")
 
 LABEL_NONE, LABEL_UP, LABEL_DOWN = 0, 1, 2
@@ -45,7 +47,7 @@ class _Inst(C.Structure):
 class _State(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("s", "rung_of", "replica_of", "E", "C", "label", "rt",
                                           "acc", "att", "sumE", "sumC", "sumE2", "sumC2",
-                                          "nup", "ndown", "counters")]
+                                          "nup", "ndown", "counters", "sumCt")]
 
 
 _lib = None
@@ -79,6 +81,9 @@ def lib():
         L.or_exchange.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64]
         L.or_run.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32, C.c_int32]
         L.or_run.restype = C.c_int
+        L.or_tau_lag.argtypes = [C.c_int32, C.c_int32]
+        L.or_tau_lag.restype = C.c_int32
+        L.or_tau_corr.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -93,6 +98,11 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     lib().or_philox4x32_10(_p(c), _p(k), _p(out))
     return out
+
+
+def tau_lag(M: int, l: int) -> int:
+    """Lag l of the imaginary-time correlations, in slices (or_tau_lag)."""
+    return int(lib().or_tau_lag(int(M), int(l)))
 
 
 def exp_det(x: float) -> float:
@@ -121,7 +131,7 @@ class OracleChain:
     permutation, counters, labels, swap statistics and per-rung accumulators."""
 
     ARRAYS = ("s", "rung_of", "replica_of", "E", "C", "label", "rt", "acc", "att",
-              "sumE", "sumC", "sumE2", "sumC2", "nup", "ndown", "counters")
+              "sumE", "sumC", "sumE2", "sumC2", "nup", "ndown", "counters", "sumCt")
 
     def __init__(self, inst, seed: int, index: int = 0, init: bool = True):
         self.inst = inst
@@ -156,6 +166,7 @@ class OracleChain:
         self.nup = np.zeros(R, dtype=np.uint64)
         self.ndown = np.zeros(R, dtype=np.uint64)
         self.counters = np.zeros(3, dtype=np.uint64)
+        self.sumCt = np.zeros((R, TAU_LAGS), dtype=np.int64)
         self._bind()
         if init:
             lib().or_init(C.byref(self._inst), C.byref(self._state), self.seed)
@@ -215,7 +226,17 @@ class OracleChain:
                     att=self.att[:R - 1].copy(), roundtrips=self.rt.copy(),
                     label=self.label.copy(), sumE=self.sumE.copy(), sumC=self.sumC.copy(),
                     sumE2=self.sumE2.copy(), sumC2=self.sumC2.copy(), nup=self.nup.copy(),
-                    ndown=self.ndown.copy(), t=self.t, e=self.e, n_acc=self.n_acc)
+                    ndown=self.ndown.copy(), sumCt=self.sumCt.copy(), t=self.t, e=self.e,
+                    n_acc=self.n_acc)
+
+    def tau_corr(self, spins: np.ndarray = None) -> np.ndarray:
+        """Ct_l of every replica slot [R][TAU_LAGS] (or_tau_corr)."""
+        s = self.s if spins is None else np.ascontiguousarray(spins, dtype=np.int8)
+        out = np.zeros((self.inst.R, TAU_LAGS), dtype=np.int64)
+        per = self.inst.M * self.inst.N
+        for c in range(self.inst.R):
+            lib().or_tau_corr(C.byref(self._inst), _p(s.reshape(-1)[c * per:]), _p(out[c]))
+        return out
 
 
 def energy_estimators(obs, inst):

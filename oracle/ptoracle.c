@@ -36,6 +36,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Imaginary-time correlation lags accumulated per rung (see or_tau_lag). */
+#define OR_TAU_LAGS 8
+
 #define OR_LABEL_NONE 0
 #define OR_LABEL_UP 1
 #define OR_LABEL_DOWN 2
@@ -69,6 +72,8 @@ typedef struct {
     uint64_t *nup, *ndown; /* [R] by rung: exchange steps at which the replica there was
                               labelled UP / DOWN */
     uint64_t *counters;  /* [0] sweeps t, [1] exchange steps e, [2] n_acc */
+    int64_t *sumCt;      /* [R][OR_TAU_LAGS] by rung: sum over exchange steps of the
+                            replica's Ct_l (or_tau_corr) */
 } or_state;
 
 /* ------------------------------------------------------------------ Philox4x32-10 */
@@ -278,6 +283,36 @@ void or_energies(const or_instance *in, const int8_t *s, int64_t *E, int64_t *C)
     }
 }
 
+/* ------------------------------------------------------------------ imaginary time */
+
+/* Lag l (0 <= l < OR_TAU_LAGS) of the imaginary-time correlations, in slices:
+ * max(1, floor((l + 1) M / 16)), i.e. 1/16 .. 1/2 of the Trotter direction in eighths. */
+int32_t or_tau_lag(int32_t M, int32_t l)
+{
+    int32_t d = (l + 1) * M / 16;
+    return d < 1 ? 1 : d;
+}
+
+/* Ct_l = sum_k sum_i s_i^k s_i^{(k + lag_l) mod M} of one replica s[M][N]: the spin
+ * autocorrelation along the Trotter direction.  Divided by N M it estimates
+ * (1/N) sum_i <sigma^z_i(tau) sigma^z_i(0)> at imaginary time tau = lag * beta / M, the
+ * correlation whose decay gives the gap above the ground state (the quantity the
+ * paper's application, AQUA, computes; Section 1 and its reference [14]). */
+void or_tau_corr(const or_instance *in, const int8_t *s, int64_t *out)
+{
+    int32_t N = in->N, M = in->M;
+    for (int32_t l = 0; l < OR_TAU_LAGS; ++l) {
+        int32_t lag = or_tau_lag(M, l);
+        int64_t acc = 0;
+        for (int32_t k = 0; k < M; ++k) {
+            int32_t k2 = (k + lag) % M;
+            for (int32_t i = 0; i < N; ++i)
+                acc += (int64_t)s[(size_t)k * N + i] * s[(size_t)k2 * N + i];
+        }
+        out[l] = acc;
+    }
+}
+
 /* ------------------------------------------------------------------ init */
 
 void or_init(const or_instance *in, or_state *st, uint64_t seed)
@@ -294,6 +329,7 @@ void or_init(const or_instance *in, or_state *st, uint64_t seed)
         st->rt[r] = 0;
         st->sumE[r] = st->sumC[r] = st->sumE2[r] = st->sumC2[r] = 0;
         st->nup[r] = st->ndown[r] = 0;
+        for (int32_t l = 0; l < OR_TAU_LAGS; ++l) st->sumCt[(size_t)r * OR_TAU_LAGS + l] = 0;
     }
     for (int32_t r = 0; r + 1 < R; ++r) st->acc[r] = st->att[r] = 0;
     st->counters[0] = st->counters[1] = st->counters[2] = 0;
@@ -428,6 +464,9 @@ void or_exchange(const or_instance *in, or_state *st, uint64_t seed)
         st->sumC[r] += st->C[c];
         st->sumE2[r] += st->E[c] * st->E[c];
         st->sumC2[r] += st->C[c] * st->C[c];
+        int64_t ct[OR_TAU_LAGS];
+        or_tau_corr(in, st->s + (size_t)c * in->M * in->N, ct);
+        for (int32_t l = 0; l < OR_TAU_LAGS; ++l) st->sumCt[(size_t)r * OR_TAU_LAGS + l] += ct[l];
     }
     st->counters[2] += 1;
     st->counters[1] = e + 1;
