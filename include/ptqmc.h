@@ -76,6 +76,14 @@ extern "C" {
                            reads and writes the packed words in device memory; the chain
                            is the same as under PT_INT8                                  */
 
+/* Imaginary-time correlation lags: with PT_FLAG_TAU_CORR every exchange step adds, for
+ * each rung r and l < PT_TAU_LAGS, Ct_l = sum_k sum_i s_i^k s_i^{(k + lag_l) mod M} of
+ * the replica at rung r to sumCt[r][l], lag_l = max(1, floor((l + 1) M / 16)) slices.
+ * Ct_l / (N M) estimates (1/N) sum_i <sigma^z_i(tau) sigma^z_i(0)> at imaginary time
+ * tau = lag_l beta / M, whose decay gives the gap above the ground state (the quantity
+ * the paper's application computes, Section 1). */
+#define PT_TAU_LAGS 8
+
 /* round-trip labels */
 #define PT_LABEL_NONE 0
 #define PT_LABEL_UP 1
@@ -94,6 +102,8 @@ extern "C" {
 #define PT_FLAG_BLOCK_LAUNCH_PER_SWEEP 0x20u /* slice blocks: one launch per sweep even when
                                           all blocks could be resident at once (same
                                           chain; a measurement and test hook)          */
+#define PT_FLAG_TAU_CORR 0x80u     /* accumulate imaginary-time spin correlations per rung
+                                      at every exchange step (pt_obs.sumCt); PT_INT8 only */
 #define PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT 0x40u /* test hook: resident slice blocks wait for a
                                           progress count that never comes, under a tiny
                                           poll bound, so every wait gives up and the next
@@ -149,6 +159,7 @@ typedef struct {
                                  labelled UP / DOWN (feedback-optimised ladders use
                                  f(r) = nup / (nup + ndown))                          */
     uint64_t t, e, n_acc;     /* sweeps done, exchange steps done, accumulated samples */
+    int64_t *sumCt;           /* [R][PT_TAU_LAGS] by rung (zero without PT_FLAG_TAU_CORR) */
 } pt_obs;
 
 /* Launch and timing record of a context. */

@@ -111,6 +111,9 @@ __host__ __device__ __forceinline__ int table_words(int F) { return 2 * (2 * F +
 // ordered [p][i][m] with slice k = 2m + p (parity-split, slice-minor): the Mh = M/2
 // slices of one parity of one site are contiguous, so a 32-bit word holds the four
 // same-parity slices that one Philox call serves.  M == 1: one parity, Mh = 1.
+// Imaginary-time correlation lags per rung (PT_TAU_LAGS of the C ABI).
+constexpr int kTauLags = 8;
+
 struct InstDesc {
     int32_t N, M, R;
     int32_t Mh;        // slices per parity
@@ -202,6 +205,7 @@ struct DevState {
     uint64_t *rt;
     int32_t *replica_of;  // per rung
     int64_t *sumE, *sumC, *sumE2, *sumC2;
+    int64_t *sumCt;       // per rung x kTauLags: imaginary-time correlations
     uint64_t *nup, *ndown;  // per rung: exchange steps with an UP / DOWN replica there
     uint64_t *acc, *att;  // per pair
     Counters *ctr;        // per instance

@@ -75,7 +75,7 @@ struct Plan {
         o_bp_part;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
-        o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr;
+        o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr, o_sumCt;
     size_t state_bytes, total_bytes;
 };
 
@@ -367,6 +367,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
     P.o_sumC = take((size_t)rep * 8);
     P.o_sumE2 = take((size_t)rep * 8);
     P.o_sumC2 = take((size_t)rep * 8);
+    P.o_sumCt = take((size_t)rep * PT_TAU_LAGS * 8);
     P.o_nup = take((size_t)rep * 8);
     P.o_ndown = take((size_t)rep * 8);
     P.o_acc = take((size_t)pair * 8);
@@ -886,14 +887,30 @@ int enqueue_exchange(pt_ctx *c, uint32_t t_add)
 // 7797 tiles -9 %).
 constexpr size_t kFuseMaxTiles = 64;
 
+static_assert(kTauLags == PT_TAU_LAGS, "device and ABI correlation lags differ");
+
+// With PT_FLAG_TAU_CORR: after an exchange step, the imaginary-time correlations of
+// every replica at its new rung.
+int enqueue_tau_corr(pt_ctx *c)
+{
+    if (!(c->opt.flags & PT_FLAG_TAU_CORR)) return PT_OK;
+    const hipError_t e = launch_tau_corr(c->st, (int32_t)c->plan.total_reps, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "correlation launch");
+    return PT_OK;
+}
+
 int enqueue_cycle(pt_ctx *c)
 {
     const int k = c->opt.sweeps_per_exchange;
-    if (c->plan.encoding == PT_INT8 && c->tiles.size() <= kFuseMaxTiles)
-        return enqueue_sweep(c, k, true);
-    int rc = enqueue_sweep(c, k, false);
+    int rc;
+    if (c->plan.encoding == PT_INT8 && c->tiles.size() <= kFuseMaxTiles) {
+        rc = enqueue_sweep(c, k, true);
+    } else {
+        rc = enqueue_sweep(c, k, false);
+        if (rc == PT_OK) rc = enqueue_exchange(c, (uint32_t)k);
+    }
     if (rc) return rc;
-    return enqueue_exchange(c, (uint32_t)k);
+    return enqueue_tau_corr(c);
 }
 
 int check_inst(pt_ctx *c, int32_t inst)
@@ -928,6 +945,8 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     if (opt->sweeps_per_exchange < 1) return fail(PT_EINVAL, "sweeps_per_exchange must be >= 1");
     if (opt->encoding != PT_INT8 && opt->encoding != PT_BITPACK32)
         return fail(PT_EINVAL, "unknown encoding");
+    if (opt->encoding == PT_BITPACK32 && (opt->flags & PT_FLAG_TAU_CORR))
+        return fail(PT_EINVAL, "PT_FLAG_TAU_CORR needs PT_INT8 spins");
     if (opt->block_threads < 0 || opt->block_threads > 1024 || (opt->block_threads % 64))
         return fail(PT_EINVAL, "block_threads must be a multiple of 64 in [64, 1024] or 0");
     if (opt->tile_replicas < 0 || opt->tile_bytes < 0)
@@ -1009,6 +1028,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.sumC = (int64_t *)(w + P.o_sumC);
     st.sumE2 = (int64_t *)(w + P.o_sumE2);
     st.sumC2 = (int64_t *)(w + P.o_sumC2);
+    st.sumCt = (int64_t *)(w + P.o_sumCt);
     st.nup = (uint64_t *)(w + P.o_nup);
     st.ndown = (uint64_t *)(w + P.o_ndown);
     st.acc = (uint64_t *)(w + P.o_acc);
@@ -1108,7 +1128,9 @@ int pt_sweep(pt_ctx *c, int32_t n_sweeps)
 int pt_exchange(pt_ctx *c)
 {
     if (!c) return fail(PT_EINVAL, "null context");
-    return enqueue_exchange(c, 0);
+    int rc = enqueue_exchange(c, 0);
+    if (rc) return rc;
+    return enqueue_tau_corr(c);
 }
 
 int pt_run(pt_ctx *c, int32_t n_cycles)
@@ -1192,6 +1214,8 @@ int pt_observables(pt_ctx *c, int32_t inst, pt_obs *o)
     if ((rc = get(o->sumC2, P.o_sumC2 + (size_t)b * 8, (size_t)R * 8))) return rc;
     if ((rc = get(o->nup, P.o_nup + (size_t)b * 8, (size_t)R * 8))) return rc;
     if ((rc = get(o->ndown, P.o_ndown + (size_t)b * 8, (size_t)R * 8))) return rc;
+    if ((rc = get(o->sumCt, P.o_sumCt + (size_t)b * PT_TAU_LAGS * 8, (size_t)R * PT_TAU_LAGS * 8)))
+        return rc;
     if ((rc = get(&ctr, P.o_ctr + (size_t)inst * sizeof(Counters), sizeof(Counters)))) return rc;
     if ((rc = sync_and_check(c))) return rc;
     if (o->label)

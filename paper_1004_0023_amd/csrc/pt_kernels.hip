@@ -1420,6 +1420,62 @@ __global__ void exchange_kernel(DevState st, uint32_t key0, uint32_t key1, uint3
     exchange_instance(st, blockIdx.x, key0, key1, t_add);
 }
 
+// ------------------------------------------------------------------ imaginary time
+
+// Lag l of the imaginary-time correlations, in slices: max(1, floor((l + 1) M / 16)).
+__device__ __forceinline__ int tau_lag(int M, int l)
+{
+    const int d = (l + 1) * M / 16;
+    return d < 1 ? 1 : d;
+}
+
+constexpr int kTauChunks = 16;  // workgroups per replica
+
+// Ct_l = sum_k sum_i s_i^k s_i^{(k + lag_l) mod M} of replica (blockIdx.x) over the
+// positions (k, i) of chunk blockIdx.y, added to sumCt of the replica's rung.
+__global__ void __launch_bounds__(256) tau_corr_kernel(DevState st)
+{
+    __shared__ long long red[4][kTauLags];
+    const int g = blockIdx.x;
+    const int n = st.rep_inst[g];
+    const InstDesc d = st.inst[n];
+    const int c = g - d.rep_base;
+    const uint8_t *rep = st.spins + d.spin_base + (int64_t)c * d.rep_bytes;
+    const int N = d.N, M = d.M, Mh = d.Mh;
+    int lag[kTauLags];
+#pragma unroll
+    for (int l = 0; l < kTauLags; ++l) lag[l] = tau_lag(M, l) % M;
+    int acc[kTauLags];
+#pragma unroll
+    for (int l = 0; l < kTauLags; ++l) acc[l] = 0;
+    const int total = M * N;
+    for (int pos = blockIdx.y * blockDim.x + threadIdx.x; pos < total; pos += kTauChunks * blockDim.x) {
+        const int k = pos / N, i = pos - k * N;
+        const int x = rep[(int64_t)(k & (d.parities - 1)) * N * Mh + (int64_t)i * Mh + (k >> (d.parities - 1))];
+#pragma unroll
+        for (int l = 0; l < kTauLags; ++l) {
+            int k2 = k + lag[l];
+            if (k2 >= M) k2 -= M;
+            const int y = rep[(int64_t)(k2 & (d.parities - 1)) * N * Mh + (int64_t)i * Mh + (k2 >> (d.parities - 1))];
+            acc[l] += 1 - 2 * (x ^ y);
+        }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int l = 0; l < kTauLags; ++l) {
+        const long long v = wave_sum((long long)acc[l]);
+        if (lane == 0) red[wave][l] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kTauLags) {
+        long long v = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][threadIdx.x];
+        const int r = st.rung_of[g];
+        atomicAdd(reinterpret_cast<unsigned long long *>(&st.sumCt[((int64_t)d.rep_base + r) * kTauLags + threadIdx.x]),
+                  (unsigned long long)v);
+    }
+}
+
 __global__ void advance_kernel(DevState st, int32_t n_inst, uint32_t t_add)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1544,6 +1600,13 @@ hipError_t launch_exchange(const DevState &st, int32_t n_inst, uint32_t key0, ui
 {
     if (n_inst <= 0) return hipSuccess;
     hipLaunchKernelGGL(exchange_kernel, dim3(n_inst), dim3(64), 0, s, st, key0, key1, t_add);
+    return hipGetLastError();
+}
+
+hipError_t launch_tau_corr(const DevState &st, int32_t n_reps, hipStream_t s)
+{
+    if (n_reps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tau_corr_kernel, dim3(n_reps, kTauChunks), dim3(256), 0, s, st);
     return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ PT_FLAG_TIMING, PT_FLAG_NO_GRAPH, PT_FLAG_INJECT_LAUNCH_OOR_ONCE = 0x1, 0x2, 0x4
 PT_FLAG_FOUR_SLICE_LANES = 0x10
 PT_FLAG_BLOCK_LAUNCH_PER_SWEEP = 0x20
 PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT = 0x40
+PT_FLAG_TAU_CORR = 0x80
+TAU_LAGS = 8  # PT_TAU_LAGS
 PT_FLAG_SLICE_BLOCKS = 0x8
 LABEL_NONE, LABEL_UP, LABEL_DOWN = 0, 1, 2
 MLP_LOSS_SOFTMAX, MLP_LOSS_SIGMOID = 0, 1
@@ -58,7 +60,8 @@ class _Obs(C.Structure):
                 ("roundtrips", C.c_void_p), ("label", C.c_void_p), ("sumE", C.c_void_p),
                 ("sumC", C.c_void_p), ("sumE2", C.c_void_p), ("sumC2", C.c_void_p),
                 ("nup", C.c_void_p), ("ndown", C.c_void_p),
-                ("t", C.c_uint64), ("e", C.c_uint64), ("n_acc", C.c_uint64)]
+                ("t", C.c_uint64), ("e", C.c_uint64), ("n_acc", C.c_uint64),
+                ("sumCt", C.c_void_p)]
 
 
 class _Info(C.Structure):
@@ -243,10 +246,12 @@ class Sampler:
                  roundtrips=np.zeros(R, np.uint64), label=np.zeros(R, np.int8),
                  sumE=np.zeros(R, np.int64), sumC=np.zeros(R, np.int64),
                  sumE2=np.zeros(R, np.int64), sumC2=np.zeros(R, np.int64),
-                 nup=np.zeros(R, np.uint64), ndown=np.zeros(R, np.uint64))
+                 nup=np.zeros(R, np.uint64), ndown=np.zeros(R, np.uint64),
+                 sumCt=np.zeros((R, TAU_LAGS), np.int64))
         rec = _Obs(*[o[k].ctypes.data for k in ("E_cl", "C", "rung_of", "replica_of", "acc",
                                                  "att", "roundtrips", "label", "sumE", "sumC",
-                                                 "sumE2", "sumC2", "nup", "ndown")], 0, 0, 0)
+                                                 "sumE2", "sumC2", "nup", "ndown")], 0, 0, 0,
+                   o["sumCt"].ctypes.data)
         _check(lib().pt_observables(self._ctx, int(n), C.byref(rec)))
         o["t"], o["e"], o["n_acc"] = int(rec.t), int(rec.e), int(rec.n_acc)
         return o

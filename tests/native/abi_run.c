@@ -100,7 +100,7 @@ int main(int argc, char **argv)
              *ndown = calloc(R, 8);
     int8_t *label = calloc(R, 1), *spins = calloc((size_t)R * M * N, 1);
     pt_obs o = {E_cl, C, rung_of, replica_of, acc, att, rt, label, sE, sC, sE2, sC2, nup, ndown,
-                0, 0, 0};
+                0, 0, 0, NULL};
     if (check(pt_observables(ctx, 0, &o), "pt_observables")) return 1;
     if (check(pt_get_spins(ctx, 0, spins), "pt_get_spins")) return 1;
     put_i64("E_cl", E_cl, R);

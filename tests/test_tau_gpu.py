@@ -1,0 +1,117 @@
+"""Imaginary-time spin correlations (PT_FLAG_TAU_CORR) against the CPU oracle.
+
+With the flag, every exchange step adds, per rung, Ct_l = sum_k sum_i s_i^k s_i^(k+lag_l)
+of the replica found there (eight lags spanning 1/16 .. 1/2 of the Trotter direction).
+The accumulators are integers, so the bar is bit equality, on every launch path: fused
+PT cycles (small batches), separate exchange launches (many tiles), split pt_sweep /
+pt_exchange calls, and resident slice blocks.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("E_cl", "C", "rung_of", "replica_of", "acc", "att", "roundtrips", "label", "sumE",
+        "sumC", "sumE2", "sumC2", "nup", "ndown", "sumCt")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ptqmc():
+    import torch
+    from paper_1004_0023_amd import ptqmc as P
+    torch.cuda.set_device(0)
+    P.lib()
+    return P
+
+
+def assert_same(sampler, n, ref, what=""):
+    got = sampler.observables(n)
+    want = ref.observables()
+    for k in KEYS:
+        assert np.array_equal(np.asarray(got[k]), np.asarray(want[k])), f"{what} inst {n}: {k}"
+    assert (got["t"], got["e"], got["n_acc"]) == (want["t"], want["e"], want["n_acc"]), what
+
+
+def small_batch():
+    rng = np.random.default_rng([1004, 27])
+    return [
+        W.make_instance(1, np.zeros((0, 2), np.int32), np.zeros(0, np.int8),
+                        np.array([1], np.int8), 4, [0.5, 1.0, 2.0], 1.0, name="lone"),
+        W.random_small_instance(rng, 10, 1, 4, d=3, jmax=3, hmax=1, name="classical"),
+        W.random_small_instance(rng, 7, 2, 2, d=2, jmax=1, hmax=0, name="m2r2"),
+        W.random_small_instance(rng, 13, 24, 5, d=4, jmax=2, hmax=2, name="m24"),
+        W.random_small_instance(rng, 20, 64, 6, d=3, jmax=1, hmax=1, name="m64"),
+        W.config1(),
+    ]
+
+
+def test_fused_cycles_match_oracle(ptqmc):
+    insts = small_batch()
+    seed = 0x7A0
+    k, cycles = 2, 30
+    say(f"case: correlations, small batch (fused cycles), {cycles} cycles of {k} sweeps")
+    refs = []
+    for n, inst in enumerate(insts):
+        r = oracle.OracleChain(inst, seed, index=n)
+        r.run(k, cycles)
+        refs.append(r)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=ptqmc.PT_FLAG_TAU_CORR) as s:
+        s.run(cycles)
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], "fused")
+
+
+def test_separate_exchange_and_split_calls_match_oracle(ptqmc):
+    """Eight batched instances as one replica per tile (well over 64 tiles, so the
+    exchange runs as its own launch), then split pt_sweep / pt_exchange calls."""
+    insts = [W.config3_instance(i) for i in range(8)]
+    seed = W.sampler_seed(3)
+    k = 10
+    say("case: correlations, 8 batched instances, one replica per tile, 3 cycles + split calls")
+    refs = []
+    for n, inst in enumerate(insts):
+        r = oracle.OracleChain(inst, seed, index=n)
+        r.run(k, 3)
+        r.sweep(4)
+        r.exchange()
+        refs.append(r)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_replicas=1,
+                       flags=ptqmc.PT_FLAG_TAU_CORR | ptqmc.PT_FLAG_NO_GRAPH) as s:
+        assert s.info()["n_tiles"] > 64
+        s.run(3)
+        s.sweep(4)
+        s.exchange()
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], "split")
+
+
+def test_slice_blocks_match_oracle(ptqmc):
+    inst = W.config4()
+    seed = W.sampler_seed(4)
+    say("case: correlations, config 4 (resident slice blocks), 1 cycle of 10 sweeps")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, tile_bytes=131072,
+                       block_threads=1024, flags=ptqmc.PT_FLAG_TAU_CORR) as s:
+        s.run(1)
+        ref = oracle.OracleChain(inst, seed)
+        ref.run(10, 1)
+        assert_same(s, 0, ref, "config4")
+
+
+def test_without_flag_stays_zero_and_packed_is_refused(ptqmc):
+    inst = W.config1()
+    with ptqmc.Sampler([inst], 3) as s:
+        s.run(5)
+        assert not np.any(s.observables(0)["sumCt"])
+    with pytest.raises(ptqmc.PTError) as err:
+        ptqmc.Sampler([inst], 3, encoding=ptqmc.PT_BITPACK32, flags=ptqmc.PT_FLAG_TAU_CORR)
+    assert err.value.code == ptqmc.PT_EINVAL
