@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0)
     ap.add_argument("--encoding", choices=["int8", "bitpack"], default="int8")
+    ap.add_argument("--tau-corr", action="store_true",
+                    help="also accumulate imaginary-time correlations at every exchange step")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
@@ -185,7 +187,8 @@ def main():
     print(f"bench: {desc}; {steps} steps of {k} sweeps + exchange", file=sys.stderr, flush=True)
 
     encoding = ptqmc.PT_BITPACK32 if args.encoding == "bitpack" else ptqmc.PT_INT8
-    s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=ptqmc.PT_FLAG_TIMING,
+    flags = ptqmc.PT_FLAG_TIMING | (ptqmc.PT_FLAG_TAU_CORR if args.tau_corr else 0)
+    s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags,
                       tile_bytes=args.tile_bytes, block_threads=args.block_threads,
                       encoding=encoding)
     s.run(args.warmup)  # the first launches also tune the launch shape
@@ -238,6 +241,8 @@ def main():
     peak = PEAK_INT_OPS / 1e12
     if packed:
         desc += "; bit-packed spins (32 replica slots per 32-bit word)"
+    if args.tau_corr:
+        desc += "; imaginary-time correlations accumulated at every exchange step"
     out = {
         "metric": "spin-flip attempts/s",
         "value": value,
@@ -259,6 +264,7 @@ def main():
                    "sweep_kernel_flips_per_s": flips_per_step / avg_sweep_s if avg_sweep_s else None,
                    "sweep_launches_per_step": launches_per_call,
                    "encoding": args.encoding,
+                   "tau_corr": bool(args.tau_corr),
                    "block_resident": bool(info["block_resident"]) if blocked else None,
                    "segment_rates": {"segments": n_seg,
                                      "mean": statistics.mean(seg_rates),

@@ -894,7 +894,12 @@ static_assert(kTauLags == PT_TAU_LAGS, "device and ABI correlation lags differ")
 int enqueue_tau_corr(pt_ctx *c)
 {
     if (!(c->opt.flags & PT_FLAG_TAU_CORR)) return PT_OK;
-    const hipError_t e = launch_tau_corr(c->st, (int32_t)c->plan.total_reps, c->stream);
+    // workgroups per replica: about 8192 (parity, site, four-slice group) positions each,
+    // for the largest replica of the batch
+    int64_t most = 1;
+    for (const auto &d : c->plan.desc) most = std::max<int64_t>(most, (int64_t)d.parities * d.N * d.G4);
+    const int32_t chunks = (int32_t)std::min<int64_t>(64, (most + 8191) / 8192);
+    const hipError_t e = launch_tau_corr(c->st, (int32_t)c->plan.total_reps, chunks, c->stream);
     if (e != hipSuccess) return hip_fail(e, "correlation launch");
     return PT_OK;
 }

@@ -50,8 +50,9 @@ hipError_t launch_sweep(const SweepLaunch &L, int kind, hipStream_t s);
 hipError_t launch_block_prepare(const SweepLaunch &L, hipStream_t s);
 hipError_t launch_exchange(const DevState &st, int32_t n_inst, uint32_t key0, uint32_t key1,
                            uint32_t t_add, hipStream_t s);
-// Imaginary-time correlations of every replica added to sumCt at its current rung.
-hipError_t launch_tau_corr(const DevState &st, int32_t n_reps, hipStream_t s);
+// Imaginary-time correlations of every replica added to sumCt at its current rung, with
+// `chunks` workgroups per replica.
+hipError_t launch_tau_corr(const DevState &st, int32_t n_reps, int32_t chunks, hipStream_t s);
 hipError_t launch_advance(const DevState &st, int32_t n_inst, uint32_t t_add, hipStream_t s);
 // Bit-packed encoding: initial spins, one colour class of one sweep, and E_cl, C of
 // every replica (n_eblk position blocks, n_reps replica slots).

@@ -1429,10 +1429,11 @@ __device__ __forceinline__ int tau_lag(int M, int l)
     return d < 1 ? 1 : d;
 }
 
-constexpr int kTauChunks = 16;  // workgroups per replica
-
 // Ct_l = sum_k sum_i s_i^k s_i^{(k + lag_l) mod M} of replica (blockIdx.x) over the
-// positions (k, i) of chunk blockIdx.y, added to sumCt of the replica's rung.
+// positions of chunk blockIdx.y (of gridDim.y), added to sumCt of the replica's rung.  A lane takes the
+// four slices m = 4 g4 .. 4 g4 + 3 of one (parity, site) row; slice k = 2m + p meets
+// slice k + lag in the row of parity (p + lag) mod 2 at m + (p + lag) / 2 (cyclically),
+// so neighbouring lanes read neighbouring bytes at every lag.
 __global__ void __launch_bounds__(256) tau_corr_kernel(DevState st)
 {
     __shared__ long long red[4][kTauLags];
@@ -1441,24 +1442,61 @@ __global__ void __launch_bounds__(256) tau_corr_kernel(DevState st)
     const InstDesc d = st.inst[n];
     const int c = g - d.rep_base;
     const uint8_t *rep = st.spins + d.spin_base + (int64_t)c * d.rep_bytes;
-    const int N = d.N, M = d.M, Mh = d.Mh;
+    const int N = d.N, M = d.M, Mh = d.Mh, G4 = d.G4;
     int lag[kTauLags];
 #pragma unroll
     for (int l = 0; l < kTauLags; ++l) lag[l] = tau_lag(M, l) % M;
     int acc[kTauLags];
 #pragma unroll
     for (int l = 0; l < kTauLags; ++l) acc[l] = 0;
-    const int total = M * N;
-    for (int pos = blockIdx.y * blockDim.x + threadIdx.x; pos < total; pos += kTauChunks * blockDim.x) {
-        const int k = pos / N, i = pos - k * N;
-        const int x = rep[(int64_t)(k & (d.parities - 1)) * N * Mh + (int64_t)i * Mh + (k >> (d.parities - 1))];
+    const int total = d.parities * N * G4;
+    if (M >= 2 && (Mh & 3) == 0) {
+        // whole words: the four bytes from slice m2 on are two aligned words joined by a
+        // byte alignment (rows hold Mh / 4 words, cyclically), and a byte pair differs
+        // iff its xor is 1, so one popcount counts four products at once
+        const uint32_t *rep32 = reinterpret_cast<const uint32_t *>(rep);
+        const int Wr = Mh >> 2;
+        for (int pos = blockIdx.y * blockDim.x + threadIdx.x; pos < total; pos += gridDim.y * blockDim.x) {
+            const int g4 = pos % G4;
+            const int pi = pos / G4;
+            const int i = pi % N, p = pi / N;
+            const uint32_t X = rep32[((int64_t)p * N + i) * Wr + g4];
 #pragma unroll
-        for (int l = 0; l < kTauLags; ++l) {
-            int k2 = k + lag[l];
-            if (k2 >= M) k2 -= M;
-            const int y = rep[(int64_t)(k2 & (d.parities - 1)) * N * Mh + (int64_t)i * Mh + (k2 >> (d.parities - 1))];
-            acc[l] += 1 - 2 * (x ^ y);
+            for (int l = 0; l < kTauLags; ++l) {
+                const int q = p + lag[l];
+                int m2 = 4 * g4 + (q >> 1);
+                if (m2 >= Mh) m2 -= Mh;
+                const uint32_t *row2 = rep32 + ((int64_t)(q & 1) * N + i) * Wr;
+                const int j = m2 >> 2;
+                const uint32_t lo = row2[j], hi = row2[(j + 1 == Wr) ? 0 : j + 1];
+                const uint32_t Y = __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)(m2 & 3));
+                acc[l] += 4 - 2 * (int)__popc(X ^ Y);
+            }
         }
+    } else {
+    for (int pos = blockIdx.y * blockDim.x + threadIdx.x; pos < total; pos += gridDim.y * blockDim.x) {
+        const int g4 = pos % G4;
+        const int pi = pos / G4;
+        const int i = pi % N, p = pi / N;
+        const uint8_t *row = rep + (int64_t)p * N * Mh + (int64_t)i * Mh;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int m = 4 * g4 + b;
+            if (m >= Mh) break;
+            const int x = row[m];
+#pragma unroll
+            for (int l = 0; l < kTauLags; ++l) {
+                int y = x;  // M == 1: the slice meets itself
+                if (M >= 2) {
+                    const int q = p + lag[l];
+                    int m2 = m + (q >> 1);
+                    if (m2 >= Mh) m2 -= Mh;
+                    y = rep[(int64_t)(q & 1) * N * Mh + (int64_t)i * Mh + m2];
+                }
+                acc[l] += 1 - 2 * (x ^ y);
+            }
+        }
+    }
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
@@ -1603,10 +1641,10 @@ hipError_t launch_exchange(const DevState &st, int32_t n_inst, uint32_t key0, ui
     return hipGetLastError();
 }
 
-hipError_t launch_tau_corr(const DevState &st, int32_t n_reps, hipStream_t s)
+hipError_t launch_tau_corr(const DevState &st, int32_t n_reps, int32_t chunks, hipStream_t s)
 {
-    if (n_reps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tau_corr_kernel, dim3(n_reps, kTauChunks), dim3(256), 0, s, st);
+    if (n_reps <= 0 || chunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tau_corr_kernel, dim3(n_reps, chunks), dim3(256), 0, s, st);
     return hipGetLastError();
 }
 
