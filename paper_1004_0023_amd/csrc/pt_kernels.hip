@@ -6,11 +6,13 @@
 //                  per (site, two words of four same-parity slices), byte-SWAR local
 //                  fields (v_perm per neighbour), one Philox call per word and class;
 //                  then E_cl and C from the byte field with v_dot4
-//   sweep_block    one parity phase of one sweep of slice blocks of replicas too large
-//                  for one workgroup's LDS (or whose rows need offsets beyond 16 bits)
+//   sweep_block    sweeps of slice blocks of replicas too large for one workgroup's LDS
+//                  (or whose rows need offsets beyond 16 bits): all sweeps of a call in
+//                  one launch with every block resident, or one launch per sweep
 //   sweep_generic  the same chain for any other shape (slice groups that are not a power
 //                  of two, M = 1, large fields), one byte at a time
 //   exchange       one even/odd replica-exchange step per instance (one workgroup each)
+//   tau_corr       imaginary-time spin correlations of every replica, added per rung
 //   advance        t += n
 //
 // The sweep kernels visit colour classes (slice parity p, spatial colour g) in order; a
