@@ -142,3 +142,25 @@ def test_annealing_ladder_gap_matches_exact_diagonalisation(ptqmc):
         fit = AN.fit_gap(taus[1:], G[r, 1:], beta)
         say(f"  s = {s_vals[r]:.3f}: ED gap {gap:.4f}, fitted {fit:.4f}")
         assert fit == pytest.approx(gap, rel=0.08)
+
+
+def test_checkpoint_carries_correlations(ptqmc):
+    """The accumulators are part of the saved state: a run resumed from a checkpoint
+    ends where the uninterrupted oracle does, sumCt included."""
+    insts = small_batch()[3:]
+    seed = 0x7A1
+    say("case: correlations across save / load")
+    refs = []
+    for n, inst in enumerate(insts):
+        r = oracle.OracleChain(inst, seed, index=n)
+        r.run(3, 20)
+        refs.append(r)
+    flags = ptqmc.PT_FLAG_TAU_CORR
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=3, flags=flags) as a:
+        a.run(9)
+        blob = a.save()
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=3, flags=flags) as b:
+        b.load(blob)
+        b.run(11)
+        for n in range(len(insts)):
+            assert_same(b, n, refs[n], "resumed")
