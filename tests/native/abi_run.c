@@ -2,15 +2,16 @@
  * instance from a text file, run n_cycles PT cycles with a library-owned workspace and
  * stream, and print the observables and spins as text.
  *
- *   abi_run <instance.txt> <seed> <sweeps_per_exchange> <n_cycles>
+ *   abi_run <instance.txt> <seed> <sweeps_per_exchange> <n_cycles> [encoding [flags]]
  *
  * instance.txt: "N M R n_edges n_colors", then n_edges lines "i j J", then N values of h,
  * N colours, R values of b, R values of K (whitespace separated; b and K as %a hex
  * floats so they round-trip exactly).  Output lines: "E_cl ...", "C ...", "rung_of ...",
  * "replica_of ...", "acc ...", "att ...", "roundtrips ...", "label ...", "sumE ...",
  * "sumC ...", "sumE2 ...", "sumC2 ...", "nup ...", "ndown ...", "counters t e n_acc",
- * "spins ..." (R x M x N values in {-1, +1} by slot, slice, site).  Exit status 0 on
- * success, 1 on a library error (its message on stderr). */
+ * "spins ..." (R x M x N values in {-1, +1} by slot, slice, site) and, with
+ * PT_FLAG_TAU_CORR among the flags, "sumCt ..." (R x PT_TAU_LAGS by rung).  Exit status 0
+ * on success, 1 on a library error (its message on stderr). */
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -49,10 +50,13 @@ static void put_i32(const char *name, const int32_t *v, int n)
 
 int main(int argc, char **argv)
 {
-    if (argc != 5) {
-        fprintf(stderr, "usage: %s instance.txt seed sweeps_per_exchange n_cycles\n", argv[0]);
+    if (argc < 5 || argc > 7) {
+        fprintf(stderr, "usage: %s instance.txt seed sweeps_per_exchange n_cycles [encoding [flags]]\n",
+                argv[0]);
         return 2;
     }
+    const int encoding = argc > 5 ? atoi(argv[5]) : PT_INT8;
+    const uint32_t flags = argc > 6 ? (uint32_t)strtoul(argv[6], NULL, 0) : 0u;
     FILE *f = fopen(argv[1], "r");
     if (!f) {
         perror(argv[1]);
@@ -88,7 +92,7 @@ int main(int argc, char **argv)
     fclose(f);
 
     const pt_instance inst = {N, M, R, E, ncol, ei, ej, J, h, col, b, K};
-    const pt_options opt = {strtoull(argv[2], NULL, 0), atoi(argv[3]), PT_INT8, 0, 0, 0, 0};
+    const pt_options opt = {strtoull(argv[2], NULL, 0), atoi(argv[3]), encoding, flags, 0, 0, 0};
     pt_ctx *ctx = NULL;
     if (check(pt_init(&ctx, &inst, 1, &opt, NULL, NULL, 0), "pt_init")) return 1;
     if (check(pt_run(ctx, atoi(argv[4])), "pt_run")) return 1;
@@ -99,8 +103,9 @@ int main(int argc, char **argv)
     uint64_t *acc = calloc(R, 8), *att = calloc(R, 8), *rt = calloc(R, 8), *nup = calloc(R, 8),
              *ndown = calloc(R, 8);
     int8_t *label = calloc(R, 1), *spins = calloc((size_t)R * M * N, 1);
+    int64_t *sCt = calloc((size_t)R * PT_TAU_LAGS, 8);
     pt_obs o = {E_cl, C, rung_of, replica_of, acc, att, rt, label, sE, sC, sE2, sC2, nup, ndown,
-                0, 0, 0, NULL};
+                0, 0, 0, sCt};
     if (check(pt_observables(ctx, 0, &o), "pt_observables")) return 1;
     if (check(pt_get_spins(ctx, 0, spins), "pt_get_spins")) return 1;
     put_i64("E_cl", E_cl, R);
@@ -124,6 +129,7 @@ int main(int argc, char **argv)
     printf("spins");
     for (size_t k = 0; k < (size_t)R * M * N; ++k) printf(" %d", (int)spins[k]);
     printf("\n");
+    if (flags & PT_FLAG_TAU_CORR) put_i64("sumCt", sCt, R * PT_TAU_LAGS);
     pt_free(ctx);
     return 0;
 }

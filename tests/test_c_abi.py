@@ -47,7 +47,10 @@ def test_driver_compiles_against_the_header(tmp_path):
 
 
 @pytest.mark.gpu
-def test_c_driver_matches_oracle(tmp_path):
+@pytest.mark.parametrize("encoding,flags", [(0, 0), (1, 0), (0, 0x80)])
+def test_c_driver_matches_oracle(tmp_path, encoding, flags):
+    """Byte and bit-packed encodings, and the correlation accumulators (flag 0x80,
+    PT_FLAG_TAU_CORR), all through the C ABI alone."""
     exe = build_driver(tmp_path)
     rng = np.random.default_rng([1004, 27])
     for n, inst in enumerate([W.config1(),
@@ -55,9 +58,10 @@ def test_c_driver_matches_oracle(tmp_path):
         seed, k, cycles = 0xC0FFEE + n, 3, 40
         path = str(tmp_path / f"inst{n}.txt")
         write_instance(inst, path)
-        print(f"case: C driver, instance {n} (N={inst.N} M={inst.M} R={inst.R})", flush=True)
-        out = subprocess.run([exe, path, str(seed), str(k), str(cycles)], capture_output=True,
-                             text=True, timeout=120)
+        print(f"case: C driver, instance {n} (N={inst.N} M={inst.M} R={inst.R}), "
+              f"encoding {encoding}, flags {flags:#x}", flush=True)
+        out = subprocess.run([exe, path, str(seed), str(k), str(cycles), str(encoding),
+                              str(flags)], capture_output=True, text=True, timeout=120)
         assert out.returncode == 0, out.stderr
         got = {}
         for line in out.stdout.splitlines():
@@ -71,3 +75,5 @@ def test_c_driver_matches_oracle(tmp_path):
             assert np.array_equal(got[key], np.asarray(want[key]).astype(np.int64)), key
         assert tuple(got["counters"]) == (want["t"], want["e"], want["n_acc"])
         assert np.array_equal(got["spins"], ref.s.reshape(-1).astype(np.int64))
+        if flags & 0x80:
+            assert np.array_equal(got["sumCt"], want["sumCt"].reshape(-1))
