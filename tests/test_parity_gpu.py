@@ -366,3 +366,41 @@ def test_replica_too_large_is_refused(ptqmc):
     with pytest.raises(ptqmc.PTError) as ei:
         ptqmc.Sampler([inst], 1, sweeps_per_exchange=1)
     assert ei.value.code == ptqmc.PT_EINVAL and "does not fit" in str(ei.value)
+
+
+@pytest.mark.parametrize("mode", ["tiles", "slice_blocks", "bitpack", "tau"])
+def test_every_graph_replay_matches_oracle(ptqmc, mode):
+    """pt_run replays a captured graph of 16 cycles.  Three replays, with eager
+    pt_sweep / pt_exchange calls and synchronisations between them, each checked against
+    the oracle: whole-replica tiles (fused cycles), resident slice blocks, the packed
+    encoding, and the correlation accumulators."""
+    insts = fast_batch()[:5]
+    seed = 0x6A7
+    k = 2
+    flags = {"tiles": 0, "slice_blocks": ptqmc.PT_FLAG_SLICE_BLOCKS, "bitpack": 0,
+             "tau": ptqmc.PT_FLAG_TAU_CORR}[mode]
+    enc = ptqmc.PT_BITPACK32 if mode == "bitpack" else ptqmc.PT_INT8
+    keys = KEYS + (("sumCt",) if mode == "tau" else ())
+    say(f"case: graph replays, {mode}")
+    refs = [oracle.OracleChain(inst, seed, index=n) for n, inst in enumerate(insts)]
+    # a fixed block size turns the launch-shape tuner off, so every run(16) is a replay
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags, encoding=enc,
+                       block_threads=256) as s:
+        for rep in range(3):
+            s.run(16)  # one replay of the captured 16-cycle graph
+            s.sync()
+            for r in refs:
+                r.run(k, 16)
+            for n in range(len(insts)):
+                got, want = s.observables(n), refs[n].observables()
+                for key in keys:
+                    assert np.array_equal(np.asarray(got[key]), np.asarray(want[key])), (mode, rep, n, key)
+                assert np.array_equal(s.spins(n), refs[n].s), (mode, rep, n)
+            # eager work between replays
+            s.sweep(1)
+            s.exchange()
+            for r in refs:
+                r.sweep(1)
+                r.exchange()
+        if mode == "slice_blocks":
+            assert s.info()["block_resident"] == 1
