@@ -864,27 +864,52 @@ struct SlotSet {
     __device__ __forceinline__ int at(int r) const { return s0 + r + (r >= cut ? jump : 0); }
 };
 
+// A thread's share of a slot set whose P * ns (replica, slot) pairs per site fit the
+// workgroup: it keeps pair (q, sl) and runs sites s_first, s_first + sstep, ... of each
+// class.  It depends only on the thread and the slot set, so a resident block computes
+// it once per call, not once per sweep (the divisions would cost as much as a few
+// attempts).
+struct PhaseLane {
+    int q, sl, sstep, s_first;
+};
+
+__device__ __forceinline__ PhaseLane phase_lane(const Tile &tile, const SlotSet &S, int nt)
+{
+    const int tid = threadIdx.x;
+    const int lanes = tile.P * S.ns;
+    PhaseLane L;
+    if (lanes > nt) {
+        L.q = L.sl = L.sstep = 0;
+        L.s_first = 1 << 30;
+        return L;
+    }
+    const int r = tid % lanes;
+    L.q = r / S.ns;
+    L.sl = S.at(r - L.q * S.ns);
+    L.sstep = nt / lanes;
+    L.s_first = (tid < L.sstep * lanes) ? tid / lanes : (1 << 30);
+    return L;
+}
+
 // All colour classes of parity PAR over the slots of S (a whole sweep: phase 0 over slots
 // 1..ng+1, phase 1 over 1..ng).  Slots of one parity are independent of each other within
-// a phase, so a phase may be run as several slot sets in any order.  Each thread keeps
-// one (replica, slot) pair and strides over the sites of a class.
+// a phase, so a phase may be run as several slot sets in any order.  When the pairs fit
+// the workgroup each thread keeps one (replica, slot) pair, given by PL, and strides over
+// the sites of a class; otherwise the items of a class are dealt out one by one.
 template <int DT, int PAR>
 __device__ __forceinline__ void block_phase(const BlockArgs &a, const InstDesc &d, const Tile &tile,
-                                            const BlockLds &t, const SlotSet &S)
+                                            const BlockLds &t, const SlotSet &S, const PhaseLane &PL,
+                                            int nt)
 {
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
     const int D = (DT > 0) ? DT : d.D;
     const int ns = S.ns;
     const int lanes = tile.P * ns;  // per site
     if (lanes <= nt) {
-        const int r = tid % lanes;
-        const int q = r / ns, sl = S.at(r - q * ns);
-        const int sstep = nt / lanes;
-        const int s_first = (tid < sstep * lanes) ? tid / lanes : (1 << 30);
         for (int g = 0; g < d.n_colors; ++g) {
             const int s1 = t.coff[g + 1];
-            for (int si = t.coff[g] + s_first; si < s1; si += sstep)
-                block_item<DT, PAR>(a, t, D, t.csite[si], q, sl);
+            for (int si = t.coff[g] + PL.s_first; si < s1; si += PL.sstep)
+                block_item<DT, PAR>(a, t, D, t.csite[si], PL.q, PL.sl);
             __syncthreads();
         }
     } else {
@@ -901,32 +926,65 @@ __device__ __forceinline__ void block_phase(const BlockArgs &a, const InstDesc &
     }
 }
 
-template <int DT>
-__device__ __forceinline__ void block_sweep(const BlockArgs &a, const InstDesc &d, const Tile &tile,
-                                            const BlockLds &t)
+// The slot sets of a whole sweep (phase 0, then phase 1) or of the split sweep below, with
+// the workgroup size nt.
+struct SweepSets {
+    SlotSet s[4];
+    PhaseLane l[4];
+    int nt;
+};
+
+__device__ __forceinline__ SweepSets whole_sweep_sets(const Tile &tile, int nt)
 {
     const int ng = tile.ng;
-    block_phase<DT, 0>(a, d, tile, t, SlotSet{1, ng + 1, ng + 1, 0});
-    block_phase<DT, 1>(a, d, tile, t, SlotSet{1, ng, ng, 0});
+    SweepSets w;
+    w.nt = nt;
+    w.s[0] = SlotSet{1, ng + 1, ng + 1, 0};
+    w.s[1] = SlotSet{1, ng, ng, 0};
+    w.s[2] = w.s[3] = w.s[1];
+    for (int k = 0; k < 2; ++k) w.l[k] = phase_lane(tile, w.s[k], nt);
+    w.l[2] = w.l[3] = w.l[1];
+    return w;
+}
+
+template <int DT>
+__device__ __forceinline__ void block_sweep(const BlockArgs &a, const InstDesc &d, const Tile &tile,
+                                            const BlockLds &t, const SweepSets &w)
+{
+    block_phase<DT, 0>(a, d, tile, t, w.s[0], w.l[0], w.nt);
+    block_phase<DT, 1>(a, d, tile, t, w.s[1], w.l[1], w.nt);
+}
+
+__device__ __forceinline__ SweepSets split_sweep_sets(const Tile &tile, int nt)
+{
+    const int ng = tile.ng;
+    SweepSets w;
+    w.nt = nt;
+    w.s[0] = SlotSet{2, ng - 1, ng - 1, 0};  // phase 0: 2..ng
+    w.s[1] = SlotSet{1, 2, 1, ng - 1};       // phase 0: 1 and ng + 1
+    w.s[2] = SlotSet{1, 2, 1, ng - 2};       // phase 1: 1 and ng
+    w.s[3] = SlotSet{2, ng - 2, ng - 2, 0};  // phase 1: 2..ng - 1
+    for (int k = 0; k < 4; ++k) w.l[k] = phase_lane(tile, w.s[k], nt);
+    return w;
 }
 
 // A sweep of a resident block (ng >= 6) ordered so that the exchange with the neighbours
-// overlaps work: phase 0 first over slots 2..ng, which read no halo; then wait_halos()
-// (the neighbours' parity-1 groups of the previous sweep); phase 0 over slots 1 and ng+1;
-// phase 1 over slots 1, 2, ng-1 and ng, which hold the groups the neighbours need; then
-// publish(); and phase 1 over slots 3..ng-2 while the neighbours go on.
-template <int DT, class Wait, class Publish>
+// overlaps work: phase 0 first over slots 2..ng, which read no halo; then halos_in() (the
+// neighbours' parity-1 groups of the previous sweep into the halo slots); phase 0 over
+// slots 1 and ng+1; phase 1 over slots 1 and ng, the groups the neighbours need; then
+// publish(); and phase 1 over slots 2..ng-1 while the neighbours go on.
+template <int DT, class HalosIn, class Publish>
 __device__ __forceinline__ void block_sweep_split(const BlockArgs &a, const InstDesc &d,
                                                   const Tile &tile, const BlockLds &t,
-                                                  Wait &&wait_halos, Publish &&publish)
+                                                  const SweepSets &w, HalosIn &&halos_in,
+                                                  Publish &&publish)
 {
-    const int ng = tile.ng;
-    block_phase<DT, 0>(a, d, tile, t, SlotSet{2, ng - 1, ng - 1, 0});
-    wait_halos();
-    block_phase<DT, 0>(a, d, tile, t, SlotSet{1, 2, 1, ng - 1});
-    block_phase<DT, 1>(a, d, tile, t, SlotSet{1, 4, 2, ng - 4});
+    block_phase<DT, 0>(a, d, tile, t, w.s[0], w.l[0], w.nt);
+    halos_in();
+    block_phase<DT, 0>(a, d, tile, t, w.s[1], w.l[1], w.nt);
+    block_phase<DT, 1>(a, d, tile, t, w.s[2], w.l[2], w.nt);
     publish();
-    block_phase<DT, 1>(a, d, tile, t, SlotSet{3, ng - 4, ng - 4, 0});
+    block_phase<DT, 1>(a, d, tile, t, w.s[3], w.l[3], w.nt);
 }
 
 // Workgroups go to the XCDs (each with its own L2 cache) round robin by index.  The slice
@@ -1144,7 +1202,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
     const Tile tile = st.tiles[L.tile0 + bt];
     const int n = tile.inst;
     const InstDesc d = st.inst[n];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
+    // The workgroup size is kept in a register the compiler cannot see through: otherwise,
+    // short of registers, it re-reads it from the dispatch packet in every phase of every
+    // sweep, a global load waited for in full.
+    int nt = blockDim.x;
+    __asm__ volatile("" : "+s"(nt));
     const int P = tile.P, ng = tile.ng, g0 = tile.g0, G4 = d.G4, N = d.N;
     int64_t o[7];
     block_offsets(d, P, ng, o);
@@ -1184,17 +1247,42 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
 
     const int n_sw = PERSIST ? L.n_sweeps : 1;
     const int ip = tile.prev - L.tile0, in = tile.next - L.tile0;
+    const int hbp = st.tiles[tile.prev].hb, hbn = st.tiles[tile.next].hb;
+    const int polls = L.wait_polls > 0 ? L.wait_polls : kWaitPolls;
     // resident blocks: wait for both neighbours' previous sweep and take their parity-1
     // boundary groups as halos
     auto wait_halos = [&](int sw) {
-        block_wait(st, ip, in, sw + L.wait_extra, L.wait_polls > 0 ? L.wait_polls : kWaitPolls);
+        block_wait(st, ip, in, sw + L.wait_extra, polls);
         const uint32_t *rin = st.halo + (int64_t)((tsw + sw) & 1) * st.halo_words;
-        const int hbp = st.tiles[tile.prev].hb, hbn = st.tiles[tile.next].hb;
         for (int i = tid; i < N; i += nt) {
             const uint32_t h1p = rin[hbp + 2 * N + i];
             const uint32_t h1n = rin[hbn + N + i];
             sp32[block_at(a, 1, 0, i, 0) >> 2] = h1p;
             sp32[block_at(a, 1, 0, i, ng + 1) >> 2] = h1n;
+        }
+        __syncthreads();
+    };
+    // With at most one site per thread the halos of sweep sw are fetched into registers at
+    // the end of sweep sw - 1 (fetch_halos) and stored to LDS only before the edge slots of
+    // sweep sw (store_halos), so the load latency overlaps phase 0's interior slots.  The
+    // parity-1 halo slots are read by no slot of the interior.
+    const bool early = PERSIST && ng >= 6 && N <= nt;
+    uint32_t hreg_p = 0, hreg_n = 0;
+    // The loads are issued after every sweep of a resident block, also when their values go
+    // unused (the last sweep of the call, or no early halos), and by every thread (past N,
+    // of site N - 1): loads under a branch would be waited for where the branch ends.  They
+    // stay inside the record buffers.
+    auto fetch_halos = [&](int sw, bool wait) {
+        if (wait) block_wait(st, ip, in, sw + L.wait_extra, polls);
+        const uint32_t *rin = st.halo + (int64_t)((tsw + sw) & 1) * st.halo_words;
+        const int i = min(tid, N - 1);
+        hreg_p = rin[hbp + 2 * N + i];
+        hreg_n = rin[hbn + N + i];
+    };
+    auto store_halos = [&]() {
+        if (tid < N) {
+            sp32[block_at(a, 1, 0, tid, 0) >> 2] = hreg_p;
+            sp32[block_at(a, 1, 0, tid, ng + 1) >> 2] = hreg_n;
         }
         __syncthreads();
     };
@@ -1216,24 +1304,31 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
     // the sweep loop, instantiated per degree (the switch stays outside the loop, so only one
     // degree's phase set-up is live in it)
     const bool split = PERSIST && ng >= 6;
+    const SweepSets sets = split ? split_sweep_sets(tile, nt) : whole_sweep_sets(tile, nt);
     auto sweeps = [&](auto dt) {
         constexpr int DT = decltype(dt)::value;
         for (int sw = 0; sw < n_sw; ++sw) {
             a.tt = (uint32_t)(tsw + sw);
             if (split) {
                 block_sweep_split<DT>(
-                    a, d, tile, t,
+                    a, d, tile, t, sets,
                     [&]() {
-                        if (sw > 0) wait_halos(sw);
+                        if (sw > 0) {
+                            if (early)
+                                store_halos();
+                            else
+                                wait_halos(sw);
+                        }
                     },
                     [&]() {
                         if (sw + 1 < n_sw) publish(sw);
                     });
             } else {
                 if (PERSIST && sw > 0) wait_halos(sw);
-                block_sweep<DT>(a, d, tile, t);
+                block_sweep<DT>(a, d, tile, t, sets);
                 if (PERSIST && sw + 1 < n_sw) publish(sw);
             }
+            if (PERSIST) fetch_halos(sw + 1, early && sw + 1 < n_sw);
         }
     };
     switch (d.D) {
