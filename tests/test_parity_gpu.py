@@ -290,6 +290,31 @@ def test_slice_blocks_match_oracle(ptqmc, tile_bytes, block_threads, per_sweep):
             assert_same(s, n, refs[n], "blocks")
 
 
+@pytest.mark.parametrize("k", [3, 10])
+def test_resident_split_blocks_match_oracle(ptqmc, k):
+    """Resident slice blocks of eight groups (M = 256) run the split sweep order.  With at
+    most one site per thread the next sweep's halos are loaded into registers at the end
+    of a sweep: N = 200 leaves threads past N (they load site N - 1 and keep it unused),
+    N = 256 fills the workgroup, and N = 300 exceeds it, so those blocks wait and load
+    their halos before the edge slots instead.  Calls of k sweeps, then of one and of
+    seven sweeps (a one-sweep call fetches halos it never uses)."""
+    rng = np.random.default_rng([1004, 26])
+    insts = [W.random_small_instance(rng, N, 256, 3, d=4, jmax=2, hmax=1, name=f"split{N}")
+             for N in (200, 256, 300)]
+    seed = 0x5B117
+    cycles = 4
+    say(f"case: resident split slice blocks, N in 200/256/300, M=256, k={k}")
+    refs = oracle_batch(insts, seed, k, cycles, extra_sweeps=8)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_bytes=0, block_threads=256,
+                       flags=ptqmc.PT_FLAG_SLICE_BLOCKS) as s:
+        s.run(cycles)
+        s.sweep(1)
+        s.sweep(7)
+        assert s.info()["block_resident"] == 1
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], "split blocks")
+
+
 def test_config2_slice_blocks(ptqmc):
     inst = W.config2()
     seed = W.sampler_seed(2)
