@@ -1529,8 +1529,16 @@ __device__ __forceinline__ int tau_lag(int M, int l)
 // Ct_l = sum_k sum_i s_i^k s_i^{(k + lag_l) mod M} of replica (blockIdx.x) over the
 // positions of chunk blockIdx.y (of gridDim.y), added to sumCt of the replica's rung.  A lane takes the
 // four slices m = 4 g4 .. 4 g4 + 3 of one (parity, site) row; slice k = 2m + p meets
-// slice k + lag in the row of parity (p + lag) mod 2 at m + (p + lag) / 2 (cyclically),
-// so neighbouring lanes read neighbouring bytes at every lag.
+// slice k + lag in the row of parity (p + lag) mod 2 at m + (p + lag) / 2 (cyclically).
+//
+// When a site's two rows fit one wave (Mh % 4 == 0 and 2 Wr <= 64 words, Wr = Mh / 4), a
+// wave holds both rows of 64 / (2 Wr) sites, one word per lane, and takes every lagged
+// word from the lane that loaded it (ds_bpermute): one load per four slices, one lane read
+// of the row's next word, and per lag a byte alignment, one lane read, an xor and a
+// popcount.  A lane's sources and byte shifts depend only on the lane, so they are set up
+// once.  The loop runs per wave (every
+// lane stays active for the lane reads); lanes past the last site only mask their sums.
+// Other rows fall back to loads: neighbouring lanes read neighbouring bytes at every lag.
 __global__ void __launch_bounds__(256) tau_corr_kernel(DevState st)
 {
     __shared__ long long red[4][kTauLags];
@@ -1547,7 +1555,84 @@ __global__ void __launch_bounds__(256) tau_corr_kernel(DevState st)
 #pragma unroll
     for (int l = 0; l < kTauLags; ++l) acc[l] = 0;
     const int total = d.parities * N * G4;
-    if (M >= 2 && (Mh & 3) == 0) {
+    const int Wr4 = Mh >> 2;
+    if (M >= 2 && (Mh & 3) == 0 && 2 * Wr4 <= 64) {
+        const uint32_t *rep32 = reinterpret_cast<const uint32_t *>(rep);
+        const int Wr = Wr4, gw = 2 * Wr, spw = 64 / gw;
+        const int lane = threadIdx.x & 63;
+        const int sl = lane / gw, rem = lane - sl * gw;
+        const int p = rem >= Wr ? 1 : 0, g4 = rem - p * Wr;
+        const bool used = sl < spw;
+        // A lane reads lag l's word from lane j of row (p + lag) mod 2 of its site.  Every
+        // lane that reads row P' at lag l has the same parity, (P' + lag) mod 2, and so
+        // the same byte shift: the source lane shifts its own word by it (joining it with
+        // the next word of its row), and one lane read per lag suffices.
+        const int nxt = used ? 4 * (sl * gw + p * Wr + ((g4 + 1 == Wr) ? 0 : g4 + 1)) : 4 * lane;
+        int src[kTauLags];
+        uint32_t ssh[kTauLags];
+#pragma unroll
+        for (int l = 0; l < kTauLags; ++l) {
+            const int q = p + lag[l];
+            const int sh = q >> 1;                 // slices to move along the row
+            int j = g4 + (sh >> 2);                // sh / 4 <= Mh / 8 < Wr
+            if (j >= Wr) j -= Wr;
+            src[l] = used ? 4 * (sl * gw + (q & 1) * Wr + j) : 4 * lane;
+            const int pr = (p + lag[l]) & 1;       // the parity of the lanes that read this row
+            ssh[l] = (uint32_t)(((pr + lag[l]) >> 1) & 3);
+        }
+        const int waves = gridDim.y * (blockDim.x >> 6);
+        const int w0 = blockIdx.y * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        uint32_t pc[kTauLags];
+#pragma unroll
+        for (int l = 0; l < kTauLags; ++l) pc[l] = 0;
+        int npos = 0;
+        // four site groups per step, their loads issued together
+        constexpr int kU = 4;
+        const int step = waves * spw;
+        const uint32_t row0 = (uint32_t)p * (uint32_t)N;
+        for (int s0 = w0 * spw; s0 < N; s0 += kU * step) {
+            uint32_t X[kU];
+            bool ok[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = s0 + u * step + sl;
+                ok[u] = used && i < N;
+                X[u] = ok[u] ? rep32[(row0 + (uint32_t)i) * (uint32_t)Wr + (uint32_t)g4] : 0u;
+                npos += ok[u] ? 1 : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t Xn = (uint32_t)__builtin_amdgcn_ds_bpermute(nxt, (int)X[u]);
+#pragma unroll
+                for (int l = 0; l < kTauLags; ++l) {
+                    const uint32_t V = __builtin_amdgcn_alignbyte(Xn, X[u], ssh[l]);
+                    const uint32_t Y = (uint32_t)__builtin_amdgcn_ds_bpermute(src[l], (int)V);
+                    pc[l] += ok[u] ? (uint32_t)__popc(X[u] ^ Y) : 0u;
+                }
+            }
+        }
+        // Four products per position; a differing byte pair contributes -1 instead of +1.
+        // The wave's sums (32-bit: a replica holds at most 2 N M < 2^31 products) go
+        // straight to the rung's accumulators, one lag per lane of lanes 0..7; waves
+        // without sites add nothing.
+        if (w0 * spw >= N) return;
+        int v[kTauLags];
+#pragma unroll
+        for (int l = 0; l < kTauLags; ++l) v[l] = 4 * npos - 2 * (int)pc[l];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+            for (int l = 0; l < kTauLags; ++l) v[l] += __shfl_xor(v[l], o);
+        if (lane < kTauLags) {
+            int mine = v[0];
+#pragma unroll
+            for (int l = 1; l < kTauLags; ++l) mine = (lane == l) ? v[l] : mine;
+            const int r = st.rung_of[g];
+            atomicAdd(reinterpret_cast<unsigned long long *>(&st.sumCt[((int64_t)d.rep_base + r) * kTauLags + lane]),
+                      (unsigned long long)(long long)mine);
+        }
+        return;
+    } else if (M >= 2 && (Mh & 3) == 0) {
         // whole words: the four bytes from slice m2 on are two aligned words joined by a
         // byte alignment (rows hold Mh / 4 words, cyclically), and a byte pair differs
         // iff its xor is 1, so one popcount counts four products at once

@@ -52,6 +52,9 @@ def small_batch():
         W.random_small_instance(rng, 13, 24, 5, d=4, jmax=2, hmax=2, name="m24"),
         W.random_small_instance(rng, 20, 64, 6, d=3, jmax=1, hmax=1, name="m64"),
         W.config1(),
+        # one word per row (two lanes per site), and rows too long for one wave
+        W.random_small_instance(rng, 37, 8, 3, d=2, jmax=1, hmax=1, name="m8"),
+        W.random_small_instance(rng, 5, 512, 3, d=2, jmax=1, hmax=1, name="m512"),
     ]
 
 
