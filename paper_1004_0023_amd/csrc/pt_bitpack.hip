@@ -126,6 +126,8 @@ __device__ __forceinline__ uint32_t spread4(uint32_t v)
 // (kBpSlots = 4 slots) at one four-slice group: item = ((w * Sg + si) * G4 + g4) * 8 + j,
 // the eight lanes of a word are neighbouring and OR their flip masks together.
 constexpr int kBpSlots = 32 / kBpSweepLanes;
+// Sites of at most this degree load all their neighbours' words at once.
+constexpr int kBpMaxDegree = 8;
 
 __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
 {
@@ -179,16 +181,35 @@ __global__ void __launch_bounds__(kBpThreads) bp_sweep_kernel(BpLaunch L)
             // one byte per slot (it is at most F), the lane's 4 slots in one word per slice
             int base = st.hfield[d.site_base + i];
             uint32_t acc[4] = {0u, 0u, 0u, 0u};
-            for (int e = off[i]; e < off[i + 1]; ++e) {
-                const int a = adj[e];
+            auto add_neighbour = [&](int a, const uint4 &Y) {
                 const int J = a >> 16;
                 const uint32_t aJ = (uint32_t)(J < 0 ? -J : J);
                 const uint32_t neg = J < 0 ? 0xFu : 0u;
                 base -= (int)aJ;
-                const uint4 Y = *reinterpret_cast<const uint4 *>(bp_rowp(st, d, w, p, a & 0xFFFF) + 4 * g4);
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     acc[b] += aJ * spread4(((word_of(Y, b) >> sh) & 0xFu) ^ neg);
+            };
+            const int e0 = off[i], deg = off[i + 1] - e0;
+            if (deg <= kBpMaxDegree) {
+                // All entries, then all neighbour words, in flight together (integer sums:
+                // the order cannot matter).  Slots past the degree hold the site itself with
+                // J = 0, so every word load is unconditional (a load under a branch would be
+                // waited for where the branch ends) and adds nothing.
+                int av[kBpMaxDegree];
+                uint4 Yv[kBpMaxDegree];
+#pragma unroll
+                for (int k = 0; k < kBpMaxDegree; ++k) av[k] = (k < deg) ? adj[e0 + k] : i;
+#pragma unroll
+                for (int k = 0; k < kBpMaxDegree; ++k)
+                    Yv[k] = *reinterpret_cast<const uint4 *>(bp_rowp(st, d, w, p, av[k] & 0xFFFF) + 4 * g4);
+#pragma unroll
+                for (int k = 0; k < kBpMaxDegree; ++k) add_neighbour(av[k], Yv[k]);
+            } else {
+                for (int e = e0; e < e0 + deg; ++e) {
+                    const int a = adj[e];
+                    add_neighbour(a, *reinterpret_cast<const uint4 *>(bp_rowp(st, d, w, p, a & 0xFFFF) + 4 * g4));
+                }
             }
             if (byte_index) {
                 // V = x (2F+1) + f + F = x (2F+1) + (base + F) + 2 acc, with base + F >= 0
