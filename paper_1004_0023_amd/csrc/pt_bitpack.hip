@@ -308,15 +308,32 @@ __global__ void __launch_bounds__(kBpThreads) bp_energy_part_kernel(DevState st)
         for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int r = 0; r < 8; ++r) f[b][r] = base;
-        for (int e = off[i]; e < off[i + 1]; ++e) {
-            const int a = adj[e];
+        auto add_neighbour = [&](int a, const uint4 &Y) {
             const int J2 = 2 * (a >> 16);
-            const uint4 Y = *reinterpret_cast<const uint4 *>(bp_rowp(st, d, w, p, a & 0xFFFF) + 4 * g4);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const uint32_t y = word_of(Y, b) >> sh;
 #pragma unroll
                 for (int r = 0; r < 8; ++r) f[b][r] += J2 * (int)((y >> r) & 1u);
+            }
+        };
+        const int e0 = off[i], deg = off[i + 1] - e0;
+        if (deg <= kBpMaxDegree) {
+            // as in the sweep: every word load unconditional, empty slots are the site
+            // itself with J = 0
+            int av[kBpMaxDegree];
+            uint4 Yv[kBpMaxDegree];
+#pragma unroll
+            for (int k = 0; k < kBpMaxDegree; ++k) av[k] = (k < deg) ? adj[e0 + k] : i;
+#pragma unroll
+            for (int k = 0; k < kBpMaxDegree; ++k)
+                Yv[k] = *reinterpret_cast<const uint4 *>(bp_rowp(st, d, w, p, av[k] & 0xFFFF) + 4 * g4);
+#pragma unroll
+            for (int k = 0; k < kBpMaxDegree; ++k) add_neighbour(av[k], Yv[k]);
+        } else {
+            for (int e = e0; e < e0 + deg; ++e) {
+                const int a = adj[e];
+                add_neighbour(a, *reinterpret_cast<const uint4 *>(bp_rowp(st, d, w, p, a & 0xFFFF) + 4 * g4));
             }
         }
         // the next slice k + 1 of slice k = 2m + p: parity 1 index m (p = 0), parity 0
