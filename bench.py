@@ -191,7 +191,16 @@ def main():
     s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags,
                       tile_bytes=args.tile_bytes, block_threads=args.block_threads,
                       encoding=encoding)
-    s.run(args.warmup)  # the first launches also tune the launch shape
+    # Untimed set-up: without a launch shape given, the first sweep calls time the candidate
+    # shapes (two rounds of 15); run cycles until that is done, whatever W is, so that
+    # neither the warm-up nor the timed steps include tuning.  Then the W warm-up cycles.
+    for _ in range(64):
+        if s.info()["tuned"]:
+            break
+        s.run(1)
+    if not s.info()["tuned"]:
+        raise RuntimeError("launch-shape tuning did not finish in 64 cycles")
+    s.run(args.warmup)
     s.sync()
     s.timing_reset()
     torch.cuda.synchronize()

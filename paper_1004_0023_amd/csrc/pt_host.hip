@@ -827,15 +827,20 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
 }
 
 // Self-tuning: while candidates remain, each sweep launch uses the next candidate shape
-// and is timed (synchronously) with its own events; afterwards the fastest per-sweep
-// shape is kept.  Launch shape does not change the trajectory, so tuning costs only the
-// slower candidates' extra time.
+// and is timed (synchronously) with its own events.  The candidates are run in
+// kTuneRounds rounds, each keeping its best per-sweep time (one timing of a short call
+// can be off by more than the gap between shapes), and the fastest shape is kept.
+// Launch shape does not change the trajectory, so tuning costs only the slower
+// candidates' extra time.
+constexpr size_t kTuneRounds = 2;
 int enqueue_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
 {
     if (n_sweeps <= 0) return PT_OK;
     if (c->plan.encoding == PT_BITPACK32) return enqueue_bp_sweep(c, n_sweeps);
     if (!c->tuning) return enqueue_sweep_once(c, n_sweeps, fuse_exchange);
-    const auto shape = c->cand[c->cand_next];
+    const size_t nc = c->cand.size();
+    const size_t k = c->cand_next % nc;
+    const auto shape = c->cand[k];
     int rc = build_tiles(c, 0, shape.first);
     if (rc) return rc;
     c->block_threads = shape.second;
@@ -847,11 +852,12 @@ int enqueue_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
     HIP_TRY(hipEventSynchronize(c->tune_ev[1]));
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, c->tune_ev[0], c->tune_ev[1]));
-    c->cand_ms[c->cand_next] = (c->fallbacks == fb) ? (double)ms / n_sweeps : 1e30;
-    if (++c->cand_next == c->cand.size()) {
+    const double t = (c->fallbacks == fb) ? (double)ms / n_sweeps : 1e30;
+    c->cand_ms[k] = (c->cand_next < nc) ? t : std::min(c->cand_ms[k], t);
+    if (++c->cand_next == kTuneRounds * nc) {
         size_t best = 0;
-        for (size_t k = 1; k < c->cand.size(); ++k)
-            if (c->cand_ms[k] < c->cand_ms[best]) best = k;
+        for (size_t j = 1; j < nc; ++j)
+            if (c->cand_ms[j] < c->cand_ms[best]) best = j;
         c->tuning = false;
         rc = build_tiles(c, 0, c->cand[best].first);
         if (rc) return rc;
