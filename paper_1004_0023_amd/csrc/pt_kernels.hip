@@ -930,21 +930,22 @@ __device__ __forceinline__ PhaseLane phase_lane(const Tile &tile, const SlotSet 
 template <int DT, int PAR>
 __device__ __forceinline__ void block_phase(const BlockArgs &a, const InstDesc &d, const Tile &tile,
                                             const BlockLds &t, const SlotSet &S, const PhaseLane &PL,
-                                            int nt)
+                                            int nt, int g_lo = 0, int g_hi = 1 << 30)
 {
     const int tid = threadIdx.x;
     const int D = (DT > 0) ? DT : d.D;
     const int ns = S.ns;
     const int lanes = tile.P * ns;  // per site
+    g_hi = min(g_hi, d.n_colors);
     if (lanes <= nt) {
-        for (int g = 0; g < d.n_colors; ++g) {
+        for (int g = g_lo; g < g_hi; ++g) {
             const int s1 = t.coff[g + 1];
             for (int si = t.coff[g] + PL.s_first; si < s1; si += PL.sstep)
                 block_item<DT, PAR>(a, t, D, t.csite[si], PL.q, PL.sl);
             __syncthreads();
         }
     } else {
-        for (int g = 0; g < d.n_colors; ++g) {
+        for (int g = g_lo; g < g_hi; ++g) {
             const int s0 = t.coff[g];
             const int items = (t.coff[g + 1] - s0) * lanes;
             for (int it = tid; it < items; it += nt) {
@@ -1003,19 +1004,22 @@ __device__ __forceinline__ SweepSets split_sweep_sets(const Tile &tile, int nt)
 // overlaps work: phase 0 first over slots 2..ng, which read no halo; then halos_in() (the
 // neighbours' parity-1 groups of the previous sweep into the halo slots); phase 0 over
 // slots 1 and ng+1; phase 1 over slots 1 and ng, the groups the neighbours need; then
-// publish(); and phase 1 over slots 2..ng-1 while the neighbours go on.
-template <int DT, class HalosIn, class Publish>
+// records() stores them; phase 1 over slots 2..ng-1 while the neighbours go on, with
+// commit() after its first colour class, when the record stores have long completed.
+template <int DT, class HalosIn, class Records, class Commit>
 __device__ __forceinline__ void block_sweep_split(const BlockArgs &a, const InstDesc &d,
                                                   const Tile &tile, const BlockLds &t,
                                                   const SweepSets &w, HalosIn &&halos_in,
-                                                  Publish &&publish)
+                                                  Records &&records, Commit &&commit)
 {
     block_phase<DT, 0>(a, d, tile, t, w.s[0], w.l[0], w.nt);
     halos_in();
     block_phase<DT, 0>(a, d, tile, t, w.s[1], w.l[1], w.nt);
     block_phase<DT, 1>(a, d, tile, t, w.s[2], w.l[2], w.nt);
-    publish();
-    block_phase<DT, 1>(a, d, tile, t, w.s[3], w.l[3], w.nt);
+    records();
+    block_phase<DT, 1>(a, d, tile, t, w.s[3], w.l[3], w.nt, 0, 1);
+    commit();
+    block_phase<DT, 1>(a, d, tile, t, w.s[3], w.l[3], w.nt, 1);
 }
 
 // Workgroups go to the XCDs (each with its own L2 cache) round robin by index.  The slice
@@ -1321,16 +1325,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
     // progress.  Every wave waits for its record stores to reach the L2 (vmcnt 0; a
     // workgroup release does not wait for them), then one agent-scope release by thread 0
     // (one write-back of the XCD's L2) precedes the progress count.
-    auto publish = [&](int sw) {
+    auto store_records = [&](int sw) {
         uint32_t *rout = st.halo + (int64_t)((tsw + sw + 1) & 1) * st.halo_words + tile.hb;
         for (int i = tid; i < N; i += nt) {
             rout[N + i] = sp32[block_at(a, 1, 0, i, 1) >> 2];
             rout[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
         }
+    };
+    auto commit = [&](int sw) {
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
         if (tid == 0)
             __hip_atomic_store(&st.prog[bt], sw + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    auto publish = [&](int sw) {
+        store_records(sw);
+        commit(sw);
     };
     // the sweep loop, instantiated per degree (the switch stays outside the loop, so only one
     // degree's phase set-up is live in it)
@@ -1352,7 +1362,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
                         }
                     },
                     [&]() {
-                        if (sw + 1 < n_sw) publish(sw);
+                        if (sw + 1 < n_sw) store_records(sw);
+                    },
+                    [&]() {
+                        if (sw + 1 < n_sw) commit(sw);
                     });
             } else {
                 if (PERSIST && sw > 0) wait_halos(sw);
