@@ -430,6 +430,7 @@ struct pt_ctx {
     // timing
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, int>> sweep_ev, exch_ev;  // indices into ev_pool
+    std::vector<int> sweep_ev_calls;  // sweep calls each sweep_ev pair covers
     size_t ev_used = 0;
     double sweep_ms = 0, exch_ms = 0;
     int64_t sweep_n = 0, exch_n = 0;
@@ -582,11 +583,12 @@ int harvest_events(pt_ctx *c)
 {
     if (c->ev_used == 0) return PT_OK;
     HIP_TRY(hipStreamSynchronize(c->stream));
-    for (auto &p : c->sweep_ev) {
+    for (size_t k = 0; k < c->sweep_ev.size(); ++k) {
+        const auto &p = c->sweep_ev[k];
         float ms = 0;
         HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[p.first], c->ev_pool[p.second]));
         c->sweep_ms += ms;
-        c->sweep_n++;
+        c->sweep_n += k < c->sweep_ev_calls.size() ? c->sweep_ev_calls[k] : 1;
     }
     for (auto &p : c->exch_ev) {
         float ms = 0;
@@ -595,6 +597,7 @@ int harvest_events(pt_ctx *c)
         c->exch_n++;
     }
     c->sweep_ev.clear();
+    c->sweep_ev_calls.clear();
     c->exch_ev.clear();
     c->ev_used = 0;
     return PT_OK;
@@ -722,17 +725,36 @@ int enqueue_bp_sweep(pt_ctx *c, int n_sweeps)
     if (timing) {
         HIP_TRY(hipEventRecord(c->ev_pool[eb], c->stream));
         c->sweep_ev.emplace_back(ea, eb);
+        c->sweep_ev_calls.push_back(1);
     }
     return PT_OK;
 }
 
 // n_sweeps sweeps of every tile; with fuse_exchange the tile that completes an instance
 // then runs the instance's exchange step (a PT cycle in one set of launches).
-int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
+// Every tile a fast whole-replica tile holding a whole instance (the condition for a
+// launch of several PT cycles).
+bool whole_instance_tiles(const pt_ctx *c)
+{
+    if (c->n_generic_tiles != 0 || c->n_block_tiles != 0 || c->n_fast_tiles != n_inst_of(c))
+        return false;
+    for (int k = 0; k < c->n_fast_tiles; ++k) {
+        const Tile &t = c->tiles[k];
+        if (t.c0 != 0 || t.P != c->plan.desc[t.inst].R) return false;
+    }
+    return true;
+}
+
+// enqueue_sweep_once with cycles > 1 found the tiles no longer whole instances (after a
+// launch-failure fallback): nothing was queued, run the cycles one by one.
+constexpr int kCycleByCycle = 1;
+
+int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange, int cycles = 1)
 {
     if (n_sweeps <= 0) return PT_OK;
     const bool timing = (c->opt.flags & PT_FLAG_TIMING) != 0;
     for (;;) {
+        if (cycles > 1 && !whole_instance_tiles(c)) return kCycleByCycle;
         SweepLaunch L{};
         L.st = c->st;
         L.key0 = c->key_flip0;
@@ -744,6 +766,7 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
         L.swap_key0 = c->key_swap0;
         L.swap_key1 = c->key_swap1;
         L.t_add = (uint32_t)n_sweeps;
+        L.cycles = cycles;
         int ea = -1, eb = -1;
         if (timing) {
             int rc = event_pair(c, ea, eb);
@@ -802,6 +825,7 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange)
             if (timing) {
                 HIP_TRY(hipEventRecord(c->ev_pool[eb], c->stream));
                 c->sweep_ev.emplace_back(ea, eb);
+                c->sweep_ev_calls.push_back(cycles);
             }
             return PT_OK;
         }
@@ -1148,6 +1172,23 @@ int pt_run(pt_ctx *c, int32_t n_cycles)
 {
     if (!c) return fail(PT_EINVAL, "null context");
     if (n_cycles < 0) return fail(PT_EINVAL, "n_cycles < 0");
+    // Batches whose instances each fit one whole-replica tile run up to kLaunchCycles
+    // cycles per launch, each workgroup doing its instance's exchange steps itself (no
+    // launch per cycle, no graph).  Not with the correlations (a launch of their own per
+    // exchange), while tuning, or with a launch failure to inject.
+    constexpr int kLaunchCycles = 1024;
+    if (n_cycles > 1 && c->plan.encoding == PT_INT8 && !(c->opt.flags & PT_FLAG_TAU_CORR) &&
+        !c->tuning && !c->inject_pending && whole_instance_tiles(c)) {
+        const int k = c->opt.sweeps_per_exchange;
+        while (n_cycles > 0) {
+            const int m = std::min(n_cycles, kLaunchCycles);
+            const int rc = enqueue_sweep_once(c, k, true, m);
+            if (rc == kCycleByCycle) break;
+            if (rc) return rc;
+            n_cycles -= m;
+        }
+        if (n_cycles == 0) return PT_OK;
+    }
     const bool eager = (c->opt.flags & (PT_FLAG_NO_GRAPH | PT_FLAG_TIMING)) != 0 ||
                        c->inject_pending || c->tuning;
     if (eager) {

@@ -26,6 +26,9 @@ struct SweepLaunch {
     // amount added to every awaited progress count (0; a test hook sets it so that the
     // waits run into their bound)
     int32_t wait_polls, wait_extra;
+    // fused whole-replica launches whose tiles each hold a whole instance: PT cycles run by
+    // the launch (0 or 1: one)
+    int32_t cycles;
 };
 
 // Lanes per 32-slot word in the bit-packed sweep (each serves 32 / kBpSweepLanes slots).

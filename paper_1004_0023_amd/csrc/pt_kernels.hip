@@ -330,7 +330,8 @@ __device__ void exchange_instance(const DevState &st, int n, uint32_t key0, uint
     const int R = d.R;
     const int base = d.rep_base;
     const int pb = d.pair_base;
-    const uint64_t e = st.ctr[n].e;
+    // a vector load: a workgroup that runs several cycles in one launch updates e itself
+    const uint64_t e = __hip_atomic_load(&st.ctr[n].e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int par = (int)(e & 1u);
     for (int j = threadIdx.x;; j += blockDim.x) {
         const int r = par + 2 * j;
@@ -699,8 +700,10 @@ __device__ __forceinline__ void fast_energy(const DevState &st, const InstDesc &
     }
 }
 
-template <bool FUSE>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) sweep_fast_kernel(SweepLaunch L)
+// MULTI: a fused launch of L.cycles PT cycles (its own instantiation, bounded at four
+// waves per SIMD: the exchange step in the loop needs more registers than eight allow).
+template <bool FUSE, bool MULTI = false>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MULTI ? 4 : 8))) sweep_fast_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
@@ -709,24 +712,39 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const InstDesc d = st.inst[n];
     TileLds t = carve(lds, d, 0, tile.P);
     stage_common(st, d, n, tile, t, 0);
-    const uint64_t t0 = st.ctr[n].t;
+    uint64_t t0 = st.ctr[n].t;
     __syncthreads();
 
-    if (L.lane_words == 2 && d.G4 >= 2)
-        fast_dispatch<2>(L, d, tile, t, t0);
-    else
-        fast_dispatch<1>(L, d, tile, t, t0);
+    // With MULTI (fused launches whose tiles each hold a whole instance) the workgroup
+    // runs L.cycles PT cycles: after each but the last it does the instance's exchange
+    // step itself, with the replicas still in LDS, then stages the threshold tables of
+    // the replicas' new rungs and reads the advanced sweep counter.
+    for (int cyc = 0;; ++cyc) {
+        if (L.lane_words == 2 && d.G4 >= 2)
+            fast_dispatch<2>(L, d, tile, t, t0);
+        else
+            fast_dispatch<1>(L, d, tile, t, t0);
 
-    switch (d.D) {
-    case 1: fast_energy<1>(st, d, tile, t); break;
-    case 2: fast_energy<2>(st, d, tile, t); break;
-    case 3: fast_energy<3>(st, d, tile, t); break;
-    case 4: fast_energy<4>(st, d, tile, t); break;
-    case 5: fast_energy<5>(st, d, tile, t); break;
-    case 6: fast_energy<6>(st, d, tile, t); break;
-    case 7: fast_energy<7>(st, d, tile, t); break;
-    case 8: fast_energy<8>(st, d, tile, t); break;
-    default: fast_energy<0>(st, d, tile, t); break;
+        switch (d.D) {
+        case 1: fast_energy<1>(st, d, tile, t); break;
+        case 2: fast_energy<2>(st, d, tile, t); break;
+        case 3: fast_energy<3>(st, d, tile, t); break;
+        case 4: fast_energy<4>(st, d, tile, t); break;
+        case 5: fast_energy<5>(st, d, tile, t); break;
+        case 6: fast_energy<6>(st, d, tile, t); break;
+        case 7: fast_energy<7>(st, d, tile, t); break;
+        case 8: fast_energy<8>(st, d, tile, t); break;
+        default: fast_energy<0>(st, d, tile, t); break;
+        }
+        if (!(FUSE && MULTI) || cyc + 1 >= L.cycles) break;
+        // only this workgroup reads what the exchange writes: its barriers order it; the
+        // counters are re-read with vector loads (a scalar-cache copy would be stale)
+        __syncthreads();
+        exchange_instance(st, n, L.swap_key0, L.swap_key1, L.t_add);
+        __syncthreads();
+        stage_tables(st, d, tile.c0, tile.P, t.tbl);
+        t0 = __hip_atomic_load(&st.ctr[n].t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
     }
     write_back(st, d, tile, t);
     if constexpr (FUSE) finish_tile(L, st, n, t.red);
@@ -1782,6 +1800,7 @@ hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int3
         {reinterpret_cast<const void *>(&sweep_block_kernel<true, true>), block_bytes},
         {reinterpret_cast<const void *>(&sweep_fast_kernel<false>), fast_bytes},
         {reinterpret_cast<const void *>(&sweep_fast_kernel<true>), fast_bytes},
+        {reinterpret_cast<const void *>(&sweep_fast_kernel<true, true>), fast_bytes},
         {reinterpret_cast<const void *>(&sweep_generic_kernel<false>), generic_bytes},
         {reinterpret_cast<const void *>(&sweep_generic_kernel<true>), generic_bytes},
     };
@@ -1827,7 +1846,9 @@ hipError_t launch_sweep(const SweepLaunch &L, int kind, hipStream_t s)
     const dim3 grid(L.n_tiles), block(L.block_threads);
     const bool fuse = L.fuse_exchange != 0;
     if (kind == kTileFast) {
-        if (fuse)
+        if (fuse && L.cycles > 1)
+            hipLaunchKernelGGL((sweep_fast_kernel<true, true>), grid, block, L.lds_bytes, s, L);
+        else if (fuse)
             hipLaunchKernelGGL(sweep_fast_kernel<true>, grid, block, L.lds_bytes, s, L);
         else
             hipLaunchKernelGGL(sweep_fast_kernel<false>, grid, block, L.lds_bytes, s, L);

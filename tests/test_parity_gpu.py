@@ -393,24 +393,28 @@ def test_replica_too_large_is_refused(ptqmc):
     assert ei.value.code == ptqmc.PT_EINVAL and "does not fit" in str(ei.value)
 
 
-@pytest.mark.parametrize("mode", ["tiles", "slice_blocks", "bitpack", "tau"])
+@pytest.mark.parametrize("mode", ["tiles", "whole_tiles", "slice_blocks", "bitpack", "tau"])
 def test_every_graph_replay_matches_oracle(ptqmc, mode):
     """pt_run replays a captured graph of 16 cycles.  Three replays, with eager
     pt_sweep / pt_exchange calls and synchronisations between them, each checked against
-    the oracle: whole-replica tiles (fused cycles), resident slice blocks, the packed
-    encoding, and the correlation accumulators."""
+    the oracle: whole-replica tiles of one replica each (fused cycles), resident slice
+    blocks, the packed encoding, and the correlation accumulators.  With every instance
+    in one tile (whole_tiles) a run(16) is instead one launch of 16 cycles, each
+    workgroup doing its instance's exchange steps itself."""
     insts = fast_batch()[:5]
     seed = 0x6A7
     k = 2
-    flags = {"tiles": 0, "slice_blocks": ptqmc.PT_FLAG_SLICE_BLOCKS, "bitpack": 0,
-             "tau": ptqmc.PT_FLAG_TAU_CORR}[mode]
+    flags = {"tiles": 0, "whole_tiles": 0, "slice_blocks": ptqmc.PT_FLAG_SLICE_BLOCKS,
+             "bitpack": 0, "tau": ptqmc.PT_FLAG_TAU_CORR}[mode]
     enc = ptqmc.PT_BITPACK32 if mode == "bitpack" else ptqmc.PT_INT8
     keys = KEYS + (("sumCt",) if mode == "tau" else ())
     say(f"case: graph replays, {mode}")
     refs = [oracle.OracleChain(inst, seed, index=n) for n, inst in enumerate(insts)]
     # a fixed block size turns the launch-shape tuner off, so every run(16) is a replay
+    # (or, for whole_tiles, one multi-cycle launch); one replica per tile keeps "tiles" on
+    # the graph path
     with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags, encoding=enc,
-                       block_threads=256) as s:
+                       block_threads=256, tile_replicas=1 if mode == "tiles" else 0) as s:
         for rep in range(3):
             s.run(16)  # one replay of the captured 16-cycle graph
             s.sync()
