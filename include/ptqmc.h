@@ -207,7 +207,11 @@ int pt_exchange(pt_ctx *ctx);
  * pt_sweep(k) + pt_exchange() per cycle (Figure 6's loop).  Cycles are replayed from a HIP
  * graph; for batches of at most 64 tiles each cycle is a single set of launches in which
  * the workgroup that finishes an instance's last tile runs that instance's exchange step
- * (per-instance completion counts), larger batches launch the exchange separately. */
+ * (per-instance completion counts), larger batches launch the exchange separately.  When
+ * every instance fits one tile (and PT_FLAG_TAU_CORR is off) up to 1024 cycles run in one
+ * launch instead, each workgroup doing its instance's exchange steps itself.  The chain
+ * is the same in every case; with PT_FLAG_TIMING such a launch counts as one sweep call per
+ * cycle. */
 int pt_run(pt_ctx *ctx, int32_t n_cycles);
 
 /* Wait for all work queued on the context's stream. */
