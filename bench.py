@@ -192,7 +192,7 @@ def main():
                       tile_bytes=args.tile_bytes, block_threads=args.block_threads,
                       encoding=encoding)
     # Untimed set-up: without a launch shape given, the first sweep calls time the candidate
-    # shapes (two rounds of 15); run cycles until that is done, whatever W is, so that
+    # shapes (three rounds of 15); run cycles until that is done, whatever W is, so that
     # neither the warm-up nor the timed steps include tuning.  Then the W warm-up cycles.
     for _ in range(64):
         if s.info()["tuned"]:

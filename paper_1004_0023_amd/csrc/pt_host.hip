@@ -856,7 +856,7 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange, int cycles =
 // can be off by more than the gap between shapes), and the fastest shape is kept.
 // Launch shape does not change the trajectory, so tuning costs only the slower
 // candidates' extra time.
-constexpr size_t kTuneRounds = 2;
+constexpr size_t kTuneRounds = 3;
 int enqueue_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
 {
     if (n_sweeps <= 0) return PT_OK;

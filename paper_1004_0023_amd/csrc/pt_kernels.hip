@@ -206,47 +206,16 @@ __device__ __forceinline__ void copy_spins(uint32_t *lds_sp, uint32_t *dev, int 
         uint4 *D4 = reinterpret_cast<uint4 *>(dev);
         const int qs = nt / wv, rs = nt - qs * wv;
         int q = threadIdx.x / wv, r = threadIdx.x - q * wv;
-        if (IN) {
-            // four pieces in flight per thread: every load is issued (positions past the
-            // last replica read its first piece again) and only the stores are predicated
-            constexpr int kU = 4;
-            while (q < P) {
-                int qq[kU], rr[kU];
-                uint4 v[kU];
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    qq[u] = q;
-                    rr[u] = r;
-                    q += qs;
-                    r += rs;
-                    if (r >= wv) {
-                        r -= wv;
-                        ++q;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const bool ok = qq[u] < P;
-                    v[u] = D4[(int64_t)(ok ? qq[u] : P - 1) * dv + (ok ? rr[u] : 0)];
-                }
-                // the values are taken here, all four at once: without this the compiler
-                // sinks each load into its predicated store and waits for them one by one
-#pragma unroll
-                for (int u = 0; u < kU; ++u)
-                    __asm__ volatile("" : "+v"(v[u].x), "+v"(v[u].y), "+v"(v[u].z), "+v"(v[u].w));
-#pragma unroll
-                for (int u = 0; u < kU; ++u)
-                    if (qq[u] < P) L4[qq[u] * lv + rr[u]] = v[u];
-            }
-        } else {
-            for (; q < P;) {
+        for (; q < P;) {
+            if (IN)
+                L4[q * lv + r] = D4[(int64_t)q * dv + r];
+            else
                 D4[(int64_t)q * dv + r] = L4[q * lv + r];
-                q += qs;
-                r += rs;
-                if (r >= wv) {
-                    r -= wv;
-                    ++q;
-                }
+            q += qs;
+            r += rs;
+            if (r >= wv) {
+                r -= wv;
+                ++q;
             }
         }
     } else {
