@@ -187,7 +187,7 @@ def main():
     print(f"bench: {desc}; {steps} steps of {k} sweeps + exchange", file=sys.stderr, flush=True)
 
     encoding = ptqmc.PT_BITPACK32 if args.encoding == "bitpack" else ptqmc.PT_INT8
-    flags = ptqmc.PT_FLAG_TIMING | (ptqmc.PT_FLAG_TAU_CORR if args.tau_corr else 0)
+    flags = ptqmc.PT_FLAG_TAU_CORR if args.tau_corr else 0
     s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags,
                       tile_bytes=args.tile_bytes, block_threads=args.block_threads,
                       encoding=encoding)
@@ -202,10 +202,11 @@ def main():
         raise RuntimeError("launch-shape tuning did not finish in 64 cycles")
     s.run(args.warmup)
     s.sync()
-    s.timing_reset()
     torch.cuda.synchronize()
-    # the K steps run as five equal segments, each closed by a synchronisation, so the
-    # spread of the rate is visible; the reported value is all K steps over the whole time
+    # The timed region is pt_run's own route (graph replays, or multi-cycle launches when
+    # every instance fits one tile), with no events inside it.  The K steps run as five
+    # equal segments, each closed by a synchronisation, so the spread of the rate is
+    # visible; the reported value is all K steps over the whole time.
     n_seg = 5 if steps >= 5 else 1
     bounds = [steps * j // n_seg for j in range(n_seg + 1)]
     seg_s = []
@@ -221,31 +222,55 @@ def main():
     flips_per_step = k * int(info["flips_per_sweep"])
     value = steps * flips_per_step / elapsed
     seg_rates = [(bounds[j + 1] - bounds[j]) * flips_per_step / seg_s[j] for j in range(n_seg)]
-    # One sweep call (k sweeps of every replica) is timed with HIP events on the
-    # library's stream.  It runs as one launch per occupancy class of whole-replica
-    # tiles; replicas split into slice blocks run all k sweeps in one launch when every
-    # block can be resident at once, else one launch per sweep.  The roofline is quoted
-    # per launch of the dominant kernel, the call's algorithmic work and event time
-    # divided by its launch count, so the mean launch duration is the one a kernel trace
-    # reports.
-    avg_sweep_s = info["sweep_ms"] / max(1, info["sweep_launches"]) / 1e3
-    blocked = info["block_tiles"] > 0
+    route = "multi-cycle launches" if info["multi_launches"] > 0 else "graph replays"
+
+    # Calibration pass, right after the timed region on the same context: timing switched
+    # on, pt_run launches cycle by cycle with HIP events on the library's stream around
+    # every sweep call (one launch per occupancy class of whole-replica tiles; slice
+    # blocks: one resident launch per call, or one per sweep; packed: one per colour
+    # class) and every exchange launch; multi-cycle launches are timed whole.  The
+    # roofline is quoted per launch of the dominant kernel: the call's algorithmic work
+    # and event time divided by its launch count, so the mean launch duration is the one
+    # a kernel trace of the timed route reports.
+    multi = info["multi_launches"] > 0
+    cal_cycles = 4096 if multi else max(1, min(steps, 100))
+    s.timing_reset()
+    pre = s.info()
+    s.timing_enable(True)
+    s.run(cal_cycles)
+    s.sync()
+    cal = s.info()
+    s.timing_enable(False)
+    # the launch counts of multi-cycle launches run on; keep this pass's
+    cal["multi_launches"] -= pre["multi_launches"]
+    cal["multi_cycles"] -= pre["multi_cycles"]
+    blocked = cal["block_tiles"] > 0
     packed = encoding == ptqmc.PT_BITPACK32
-    if packed:
-        # one launch per colour class and sweep, plus the two energy launches of the call
-        kernel = "bp_sweep_kernel"
-        launches_per_call = k * max(1, info["class_launches"])
-    elif blocked:
-        kernel = "sweep_block_kernel"
-        launches_per_call = 1 if info["block_resident"] else k
-    else:
+    if multi:
         kernel = "sweep_fast_kernel"
-        launches_per_call = max(1, info["sweep_groups"])
+        cycles_per_launch = cal["multi_cycles"] / max(1, cal["multi_launches"])
+        launch_s = cal["multi_ms"] / max(1, cal["multi_launches"]) / 1e3
+        calls_per_launch = cycles_per_launch
+        launches_per_call = 1.0 / cycles_per_launch
+        avg_sweep_s = launch_s / cycles_per_launch  # one cycle, its exchange included
+    else:
+        avg_sweep_s = cal["sweep_ms"] / max(1, cal["sweep_launches"]) / 1e3
+        if packed:
+            # one launch per colour class and sweep, plus the two energy launches of the call
+            kernel = "bp_sweep_kernel"
+            launches_per_call = k * max(1, cal["class_launches"])
+        elif blocked:
+            kernel = "sweep_block_kernel"
+            launches_per_call = 1 if cal["block_resident"] else k
+        else:
+            kernel = "sweep_fast_kernel"
+            launches_per_call = max(1, cal["sweep_groups"])
+        launch_s = avg_sweep_s / launches_per_call
+        calls_per_launch = 1.0 / launches_per_call
     ops_call = 0.0
     for inst in insts:
         ops_call += k * inst.flips_per_sweep * ops_per_flip(2.0 * inst.n_edges / inst.N)
-    ops_launch = ops_call / launches_per_call
-    launch_s = avg_sweep_s / launches_per_call
+    ops_launch = ops_call * calls_per_launch
     achieved = ops_launch / launch_s / 1e12 if launch_s > 0 else 0.0
     peak = PEAK_INT_OPS / 1e12
     if packed:
@@ -268,18 +293,22 @@ def main():
         "config": {"workload": desc, "instances": len(insts), "sweeps_per_exchange": k,
                    "flips_per_step": flips_per_step, "tiles": info["n_tiles"],
                    "tile_bytes": info["tile_bytes"], "block_threads": info["block_threads"],
-                   "lds_bytes": info["lds_bytes"], "sweep_call_ms": avg_sweep_s * 1e3,
-                   "exchange_kernel_ms": info["exchange_ms"] / max(1, info["exchange_launches"]),
-                   "sweep_kernel_flips_per_s": flips_per_step / avg_sweep_s if avg_sweep_s else None,
-                   "sweep_launches_per_step": launches_per_call,
+                   "lds_bytes": info["lds_bytes"], "timed_route": route,
                    "encoding": args.encoding,
                    "tau_corr": bool(args.tau_corr),
-                   "block_resident": bool(info["block_resident"]) if blocked else None,
+                   "block_resident": bool(cal["block_resident"]) if blocked else None,
                    "segment_rates": {"segments": n_seg,
                                      "mean": statistics.mean(seg_rates),
                                      "std": statistics.pstdev(seg_rates),
                                      "median": statistics.median(seg_rates)},
-                   "mean_launch_ms": launch_s * 1e3, "ops_per_launch": ops_launch},
+                   "calibration": {"cycles": cal_cycles,
+                                   "sweep_call_ms": avg_sweep_s * 1e3,
+                                   "sweep_kernel_flips_per_s": flips_per_step / avg_sweep_s
+                                   if avg_sweep_s else None,
+                                   "exchange_kernel_ms": cal["exchange_ms"] / max(1, cal["exchange_launches"]),
+                                   "launches_per_call": launches_per_call,
+                                   "mean_launch_ms": launch_s * 1e3,
+                                   "ops_per_launch": ops_launch}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak,
                      "traffic": traffic_per_launch() if args.config == 3 and not packed else None,

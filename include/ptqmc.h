@@ -181,6 +181,11 @@ typedef struct {
                                          per sweep                                      */
     int32_t class_launches;           /* PT_BITPACK32: sweep launches per sweep (one per
                                          colour class); 0 under PT_INT8                 */
+    int64_t multi_launches;           /* pt_run launches that ran several PT cycles each
+                                         (batches whose instances each fit one tile)    */
+    int64_t multi_cycles;             /* PT cycles those launches ran                  */
+    double multi_ms;                  /* their summed event time under PT_FLAG_TIMING
+                                         (not part of sweep_ms / exchange_ms)           */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided
@@ -208,10 +213,11 @@ int pt_exchange(pt_ctx *ctx);
  * graph; for batches of at most 64 tiles each cycle is a single set of launches in which
  * the workgroup that finishes an instance's last tile runs that instance's exchange step
  * (per-instance completion counts), larger batches launch the exchange separately.  When
- * every instance fits one tile (and PT_FLAG_TAU_CORR is off) up to 1024 cycles run in one
- * launch instead, each workgroup doing its instance's exchange steps itself.  The chain
- * is the same in every case; with PT_FLAG_TIMING such a launch counts as one sweep call per
- * cycle. */
+ * every instance fits one tile (and neither PT_FLAG_TAU_CORR nor PT_FLAG_NO_GRAPH is set)
+ * up to 1024 cycles run in one launch instead, each workgroup doing its instance's exchange
+ * steps itself; pt_info counts these launches (multi_launches, multi_cycles) and, with
+ * PT_FLAG_TIMING, times them apart from the sweep and exchange launches (multi_ms).  With
+ * PT_FLAG_NO_GRAPH every cycle is launched eagerly.  The chain is the same in every case. */
 int pt_run(pt_ctx *ctx, int32_t n_cycles);
 
 /* Wait for all work queued on the context's stream. */
@@ -233,9 +239,26 @@ int pt_set_spins(pt_ctx *ctx, int32_t inst, const int8_t *in);
 int pt_save(pt_ctx *ctx, void *buf, size_t *len);
 int pt_load(pt_ctx *ctx, const void *buf, size_t len);
 
-/* Tuning and timing record; pt_timing_reset zeroes the timing fields (synchronising). */
+/* The checks pt_load makes before it copies anything, without a context or a GPU: with
+ * buf == NULL only *need (if not NULL) receives the checkpoint size for these instances
+ * and options.  Otherwise the checkpoint must have that size and a header written for
+ * them (magic, version, seed, instance count, encoding), PT_INT8 spin bytes must be 0 or
+ * 1, replica_of and rung_of of every instance inverse permutations of [0, R), and labels
+ * PT_LABEL_*: the kernels use these values as indices, so a corrupt checkpoint is refused
+ * with PT_ESTATE rather than loaded.  Layout: a 40-byte header (uint32 magic 0x51505450,
+ * uint32 version, uint64 state bytes, uint64 seed, int32 instances, int32 encoding,
+ * uint64 sum of R*N*M) followed by the state bytes. */
+int pt_checkpoint_validate(const pt_instance *inst, int32_t n_inst, const pt_options *opt,
+                           const void *buf, size_t len, size_t *need);
+
+/* Tuning and timing record; pt_timing_reset zeroes the timing fields (synchronising).
+ * pt_timing_enable switches PT_FLAG_TIMING on (on != 0) or off for the calls that follow
+ * (synchronising): while it is on, pt_run launches cycle by cycle with events around
+ * every launch instead of replaying its graph, so a caller can time the graph route with
+ * it off and take per-launch durations in a separate pass with it on. */
 int pt_get_info(pt_ctx *ctx, pt_info *out);
 int pt_timing_reset(pt_ctx *ctx);
+int pt_timing_enable(pt_ctx *ctx, int32_t on);
 
 void pt_free(pt_ctx *ctx);
 const char *pt_strerror(int code);

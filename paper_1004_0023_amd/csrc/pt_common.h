@@ -137,8 +137,26 @@ struct InstDesc {
     int64_t spin_base; // first spin byte of the instance
     // bit-packed encoding: word groups ceil(R / 32), words per (group, parity, site) row
     // (4 * G4), and the instance's first word group in the batch
-    int32_t bp_W, bp_row, bp_wg_base, bp_pad;
+    int32_t bp_W, bp_row, bp_wg_base;
+    int32_t ent_mode;  // EntMode of the fast-path neighbour entries
 };
+
+// How the byte-SWAR kernels form a site's local field from its neighbour entries.
+//   kEntPerm   32-bit entries (j * Mh) << 16 | w1 << 8 | w0: a v_perm maps each neighbour
+//              spin byte x to its weight w_x (any |J|, padded rows)
+//   kEntXad    the same entries, every |J| = 1 and every site of full degree D: a
+//              neighbour adds its spin byte x, or 1 - x when J < 0, as (x ^ m) + acc with
+//              m = 0x01010101 [J < 0] (one v_xad per word)
+//   kEntXad16  as kEntXad with 16-bit entries (j * Mh) | [J < 0] << 15, for instances
+//              whose one-replica tiles would not otherwise fit two to a compute unit
+enum EntMode { kEntPerm = 0, kEntXad = 1, kEntXad16 = 2 };
+
+// 32-bit words of the fast-path neighbour entries of an instance with N sites and row
+// length D (two 16-bit entries per word under kEntXad16).
+__host__ __device__ __forceinline__ int64_t ent_words(int64_t N, int32_t D, int32_t mode)
+{
+    return mode == kEntXad16 ? (N * D + 1) / 2 : N * D;
+}
 
 enum TileKind { kTileGeneric = 0, kTileFast = 1, kTileBlock = 2 };
 
@@ -168,7 +186,8 @@ struct DevState {
     const int32_t *adj;       // generic neighbour entry: (j & 0xFFFF) | (J << 16)
     const int32_t *adj_off;   // per site: first entry (N + 1 per instance)
     const int16_t *hfield;    // per site
-    const uint32_t *ent;      // fast neighbour entry: (j << ent_sh) << 16 | w1 << 8 | w0
+    const uint32_t *ent;      // fast neighbour entries (EntMode): (j << ent_sh) << 16 | w1 << 8 | w0,
+                              // or 16-bit (j << ent_sh) | [J < 0] << 15 two to a word
     const uint32_t *bias;     // fast per-site bias (h - sum|J| + F) in every byte
     const uint16_t *csite;    // sites of each colour, colour by colour
     const int32_t *cls_off;   // per colour: first class site (n_colors + 1 per instance)

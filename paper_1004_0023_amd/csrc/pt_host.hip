@@ -222,8 +222,30 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
         for (int i = 0; i < in.N; ++i) sites[cls[in.color[i]] + cfill[in.color[i]]++] = (uint16_t)i;
         // fast-path rows: D entries per site, (j << ent_sh) << 16 | w1 << 8 | w0 with w0 / w1 the
         // contribution |J| [J < 0] / |J| [J > 0] of a neighbour whose spin byte is 0 / 1;
-        // padding entries point at the site itself with weight 0
+        // padding entries point at the site itself with weight 0.  With every |J| = 1 and
+        // every site of degree D the kernels add x ^ m (kEntXad); when moreover a one-replica
+        // tile would take more than half a compute unit's LDS, the entries shrink to 16 bits
+        // (kEntXad16: j * Mh fits 15 bits), so that two such tiles fit one unit.
+        d.ent_mode = kEntPerm;
         if (d.fast) {
+            bool unit = true, regular = true;
+            for (int e = 0; e < in.n_edges; ++e) unit = unit && std::abs((int)in.edge_J[e]) == 1;
+            for (int i = 0; i < in.N; ++i) regular = regular && deg[i + 1] - deg[i] == d.D;
+            if (unit && regular && in.n_edges > 0) d.ent_mode = kEntXad;
+            int lg = 0;
+            while ((1 << lg) < d.Mh) ++lg;
+            if (d.ent_mode == kEntXad && d.ent_sh == lg && (int64_t)(in.N - 1) * d.Mh <= 32767 &&
+                d.D >= 4 && d.G4 >= 2 &&
+                !(flags & (PT_FLAG_SLICE_BLOCKS | PT_FLAG_FOUR_SLICE_LANES)) &&
+                sweep_tile_lds_bytes(d, 2 * in.n_edges, 1) > kLdsPerWorkgroup / 2) {
+                InstDesc d16 = d;
+                d16.ent_mode = kEntXad16;
+                if (sweep_tile_lds_bytes(d16, 2 * in.n_edges, 1) <= kLdsPerWorkgroup / 2)
+                    d.ent_mode = kEntXad16;
+            }
+        }
+        if (d.fast) {
+            std::vector<uint32_t> row;
             for (int i = 0; i < in.N; ++i) {
                 int e = deg[i];
                 for (int k = 0; k < d.D; ++k, ++e) {
@@ -233,12 +255,20 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
                         const int J = entries[e] >> 16;
                         const uint32_t w0 = (J < 0) ? (uint32_t)(-J) : 0u;
                         const uint32_t w1 = (J > 0) ? (uint32_t)J : 0u;
-                        word = (((uint32_t)j << d.ent_sh) << 16) | (w1 << 8) | w0;
+                        word = (d.ent_mode == kEntXad16)
+                                   ? (((uint32_t)j << d.ent_sh) | (J < 0 ? 0x8000u : 0u))
+                                   : ((((uint32_t)j << d.ent_sh) << 16) | (w1 << 8) | w0);
                     }
-                    P.ent.push_back(word);
+                    row.push_back(word);
                 }
                 const uint32_t b = (uint32_t)(in.h[i] - sumabs[i] + F) & 0xFFu;
                 P.bias.push_back(b * 0x01010101u);
+            }
+            if (d.ent_mode == kEntXad16) {
+                for (size_t k = 0; k < row.size(); k += 2)
+                    P.ent.push_back(row[k] | (k + 1 < row.size() ? row[k + 1] << 16 : 0u));
+            } else {
+                P.ent.insert(P.ent.end(), row.begin(), row.end());
             }
         } else {
             for (int i = 0; i < in.N; ++i) P.bias.push_back(0);
@@ -275,7 +305,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
         adjb += 2 * (int64_t)in.n_edges;
         offb += in.N + 1;
         siteb += in.N;
-        entb += d.fast ? (int64_t)in.N * d.D : 0;
+        entb += d.fast ? ent_words(in.N, d.D, d.ent_mode) : 0;
         clsb += in.n_colors + 1;
         tblb += (int64_t)in.R * d.tbl_words;
         spinb += bp ? (int64_t)d.bp_W * d.parities * in.N * d.bp_row * 4
@@ -385,6 +415,54 @@ struct CkptHeader {
     int32_t n_inst, encoding;
     uint64_t flips_per_sweep;
 };
+static_assert(sizeof(CkptHeader) == 40, "checkpoint header layout is part of the ABI");
+
+// A checkpoint for these instances and options: the header matches, and every value that
+// the kernels use as an index is in range -- spin bytes in {0, 1} (they index threshold
+// tables; any bit pattern is a valid bit-packed state), replica_of and rung_of inverse
+// permutations of [0, R) per instance (they index energies and tables), labels in
+// {NONE, UP, DOWN}.  Nothing is copied anywhere.
+int check_checkpoint(const Plan &P, const pt_options &opt, int32_t n_inst, const void *buf,
+                     size_t len)
+{
+    if (!buf) return fail(PT_EINVAL, "null checkpoint");
+    if (len < sizeof(CkptHeader)) return fail(PT_ESTATE, "checkpoint too short");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    if (h.magic != kMagic || h.version != kVersion) return fail(PT_ESTATE, "not a checkpoint");
+    if (h.state_bytes != P.state_bytes || h.n_inst != n_inst || h.seed != opt.seed ||
+        h.flips_per_sweep != P.flips_per_sweep || len != sizeof h + h.state_bytes)
+        return fail(PT_ESTATE, "checkpoint belongs to different instances or options");
+    if (h.encoding != opt.encoding)
+        return fail(PT_ESTATE, "checkpoint was written under another spin encoding");
+    const char *state = (const char *)buf + sizeof h;
+    if (P.encoding == PT_INT8) {
+        const uint8_t *sp = (const uint8_t *)(state + (P.o_spins - P.o_state));
+        for (int64_t b = 0; b < P.spin_bytes; ++b)
+            if (sp[b] > 1) return fail(PT_ESTATE, "checkpoint holds invalid spins");
+    }
+    auto i32_at = [&](size_t off, int64_t k) {
+        int32_t v;
+        std::memcpy(&v, state + (off - P.o_state) + 4 * k, 4);
+        return v;
+    };
+    for (int32_t n = 0; n < n_inst; ++n) {
+        const InstDesc &d = P.desc[n];
+        for (int r = 0; r < d.R; ++r) {
+            const int32_t c = i32_at(P.o_repof, d.rep_base + r);
+            if (c < 0 || c >= d.R || i32_at(P.o_rung, d.rep_base + c) != r)
+                return fail(PT_ESTATE, "checkpoint of instance " + std::to_string(n) +
+                                           ": replica_of and rung_of are not inverse permutations");
+        }
+        for (int c = 0; c < d.R; ++c) {
+            const int32_t lab = i32_at(P.o_label, d.rep_base + c);
+            if (lab != PT_LABEL_NONE && lab != PT_LABEL_UP && lab != PT_LABEL_DOWN)
+                return fail(PT_ESTATE, "checkpoint of instance " + std::to_string(n) +
+                                           ": invalid round-trip label");
+        }
+    }
+    return PT_OK;
+}
 
 }  // namespace
 
@@ -434,6 +512,11 @@ struct pt_ctx {
     size_t ev_used = 0;
     double sweep_ms = 0, exch_ms = 0;
     int64_t sweep_n = 0, exch_n = 0;
+    // multi-cycle launches: how many were issued and the cycles they ran (always counted),
+    // and their event time under PT_FLAG_TIMING (kept apart from the sweep calls)
+    std::vector<std::pair<int, int>> multi_ev;
+    double multi_ms = 0;
+    int64_t multi_launches = 0, multi_cycles = 0;
 };
 
 namespace {
@@ -469,6 +552,10 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
             }
         const int lgMh_n = d.fast ? 31 - __builtin_clz((unsigned)d.Mh) : 0;
         const bool blocked = d.fast && (pmax < 1 || d.ent_sh != lgMh_n || (force_blocks && d.G4 >= 2));
+        if (blocked && d.ent_mode == kEntXad16)
+            return fail(PT_EINVAL, "instance " + std::to_string(n) +
+                                       ": 16-bit neighbour entries need whole-replica tiles, "
+                                       "but the device's LDS is smaller than the library assumes");
         if (blocked) {
             // slice blocks: ng four-slice groups per parity, halving until a block fits
             int ng = force_blocks ? std::max(1, d.G4 / 4) : d.G4;
@@ -497,6 +584,11 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
         p = std::max(1, std::min(p, pmax));
         if (d.fast)
             while (!is_pow2(p)) --p;
+        // at most half a compute unit's LDS per tile where fewer replicas allow it, so that
+        // two workgroups share a unit and the batch's tiles form one occupancy class
+        if (force_P <= 0)
+            while (p > 1 && sweep_tile_lds_bytes(d, P.n_adj[n], p) > c->cu_lds / 2)
+                p = d.fast ? p / 2 : p - 1;
         for (int c0 = 0; c0 < d.R;) {
             int q = std::min(p, d.R - c0);
             if (d.fast)
@@ -596,9 +688,15 @@ int harvest_events(pt_ctx *c)
         c->exch_ms += ms;
         c->exch_n++;
     }
+    for (auto &p : c->multi_ev) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[p.first], c->ev_pool[p.second]));
+        c->multi_ms += ms;
+    }
     c->sweep_ev.clear();
     c->sweep_ev_calls.clear();
     c->exch_ev.clear();
+    c->multi_ev.clear();
     c->ev_used = 0;
     return PT_OK;
 }
@@ -740,7 +838,9 @@ bool whole_instance_tiles(const pt_ctx *c)
         return false;
     for (int k = 0; k < c->n_fast_tiles; ++k) {
         const Tile &t = c->tiles[k];
-        if (t.c0 != 0 || t.P != c->plan.desc[t.inst].R) return false;
+        const InstDesc &d = c->plan.desc[t.inst];
+        // the multi-cycle kernel does not carry 16-bit neighbour entries
+        if (t.c0 != 0 || t.P != d.R || d.ent_mode == kEntXad16) return false;
     }
     return true;
 }
@@ -824,8 +924,16 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange, int cycles =
         if (e == hipSuccess) {
             if (timing) {
                 HIP_TRY(hipEventRecord(c->ev_pool[eb], c->stream));
-                c->sweep_ev.emplace_back(ea, eb);
-                c->sweep_ev_calls.push_back(cycles);
+                if (cycles > 1) {
+                    c->multi_ev.emplace_back(ea, eb);
+                } else {
+                    c->sweep_ev.emplace_back(ea, eb);
+                    c->sweep_ev_calls.push_back(1);
+                }
+            }
+            if (cycles > 1) {
+                c->multi_launches += 1;
+                c->multi_cycles += cycles;
             }
             return PT_OK;
         }
@@ -1175,10 +1283,12 @@ int pt_run(pt_ctx *c, int32_t n_cycles)
     // Batches whose instances each fit one whole-replica tile run up to kLaunchCycles
     // cycles per launch, each workgroup doing its instance's exchange steps itself (no
     // launch per cycle, no graph).  Not with the correlations (a launch of their own per
-    // exchange), while tuning, or with a launch failure to inject.
+    // exchange), while tuning, with a launch failure to inject, or under PT_FLAG_NO_GRAPH
+    // (which asks for one set of launches per cycle).
     constexpr int kLaunchCycles = 1024;
-    if (n_cycles > 1 && c->plan.encoding == PT_INT8 && !(c->opt.flags & PT_FLAG_TAU_CORR) &&
-        !c->tuning && !c->inject_pending && whole_instance_tiles(c)) {
+    if (n_cycles > 1 && c->plan.encoding == PT_INT8 &&
+        !(c->opt.flags & (PT_FLAG_TAU_CORR | PT_FLAG_NO_GRAPH)) && !c->tuning &&
+        !c->inject_pending && whole_instance_tiles(c)) {
         const int k = c->opt.sweeps_per_exchange;
         while (n_cycles > 0) {
             const int m = std::min(n_cycles, kLaunchCycles);
@@ -1386,27 +1496,24 @@ int pt_save(pt_ctx *c, void *buf, size_t *len)
 int pt_load(pt_ctx *c, const void *buf, size_t len)
 {
     if (!c || !buf) return fail(PT_EINVAL, "null argument");
-    if (len < sizeof(CkptHeader)) return fail(PT_ESTATE, "checkpoint too short");
-    CkptHeader h;
-    std::memcpy(&h, buf, sizeof h);
-    if (h.magic != kMagic || h.version != kVersion) return fail(PT_ESTATE, "not a checkpoint");
-    if (h.state_bytes != c->plan.state_bytes || h.n_inst != n_inst_of(c) ||
-        h.seed != c->opt.seed || h.flips_per_sweep != c->plan.flips_per_sweep ||
-        len != sizeof h + h.state_bytes)
-        return fail(PT_ESTATE, "checkpoint belongs to different instances or options");
-    if (h.encoding != c->opt.encoding)
-        return fail(PT_ESTATE, "checkpoint was written under another spin encoding");
-    if (c->plan.encoding == PT_INT8) {
-        // every spin byte must be 0 or 1: the kernels index tables with them (any bit
-        // pattern is a valid bit-packed state)
-        const uint8_t *sp = (const uint8_t *)buf + sizeof h + (c->plan.o_spins - c->plan.o_state);
-        for (int64_t b = 0; b < c->plan.spin_bytes; ++b)
-            if (sp[b] > 1) return fail(PT_ESTATE, "checkpoint holds invalid spins");
-    }
-    HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_state, (const char *)buf + sizeof h, h.state_bytes,
-                           hipMemcpyHostToDevice, c->stream));
+    const int rc = check_checkpoint(c->plan, c->opt, n_inst_of(c), buf, len);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_state, (const char *)buf + sizeof(CkptHeader),
+                           c->plan.state_bytes, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return PT_OK;
+}
+
+int pt_checkpoint_validate(const pt_instance *inst, int32_t n_inst, const pt_options *opt,
+                           const void *buf, size_t len, size_t *need)
+{
+    if (!opt) return fail(PT_EINVAL, "null options");
+    Plan P;
+    int rc = make_plan(inst, n_inst, opt->flags, opt->encoding, P);
+    if (rc) return rc;
+    if (need) *need = sizeof(CkptHeader) + P.state_bytes;
+    if (!buf) return PT_OK;
+    return check_checkpoint(P, *opt, n_inst, buf, len);
 }
 
 int pt_get_info(pt_ctx *c, pt_info *o)
@@ -1438,6 +1545,21 @@ int pt_get_info(pt_ctx *c, pt_info *o)
         for (const auto &d : c->plan.desc) parities = std::max(parities, d.parities);
         o->class_launches = parities * (int32_t)c->plan.bp_colour.size();
     }
+    o->multi_launches = c->multi_launches;
+    o->multi_cycles = c->multi_cycles;
+    o->multi_ms = c->multi_ms;
+    return PT_OK;
+}
+
+int pt_timing_enable(pt_ctx *c, int32_t on)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    int rc = harvest_events(c);
+    if (rc) return rc;
+    if (on)
+        c->opt.flags |= PT_FLAG_TIMING;
+    else
+        c->opt.flags &= ~PT_FLAG_TIMING;
     return PT_OK;
 }
 
@@ -1446,7 +1568,7 @@ int pt_timing_reset(pt_ctx *c)
     if (!c) return fail(PT_EINVAL, "null context");
     int rc = harvest_events(c);
     if (rc) return rc;
-    c->sweep_ms = c->exch_ms = 0;
+    c->sweep_ms = c->exch_ms = c->multi_ms = 0;
     c->sweep_n = c->exch_n = 0;
     return PT_OK;
 }

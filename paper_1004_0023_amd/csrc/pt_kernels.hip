@@ -28,6 +28,12 @@ namespace {
 
 constexpr int kWave = 64;
 
+// A compile-time int as a value (to instantiate a generic lambda per degree or mode).
+template <int V>
+struct IntC {
+    static constexpr int value = V;
+};
+
 __device__ __forceinline__ long long wave_sum(long long v)
 {
 #pragma unroll
@@ -159,7 +165,7 @@ __host__ __device__ __forceinline__ int64_t carve_offsets(const InstDesc &d, int
 {
     int64_t x = 0;
     o[0] = x; x = a16(x + (int64_t)P * rep_lds_bytes(d));
-    o[1] = x; x = a16(x + (d.fast ? (int64_t)d.N * d.D * 4 : 0));
+    o[1] = x; x = a16(x + (d.fast ? ent_words(d.N, d.D, d.ent_mode) * 4 : 0));
     o[2] = x; x = a16(x + (d.fast ? (int64_t)d.N * 4 : 0));
     o[3] = x; x = a16(x + (d.fast ? 0 : (int64_t)n_adj * 4));
     o[4] = x; x = a16(x + (d.fast ? 0 : (int64_t)(d.N + 1) * 4));
@@ -268,7 +274,8 @@ __device__ __forceinline__ void stage_common(const DevState &st, const InstDesc 
     for (int g = tid; g <= d.n_colors; g += nt) t.coff[g] = st.cls_off[d.cls_base + g];
     stage_tables(st, d, tile.c0, tile.P, t.tbl);
     if (d.fast) {
-        for (int e = tid; e < d.N * d.D; e += nt) t.ent[e] = st.ent[d.ent_base + e];
+        const int ew = (int)ent_words(d.N, d.D, d.ent_mode);
+        for (int e = tid; e < ew; e += nt) t.ent[e] = st.ent[d.ent_base + e];
         for (int i = tid; i < d.N; i += nt) t.bias[i] = st.bias[d.site_base + i];
     } else {
         for (int e = tid; e < n_adj; e += nt) t.adj[e] = st.adj[d.adj_base + e];
@@ -419,10 +426,39 @@ struct FastArgs {
     int G4, lgG4, lgMh, tbl_words;
 };
 
+// Neighbour entry e of site i's row in LDS as (byte offset of the neighbour's row within a
+// parity plane, weight word): the weight word is the entry itself under kEntPerm (its low
+// bytes are the v_perm table w0, w1), and the mask m = 0x01010101 [J < 0] under kEntXad
+// and kEntXad16.
+template <int EM>
+__device__ __forceinline__ void fast_entry(const uint32_t *ent, int idx, uint32_t &off, uint32_t &w)
+{
+    if constexpr (EM == kEntXad16) {
+        const uint32_t v = reinterpret_cast<const uint16_t *>(ent)[idx];
+        off = v & 0x7FFFu;
+        w = __builtin_amdgcn_perm(0u, v >> 15, 0u);
+    } else {
+        const uint32_t v = ent[idx];
+        off = v >> 16;
+        w = (EM == kEntXad) ? __builtin_amdgcn_perm(0u, v, 0u) : v;
+    }
+}
+
+// acc + the weighted neighbour bytes of word y (w from fast_entry).
+template <int EM>
+__device__ __forceinline__ uint32_t fast_add(uint32_t acc, uint32_t w, uint32_t y)
+{
+    if constexpr (EM == kEntPerm)
+        return acc + __builtin_amdgcn_perm(0u, w, y);
+    else
+        return (y ^ w) + acc;  // v_xad_u32
+}
+
 // One lane's update of site i, replica q, slice groups g4 .. g4 + NW - 1 of parity PAR:
 // 4 * NW Metropolis attempts served by NW Philox calls.  DT > 0 fixes the (padded) degree
-// at compile time so the neighbour loads are issued together.
-template <int DT, int NW, int PAR>
+// at compile time so the neighbour loads are issued together; EM is the instance's
+// EntMode.
+template <int DT, int NW, int PAR, int EM>
 __device__ __forceinline__ void fast_item(const FastArgs &a, const TileLds &t, int D, int i,
                                           int q, int g4)
 {
@@ -450,27 +486,27 @@ __device__ __forceinline__ void fast_item(const FastArgs &a, const TileLds &t, i
         }
     }
     // weighted count of neighbours per slice byte
-    const uint32_t *er = t.ent + i * D;
+    const int e0 = i * D;
     uint32_t acc[NW];
 #pragma unroll
     for (int k = 0; k < NW; ++k) acc[k] = 0;
     if constexpr (DT > 0) {
-        uint32_t ents[DT], ws[DT][NW];
+        uint32_t offs[DT], wts[DT], ws[DT][NW];
 #pragma unroll
-        for (int e = 0; e < DT; ++e) ents[e] = er[e];
+        for (int e = 0; e < DT; ++e) fast_entry<EM>(t.ent, e0 + e, offs[e], wts[e]);
 #pragma unroll
-        for (int e = 0; e < DT; ++e) ldsw<NW>(t.sp, nb_base + (ents[e] >> 16), ws[e]);
+        for (int e = 0; e < DT; ++e) ldsw<NW>(t.sp, nb_base + offs[e], ws[e]);
 #pragma unroll
         for (int e = 0; e < DT; ++e)
 #pragma unroll
-            for (int k = 0; k < NW; ++k) acc[k] += __builtin_amdgcn_perm(0u, ents[e], ws[e][k]);
+            for (int k = 0; k < NW; ++k) acc[k] = fast_add<EM>(acc[k], wts[e], ws[e][k]);
     } else {
         for (int e = 0; e < D; ++e) {
-            const uint32_t ent = er[e];
-            uint32_t w[NW];
-            ldsw<NW>(t.sp, nb_base + (ent >> 16), w);
+            uint32_t off, wt, w[NW];
+            fast_entry<EM>(t.ent, e0 + e, off, wt);
+            ldsw<NW>(t.sp, nb_base + off, w);
 #pragma unroll
-            for (int k = 0; k < NW; ++k) acc[k] += __builtin_amdgcn_perm(0u, ent, w[k]);
+            for (int k = 0; k < NW; ++k) acc[k] = fast_add<EM>(acc[k], wt, w[k]);
         }
     }
     const uint32_t bias = t.bias[i];
@@ -496,7 +532,7 @@ __device__ __forceinline__ void fast_item(const FastArgs &a, const TileLds &t, i
 // All colour classes of parity PAR.  A class holds ns sites x P replicas x G4/NW lanes;
 // lanes run over slice groups fastest, so the lanes of a site read one neighbour row entry
 // (broadcast) and consecutive words of each neighbour row.
-template <int DT, int NW, int PAR>
+template <int DT, int NW, int PAR, int EM>
 __device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d, const TileLds &t,
                                            int lgGW, int lgL)
 {
@@ -514,7 +550,7 @@ __device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d,
         for (int g = 0; g < d.n_colors; ++g) {
             const int s1 = t.coff[g + 1];
             for (int si = t.coff[g] + s_first; si < s1; si += sstep)
-                fast_item<DT, NW, PAR>(a, t, D, t.csite[si], q, g4);
+                fast_item<DT, NW, PAR, EM>(a, t, D, t.csite[si], q, g4);
             __syncthreads();
         }
     } else {
@@ -523,7 +559,7 @@ __device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d,
             const int items = (t.coff[g + 1] - s0) << lgL;
             for (int it = tid; it < items; it += nt) {
                 const int r = it & Lmask;
-                fast_item<DT, NW, PAR>(a, t, D, t.csite[s0 + (it >> lgL)], r >> lgGW,
+                fast_item<DT, NW, PAR, EM>(a, t, D, t.csite[s0 + (it >> lgL)], r >> lgGW,
                                        NW * (r & ((1 << lgGW) - 1)));
             }
             __syncthreads();
@@ -531,7 +567,7 @@ __device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d,
     }
 }
 
-template <int DT, int NW>
+template <int DT, int NW, bool WIDE>
 __device__ __forceinline__ void fast_sweeps(const SweepLaunch &L, const InstDesc &d,
                                             const Tile &tile, const TileLds &t, uint64_t t0)
 {
@@ -549,28 +585,56 @@ __device__ __forceinline__ void fast_sweeps(const SweepLaunch &L, const InstDesc
     a.tbl_words = d.tbl_words;
     const int lgGW = ilog2(d.G4 / NW);
     const int lgL = ilog2(tile.P) + lgGW;  // lanes per site: P * G4 / NW
-    for (int sw = 0; sw < L.n_sweeps; ++sw) {
-        a.tt = (uint32_t)(t0 + (uint64_t)sw);
-        fast_phase<DT, NW, 0>(a, d, t, lgGW, lgL);
-        fast_phase<DT, NW, 1>(a, d, t, lgGW, lgL);
-    }
+    auto run = [&](auto em) {
+        constexpr int EM = decltype(em)::value;
+        for (int sw = 0; sw < L.n_sweeps; ++sw) {
+            a.tt = (uint32_t)(t0 + (uint64_t)sw);
+            fast_phase<DT, NW, 0, EM>(a, d, t, lgGW, lgL);
+            fast_phase<DT, NW, 1, EM>(a, d, t, lgGW, lgL);
+        }
+    };
+    // 16-bit entries are only used with two words per lane and rows of at least four
+    // entries (the large replicas they are meant for; the host guarantees it), so only
+    // those instantiations carry them
+    constexpr bool k16 = WIDE && NW == 2 && (DT == 0 || DT >= 4);
+    if (WIDE && d.ent_mode == kEntXad)
+        run(IntC<WIDE ? kEntXad : kEntPerm>{});
+    else if (k16 && d.ent_mode == kEntXad16)
+        run(IntC<k16 ? kEntXad16 : kEntPerm>{});
+    else
+        run(IntC<kEntPerm>{});
 }
 
-template <int NW>
+// WIDE: the instantiation carries the kEntXad and kEntXad16 forms.  The multi-cycle kernel
+// does not (with them it would need more registers than its four waves per SIMD allow): it
+// reads kEntXad entries, which have the kEntPerm layout, the kEntPerm way, and its
+// instances fit one tile each, which kEntXad16 instances never do.
+template <int NW, bool WIDE>
 __device__ __forceinline__ void fast_dispatch(const SweepLaunch &L, const InstDesc &d,
                                               const Tile &tile, const TileLds &t, uint64_t t0)
 {
     switch (d.D) {
-    case 1: fast_sweeps<1, NW>(L, d, tile, t, t0); break;
-    case 2: fast_sweeps<2, NW>(L, d, tile, t, t0); break;
-    case 3: fast_sweeps<3, NW>(L, d, tile, t, t0); break;
-    case 4: fast_sweeps<4, NW>(L, d, tile, t, t0); break;
-    case 5: fast_sweeps<5, NW>(L, d, tile, t, t0); break;
-    case 6: fast_sweeps<6, NW>(L, d, tile, t, t0); break;
-    case 7: fast_sweeps<7, NW>(L, d, tile, t, t0); break;
-    case 8: fast_sweeps<8, NW>(L, d, tile, t, t0); break;
-    default: fast_sweeps<0, NW>(L, d, tile, t, t0); break;
+    case 1: fast_sweeps<1, NW, WIDE>(L, d, tile, t, t0); break;
+    case 2: fast_sweeps<2, NW, WIDE>(L, d, tile, t, t0); break;
+    case 3: fast_sweeps<3, NW, WIDE>(L, d, tile, t, t0); break;
+    case 4: fast_sweeps<4, NW, WIDE>(L, d, tile, t, t0); break;
+    case 5: fast_sweeps<5, NW, WIDE>(L, d, tile, t, t0); break;
+    case 6: fast_sweeps<6, NW, WIDE>(L, d, tile, t, t0); break;
+    case 7: fast_sweeps<7, NW, WIDE>(L, d, tile, t, t0); break;
+    case 8: fast_sweeps<8, NW, WIDE>(L, d, tile, t, t0); break;
+    default: fast_sweeps<0, NW, WIDE>(L, d, tile, t, t0); break;
     }
+}
+
+// Entry idx of a fast tile's neighbour rows in the 32-bit form (offset << 16 | w1 << 8 | w0)
+// whatever the instance's EntMode (a uniform branch; the energy pass runs once per call).
+__device__ __forceinline__ uint32_t fast_entry32(const InstDesc &d, const uint32_t *ent, int idx)
+{
+    if (d.ent_mode == kEntXad16) {
+        const uint32_t v = reinterpret_cast<const uint16_t *>(ent)[idx];
+        return ((v & 0x7FFFu) << 16) | ((v >> 15) ? 0x0001u : 0x0100u);
+    }
+    return ent[idx];
 }
 
 // E_cl and C of every replica of a fast tile from its final spins.  Per site and group of
@@ -608,13 +672,12 @@ __device__ __forceinline__ void fast_energy(const DevState &st, const InstDesc &
             // time bonds (2m, 2m+1) and (2m+1, 2m+2): 8 per group
             const int dis_t = (int)(popc(X0 ^ X1) + popc(X1 ^ __builtin_amdgcn_alignbyte(X0n, X0, 1)));
             c1 += 8 - 2 * dis_t;
-            const uint32_t *er = t.ent + i * D;
             const uint32_t nb = qbase + 4u * (uint32_t)g4;
             uint32_t A0 = 0, A1 = 0, sumJ = 0;
             if constexpr (DT > 0) {
                 uint32_t ents[DT], y0[DT], y1[DT];
 #pragma unroll
-                for (int e = 0; e < DT; ++e) ents[e] = er[e];
+                for (int e = 0; e < DT; ++e) ents[e] = fast_entry32(d, t.ent, i * D + e);
 #pragma unroll
                 for (int e = 0; e < DT; ++e) {
                     y0[e] = lds32(t.sp, nb + (ents[e] >> 16));
@@ -628,7 +691,7 @@ __device__ __forceinline__ void fast_energy(const DevState &st, const InstDesc &
                 }
             } else {
                 for (int e = 0; e < D; ++e) {
-                    const uint32_t ent = er[e];
+                    const uint32_t ent = fast_entry32(d, t.ent, i * D + e);
                     A0 += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, nb + (ent >> 16)));
                     A1 += __builtin_amdgcn_perm(0u, ent, lds32(t.sp, nb + (ent >> 16) + NMh));
                     sumJ = __builtin_amdgcn_udot4(ent, 0x00000101u, sumJ, false);
@@ -690,9 +753,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MULTI
     // the replicas' new rungs and reads the advanced sweep counter.
     for (int cyc = 0;; ++cyc) {
         if (L.lane_words == 2 && d.G4 >= 2)
-            fast_dispatch<2>(L, d, tile, t, t0);
+            fast_dispatch<2, !MULTI>(L, d, tile, t, t0);
         else
-            fast_dispatch<1>(L, d, tile, t, t0);
+            fast_dispatch<1, !MULTI>(L, d, tile, t, t0);
 
         switch (d.D) {
         case 1: fast_energy<1>(st, d, tile, t); break;
@@ -869,11 +932,6 @@ __device__ __forceinline__ void block_item(const BlockArgs &a, const BlockLds &t
     *reinterpret_cast<uint32_t *>(t.sp + own) = X ^ flip;
 }
 
-// A compile-time int as a value (to instantiate a generic lambda per degree).
-template <int V>
-struct IntC {
-    static constexpr int value = V;
-};
 
 // The slots a phase runs: ns of them, slot s0 + r for r < cut and s0 + r + jump beyond
 // (two runs of consecutive slots).

@@ -30,7 +30,9 @@ MLP_LOSS_SOFTMAX, MLP_LOSS_SIGMOID = 0, 1
 
 EXPORTS = ["pt_workspace_bytes", "pt_init", "pt_sweep", "pt_exchange", "pt_run", "pt_sync",
            "pt_observables", "pt_get_spins", "pt_set_spins", "pt_save", "pt_load",
-           "pt_get_info", "pt_timing_reset", "pt_free", "pt_strerror", "pt_last_error",
+           "pt_checkpoint_validate", "pt_get_info", "pt_timing_reset", "pt_timing_enable",
+           "pt_free",
+           "pt_strerror", "pt_last_error",
            "pt_threshold", "pt_threshold_device", "pt_mlp_param_count",
            "pt_mlp_workspace_bytes", "pt_mlp_forward", "pt_mlp_loss_grad", "pt_mlp_adam"]
 
@@ -73,7 +75,8 @@ class _Info(C.Structure):
                 ("sweep_launches", C.c_int64), ("exchange_ms", C.c_double),
                 ("exchange_launches", C.c_int64), ("sweep_groups", C.c_int32),
                 ("block_tiles", C.c_int32), ("block_resident", C.c_int32),
-                ("class_launches", C.c_int32)]
+                ("class_launches", C.c_int32), ("multi_launches", C.c_int64),
+                ("multi_cycles", C.c_int64), ("multi_ms", C.c_double)]
 
 
 _lib = None
@@ -103,8 +106,10 @@ def lib():
         L.pt_set_spins.argtypes = [vp, i32, vp]
         L.pt_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
         L.pt_load.argtypes = [vp, vp, C.c_size_t]
+        L.pt_checkpoint_validate.argtypes = [vp, i32, vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
         L.pt_get_info.argtypes = [vp, vp]
         L.pt_timing_reset.argtypes = [vp]
+        L.pt_timing_enable.argtypes = [vp, i32]
         L.pt_free.argtypes = [vp]
         L.pt_free.restype = None
         L.pt_strerror.argtypes = [C.c_int]
@@ -153,6 +158,54 @@ def _arr(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
+def _records(instances: Sequence):
+    """pt_instance records of the instances, and the arrays they point into (which must
+    be kept alive while the records are used)."""
+    keep: List[np.ndarray] = []
+    recs = (_Instance * len(instances))()
+    for n, inst in enumerate(instances):
+        E = int(inst.edges.shape[0])
+        ei = _arr(inst.edges[:, 0] if E else np.zeros(1), np.int32)
+        ej = _arr(inst.edges[:, 1] if E else np.zeros(1), np.int32)
+        J = _arr(inst.J if E else np.zeros(1), np.int8)
+        h = _arr(inst.h, np.int8)
+        col = _arr(inst.color, np.uint8)
+        b = _arr(inst.b, np.float64)
+        K = _arr(inst.K, np.float64)
+        keep += [ei, ej, J, h, col, b, K]
+        recs[n] = _Instance(inst.N, inst.M, inst.R, E, inst.n_colors, ei.ctypes.data,
+                            ej.ctypes.data, J.ctypes.data, h.ctypes.data, col.ctypes.data,
+                            b.ctypes.data, K.ctypes.data)
+    return recs, keep
+
+
+def _options(seed, sweeps_per_exchange=1, encoding=PT_INT8, flags=0, tile_replicas=0,
+             tile_bytes=0, block_threads=0) -> _Options:
+    return _Options(int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweeps_per_exchange), int(encoding),
+                    int(flags), int(tile_replicas), int(tile_bytes), int(block_threads))
+
+
+def checkpoint_size(instances: Sequence, seed: int, **options) -> int:
+    """Bytes of a checkpoint of these instances and options (pt_checkpoint_validate with
+    no buffer; no GPU needed)."""
+    recs, _keep = _records(list(instances))
+    opt = _options(seed, **options)
+    need = C.c_size_t(0)
+    _check(lib().pt_checkpoint_validate(C.cast(recs, C.c_void_p), len(recs), C.byref(opt),
+                                        None, 0, C.byref(need)))
+    return int(need.value)
+
+
+def checkpoint_validate(instances: Sequence, seed: int, blob: bytes, **options):
+    """Raise PTError unless pt_load would accept blob for these instances and options
+    (no GPU needed)."""
+    recs, _keep = _records(list(instances))
+    opt = _options(seed, **options)
+    buf = C.create_string_buffer(bytes(blob), len(blob))
+    _check(lib().pt_checkpoint_validate(C.cast(recs, C.c_void_p), len(recs), C.byref(opt),
+                                        C.cast(buf, C.c_void_p), len(blob), None))
+
+
 class Sampler:
     """A batch of instances sampled by the library (one pt_ctx).
 
@@ -166,25 +219,10 @@ class Sampler:
                  stream: Optional[torch.cuda.Stream] = None,
                  torch_workspace: bool = True):
         self.instances = list(instances)
-        self._keep: List[np.ndarray] = []
-        recs = (_Instance * len(self.instances))()
-        for n, inst in enumerate(self.instances):
-            E = int(inst.edges.shape[0])
-            ei = _arr(inst.edges[:, 0] if E else np.zeros(1), np.int32)
-            ej = _arr(inst.edges[:, 1] if E else np.zeros(1), np.int32)
-            J = _arr(inst.J if E else np.zeros(1), np.int8)
-            h = _arr(inst.h, np.int8)
-            col = _arr(inst.color, np.uint8)
-            b = _arr(inst.b, np.float64)
-            K = _arr(inst.K, np.float64)
-            self._keep += [ei, ej, J, h, col, b, K]
-            recs[n] = _Instance(inst.N, inst.M, inst.R, E, inst.n_colors, ei.ctypes.data,
-                                ej.ctypes.data, J.ctypes.data, h.ctypes.data, col.ctypes.data,
-                                b.ctypes.data, K.ctypes.data)
+        recs, self._keep = _records(self.instances)
         self._recs = recs
-        self.opt = _Options(int(seed) & 0xFFFFFFFFFFFFFFFF, int(sweeps_per_exchange),
-                            int(encoding), int(flags), int(tile_replicas), int(tile_bytes),
-                            int(block_threads))
+        self.opt = _options(seed, sweeps_per_exchange, encoding, flags, tile_replicas,
+                            tile_bytes, block_threads)
         L = lib()
         nbytes = C.c_size_t(0)
         _check(L.pt_workspace_bytes(C.cast(recs, C.c_void_p), len(self.instances),
@@ -285,6 +323,9 @@ class Sampler:
 
     def timing_reset(self):
         _check(lib().pt_timing_reset(self._ctx))
+
+    def timing_enable(self, on: bool):
+        _check(lib().pt_timing_enable(self._ctx, 1 if on else 0))
 
 
 class LadderNet:

@@ -162,3 +162,40 @@ def test_empty_batch_and_size_limits_rejected():
     too_m = W.random_small_instance(rng, 3, 4098, 2, d=2)
     rc, _, msg = _ws_bytes([too_m], ptqmc)
     assert rc == ptqmc.PT_EINVAL and "M must be <= 4096" in msg
+
+
+def _ckpt_header(size, seed, n_inst, encoding, flips):
+    """The 40-byte checkpoint header the ABI documents."""
+    import struct
+    return struct.pack("<IIQQiiQ", 0x51505450, 3, size - 40, seed, n_inst, encoding, flips)
+
+
+def test_checkpoint_validation_refuses_corrupt_state_without_gpu():
+    """pt_load's checks run on the host before anything is copied, and
+    pt_checkpoint_validate runs them without a context: a checkpoint of the right size and
+    header whose permutation is not a bijection, whose labels are out of range or whose
+    spin bytes are not 0/1 is refused with PT_ESTATE (those values index device memory)."""
+    ptqmc = _lib()
+    insts = [W.config1(), W.random_small_instance(np.random.default_rng(4), 6, 8, 3, name="s")]
+    seed = 99
+    size = ptqmc.checkpoint_size(insts, seed)
+    flips = sum(i.flips_per_sweep for i in insts)
+    head = _ckpt_header(size, seed, len(insts), ptqmc.PT_INT8, flips)
+    zero = head + bytes(size - 40)
+    # all-zero state: rung_of[c] = 0 for every slot is not a permutation
+    with pytest.raises(ptqmc.PTError) as e:
+        ptqmc.checkpoint_validate(insts, seed, zero)
+    assert e.value.code == ptqmc.PT_ESTATE and "permutation" in str(e.value)
+    # a spin byte of 2 (the state starts with the spins)
+    bad = bytearray(zero)
+    bad[40] = 2
+    with pytest.raises(ptqmc.PTError) as e:
+        ptqmc.checkpoint_validate(insts, seed, bytes(bad))
+    assert e.value.code == ptqmc.PT_ESTATE and "spins" in str(e.value)
+    # wrong size, wrong seed, wrong magic
+    with pytest.raises(ptqmc.PTError):
+        ptqmc.checkpoint_validate(insts, seed, zero[:-1])
+    with pytest.raises(ptqmc.PTError):
+        ptqmc.checkpoint_validate(insts, seed + 1, zero)
+    with pytest.raises(ptqmc.PTError):
+        ptqmc.checkpoint_validate(insts, seed, b"\0" * 4 + zero[4:])

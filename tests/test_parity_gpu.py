@@ -5,6 +5,7 @@ equality: spins, integer energies, the replica permutation, labels, swap counts,
 trips and accumulators.  The oracle runs one instance at a time with that instance's
 batch index.
 """
+import os
 import sys
 
 import numpy as np
@@ -12,6 +13,9 @@ import pytest
 
 import oracle
 import workloads as W
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import make_golden as golden  # noqa: E402  (digests written from the oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -119,15 +123,43 @@ def test_init_matches_oracle(ptqmc):
             assert_same(s, n, oracle.OracleChain(inst, seed, index=n), "init")
 
 
-def test_config1_full_run(ptqmc):
+@pytest.mark.parametrize("block_threads", [0, 256])
+def test_config1_full_run(ptqmc, block_threads):
+    """Config 1 for 10^4 sweeps with an exchange after every sweep.  With the tuner on
+    (block_threads 0) the one run() call stays on per-cycle launches; with the shape
+    fixed (tuner off) the same call runs as multi-cycle launches, each workgroup doing
+    its instance's exchange steps itself."""
     inst = W.config1()
     seed = W.sampler_seed(1)
-    say("case: config 1, 10^4 sweeps, exchange every sweep")
-    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=1) as s:
+    say(f"case: config 1, 10^4 sweeps, exchange every sweep, block_threads={block_threads}")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=1, block_threads=block_threads) as s:
         s.run(10_000)
         ref = oracle.OracleChain(inst, seed)
         ref.run(1, 10_000)
         assert_same(s, 0, ref, "config1")
+        info = s.info()
+        if block_threads:
+            assert info["multi_launches"] >= 10 and info["multi_cycles"] == 10_000
+        # a second call after tuning has ended takes the multi-cycle launches either way
+        before = info["multi_launches"]
+        s.run(300)
+        ref.run(1, 300)
+        assert_same(s, 0, ref, "config1 second call")
+        assert s.info()["multi_launches"] > before
+
+
+def test_config2_long_run_digest(ptqmc):
+    """Config 2 (N=128, M=64, R=32, exchange every 10 sweeps) for 1000 cycles (10^4
+    sweeps): the final state's digest equals the oracle's stored one."""
+    gold = golden.load_golden("config2")
+    inst = W.config2()
+    seed = W.sampler_seed(2)
+    assert gold["seed"] == seed and gold["sweeps_per_exchange"] == 10
+    say(f"case: config 2, {gold['cycles']} cycles of 10 sweeps, against the stored digest")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10) as s:
+        s.run(gold["cycles"])
+        got = golden.state_digest(s.spins(0), s.observables(0))
+    assert got == gold["digests"][0]
 
 
 def test_config2_truncated(ptqmc):
@@ -211,6 +243,12 @@ def test_checkpoint_resume(ptqmc):
         with ptqmc.Sampler(insts, seed + 1, sweeps_per_exchange=2) as other:
             with pytest.raises(ptqmc.PTError):
                 other.load(blob)
+        # the host-side checks accept the real checkpoint; an all-zero state (rung_of is
+        # then no permutation) is refused before anything reaches the device
+        ptqmc.checkpoint_validate(insts, seed, blob, sweeps_per_exchange=2)
+        with pytest.raises(ptqmc.PTError) as e:
+            a.load(blob[:40] + bytes(len(blob) - 40))
+        assert e.value.code == ptqmc.PT_ESTATE
 
 
 def test_set_spins_recomputes_energies(ptqmc):
@@ -242,31 +280,47 @@ def test_injected_launch_failure_falls_back(ptqmc):
             assert_same(s, n, refs[n], "fallback")
 
 
-def test_config3_full_batch_sampled(ptqmc):
-    """All 512 instances of the batched workload in the launch configuration the
-    benchmark uses; a sample of instances is re-run by the oracle, and the whole batch is
-    checked for invariants (energies equal a recomputation, permutations are bijections)."""
-    insts = W.config3()
+@pytest.fixture(scope="module")
+def config3_batch():
+    return W.config3()
+
+
+# (tile bytes, block threads): 64 KiB x 1024 is the shape the tuner picks on an MI355X for
+# this batch (the benchmark records the shape it ran); the others are the rest of the
+# tuner's range, and (0, 0) runs the tuner itself, whose first ten calls each use a
+# different candidate shape.
+CONFIG3_SHAPES = [(65536, 1024), (131072, 1024), (32768, 512), (16384, 1024), (8192, 256),
+                  (65536, 256), (0, 0)]
+
+
+@pytest.mark.parametrize("tile_bytes,block_threads", CONFIG3_SHAPES)
+def test_config3_full_batch_digests(ptqmc, config3_batch, tile_bytes, block_threads):
+    """All 512 instances of the batched workload for 16 PT cycles (160 sweeps) as one
+    pt_run call, i.e. one replay of the captured 16-cycle graph (the benchmark's route):
+    every instance's final state (spins, energies, permutation, labels, swap counts,
+    round trips, accumulators, counters) has the digest of the oracle's run of that
+    instance, stored by tests/golden/make_golden.py.  With the tuner on (0, 0) the cycles
+    run as 16 calls, each timing another candidate shape."""
+    gold = golden.load_golden("config3")
+    insts = config3_batch
     seed = W.sampler_seed(3)
-    k, cycles = 10, 3
-    say("case: config 3, 512 instances, 3 cycles of 10 sweeps")
-    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k) as s:
-        s.run(cycles)
-        sample = [0, 1, 97, 255, 384, 511]
-        for n in sample:
-            ref = oracle.OracleChain(insts[n], seed, index=n)
-            ref.run(k, cycles)
-            assert_same(s, n, ref, "config3")
-        for n in range(0, 512, 37):
-            obs = s.observables(n)
-            ref = oracle.OracleChain(insts[n], seed, index=n, init=False)
-            E, Cc = ref.energies(s.spins(n))
-            assert np.array_equal(obs["E_cl"], E) and np.array_equal(obs["C"], Cc)
-            assert sorted(obs["replica_of"]) == list(range(insts[n].R))
-            assert np.array_equal(obs["rung_of"][obs["replica_of"]], np.arange(insts[n].R))
-            assert obs["t"] == k * cycles and obs["e"] == cycles
-        # tiles of very different LDS needs go out in several occupancy classes
-        assert s.info()["sweep_groups"] >= 2
+    k, cycles = gold["sweeps_per_exchange"], gold["cycles"]
+    assert gold["seed"] == seed and gold["instances"] == len(insts) == 512
+    say(f"case: config 3, 512 instances, {cycles} cycles of {k} sweeps, "
+        f"tile_bytes={tile_bytes} block_threads={block_threads}")
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_bytes=tile_bytes,
+                       block_threads=block_threads) as s:
+        if tile_bytes:
+            s.run(cycles)   # one replay of the 16-cycle graph
+        else:
+            for _ in range(cycles):
+                s.run(1)    # tuning: each call a different candidate shape
+        info = s.info()
+        if tile_bytes:
+            assert info["tile_bytes"] == tile_bytes and info["block_threads"] == block_threads
+        bad = [n for n in range(len(insts))
+               if golden.state_digest(s.spins(n), s.observables(n)) != gold["digests"][n]]
+    assert not bad, f"{len(bad)} instances differ from the oracle, first {bad[:8]}"
 
 
 @pytest.mark.parametrize("per_sweep", [False, True])
@@ -325,6 +379,26 @@ def test_config2_slice_blocks(ptqmc):
         ref = oracle.OracleChain(inst, seed)
         ref.run(10, 6)
         assert_same(s, 0, ref, "config2 blocks")
+
+
+@pytest.mark.parametrize("mode", ["resident", "per_sweep", "bitpack"])
+def test_config4_long_run_digest(ptqmc, mode):
+    """The 8x8x16 lattice (N=1024, M=256, R=64) for 100 cycles of 10 sweeps (10^3
+    sweeps): resident slice blocks, slice blocks launched once per sweep, and the
+    bit-packed encoding all end in the state whose digest the oracle stored."""
+    gold = golden.load_golden("config4")
+    inst = W.config4()
+    seed = W.sampler_seed(4)
+    assert gold["seed"] == seed
+    flags = ptqmc.PT_FLAG_BLOCK_LAUNCH_PER_SWEEP if mode == "per_sweep" else 0
+    enc = ptqmc.PT_BITPACK32 if mode == "bitpack" else ptqmc.PT_INT8
+    say(f"case: config 4, {gold['cycles']} cycles of 10 sweeps, {mode}, against the stored digest")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, flags=flags, encoding=enc) as s:
+        s.run(gold["cycles"])
+        if mode != "bitpack":
+            assert s.info()["block_resident"] == (0 if mode == "per_sweep" else 1)
+        got = golden.state_digest(s.spins(0), s.observables(0))
+    assert got == gold["digests"][0]
 
 
 @pytest.mark.parametrize("per_sweep", [False, True])
@@ -393,15 +467,32 @@ def test_replica_too_large_is_refused(ptqmc):
     assert ei.value.code == ptqmc.PT_EINVAL and "does not fit" in str(ei.value)
 
 
+def whole_tile_batch():
+    """Instances that each fit one whole-replica fast tile (R a power of two), so that
+    pt_run takes its multi-cycle launches: a lone spin, ragged N, the largest byte field,
+    M = 256, and config 1."""
+    f = fast_batch()
+    rng = np.random.default_rng([1004, 27])
+    lone = W.make_instance(1, np.zeros((0, 2), np.int32), np.zeros(0, np.int8),
+                           np.array([1], np.int8), 8, [0.4, 0.9, 1.7, 2.5], 1.0, name="lone8r4")
+    return [lone,
+            W.random_small_instance(rng, 5, 8, 2, d=2, jmax=2, hmax=2, name="ragged8r2"),
+            f[2],  # F = 20, R = 4
+            f[3],  # M = 256, R = 2
+            W.random_small_instance(rng, 9, 32, 8, d=8, jmax=1, hmax=1, name="dense32r8"),
+            W.config1()]
+
+
 @pytest.mark.parametrize("mode", ["tiles", "whole_tiles", "slice_blocks", "bitpack", "tau"])
 def test_every_graph_replay_matches_oracle(ptqmc, mode):
     """pt_run replays a captured graph of 16 cycles.  Three replays, with eager
     pt_sweep / pt_exchange calls and synchronisations between them, each checked against
     the oracle: whole-replica tiles of one replica each (fused cycles), resident slice
     blocks, the packed encoding, and the correlation accumulators.  With every instance
-    in one tile (whole_tiles) a run(16) is instead one launch of 16 cycles, each
-    workgroup doing its instance's exchange steps itself."""
-    insts = fast_batch()[:5]
+    in one tile (whole_tiles: R a power of two) a run(16) is instead one launch of 16
+    cycles, each workgroup doing its instance's exchange steps itself; the test checks
+    that those launches ran."""
+    insts = whole_tile_batch() if mode == "whole_tiles" else fast_batch()[:5]
     seed = 0x6A7
     k = 2
     flags = {"tiles": 0, "whole_tiles": 0, "slice_blocks": ptqmc.PT_FLAG_SLICE_BLOCKS,
@@ -425,6 +516,9 @@ def test_every_graph_replay_matches_oracle(ptqmc, mode):
                 for key in keys:
                     assert np.array_equal(np.asarray(got[key]), np.asarray(want[key])), (mode, rep, n, key)
                 assert np.array_equal(s.spins(n), refs[n].s), (mode, rep, n)
+            if mode == "whole_tiles":
+                info = s.info()
+                assert info["multi_launches"] == rep + 1 and info["multi_cycles"] == 16 * (rep + 1)
             # eager work between replays
             s.sweep(1)
             s.exchange()

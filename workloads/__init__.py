@@ -303,18 +303,6 @@ def config4() -> Instance:
     return make_instance(N, edges, J, h, 256, T, 1.5, name="c4")
 
 
-def table1_shape(qubits: int) -> Instance:
-    """Stand-in for the paper's Table 1 problems (instances not published): random
-    3-regular +-1 graph with h in {-1,0,1}, M=128, the table's chain count."""
-    chains = {8: 27, 16: 34, 32: 37, 48: 57, 72: 71, 96: 111}[qubits]
-    rng = np.random.default_rng([SEED_BASE, 0, qubits])
-    edges = random_regular_graph(qubits, 3, rng)
-    J = rng.choice(np.array([-1, 1], dtype=np.int8), size=edges.shape[0])
-    h = rng.choice(np.array([-1, 0, 1], dtype=np.int8), size=qubits)
-    T = geometric_temperatures(0.1, 3.0, chains)
-    return make_instance(qubits, edges, J, h, 128, T, 1.0, name=f"table1_{qubits}")
-
-
 def sweeps_per_exchange(config: int) -> int:
     return {1: 1, 2: 10, 3: 10, 4: 10, 5: 10}[config]
 
