@@ -291,6 +291,19 @@ size_t pt_mlp_workspace_bytes(int32_t batch);
 int pt_mlp_forward(const float *params, const float *x, float *logits, int32_t batch,
                    void *workspace, void *stream);
 
+/* pt_mlp_forward without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels, with the hidden activations in a fixed array of device memory that
+ * the library holds on each GPU it runs on until the process ends (2 x 4096 x 128 floats,
+ * 4 MiB).  Nothing is allocated or freed by the call.  batch must be in
+ * [1, PT_MLP_STATIC_MAX_BATCH], else PT_EINVAL.  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (other streams, other host threads) race
+ * and must be serialised by the caller.  The device is the calling thread's current
+ * device; its array's address is looked up on the first call there. */
+#define PT_MLP_STATIC_MAX_BATCH 4096
+int pt_mlp_forward_static(const float *params, const float *x, float *logits, int32_t batch,
+                          void *stream);
+
 /* Loss loss_kind (PT_MLP_LOSS_*) against targets target[batch][64]: writes grads
  * (pt_mlp_param_count() floats) of the batch mean, and loss[0] = the batch sum of the
  * per-sample losses. */

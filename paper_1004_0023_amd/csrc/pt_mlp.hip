@@ -15,6 +15,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "../../include/ptqmc.h"
@@ -167,6 +168,39 @@ Acts carve(void *ws, int B)
     return a;
 }
 
+// Device memory of pt_mlp_forward_static: the two hidden activations (h1, h2) of at most
+// PT_MLP_STATIC_MAX_BATCH rows, in a file-scope array that each GPU holds for the life of
+// the process.  Host code never passes the array's name to a kernel (on the host it names
+// a host-side stand-in): it uses the device address hipGetSymbolAddress returns, taken
+// once per device with that device current.
+constexpr int kStaticMaxBatch = PT_MLP_STATIC_MAX_BATCH;
+static __device__ __align__(256) float scratch[2 * (size_t)kStaticMaxBatch * kH];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the first call on a device).
+int static_scratch(float **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return launched(e, "pt_mlp_forward_static: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return ptq::report_error(PT_EINVAL, "pt_mlp_forward_static: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return launched(e, "pt_mlp_forward_static: hipGetSymbolAddress");
+        if (!ptr)
+            return ptq::report_error(PT_EHIP, "pt_mlp_forward_static: no device address for the scratch array");
+        g_scratch_dev[dev] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return PT_OK;
+}
+
 hipError_t forward(hipStream_t s, const float *P, const float *x, const Acts &a, float *out, int B)
 {
     hipError_t e;
@@ -197,6 +231,27 @@ int pt_mlp_forward(const float *params, const float *x, float *logits, int32_t b
     hipStream_t s = (hipStream_t)stream;
     const Acts a = carve(workspace, batch);
     return launched(forward(s, params, x, a, logits, batch), "pt_mlp_forward");
+}
+
+int pt_mlp_forward_static(const float *params, const float *x, float *logits, int32_t batch,
+                          void *stream)
+{
+    if (!params || !x || !logits)
+        return ptq::report_error(PT_EINVAL, "pt_mlp_forward_static: null pointer");
+    if (batch < 1) return ptq::report_error(PT_EINVAL, "pt_mlp_forward_static: batch < 1");
+    if (batch > kStaticMaxBatch)
+        return ptq::report_error(PT_EINVAL, ("pt_mlp_forward_static: batch " + std::to_string(batch) +
+                                             " exceeds PT_MLP_STATIC_MAX_BATCH (" +
+                                             std::to_string(kStaticMaxBatch) + ")").c_str());
+    float *ws = nullptr;
+    const int rc = static_scratch(&ws);
+    if (rc) return rc;
+    // the forward pass reads only h1 and h2, each written in full before it is read, so
+    // nothing left by an earlier call needs clearing
+    Acts a{};
+    a.h1 = ws;
+    a.h2 = ws + (size_t)batch * kH;
+    return launched(forward((hipStream_t)stream, params, x, a, logits, batch), "pt_mlp_forward_static");
 }
 
 int pt_mlp_loss_grad(const float *params, const float *x, const float *target, int32_t batch,

@@ -34,7 +34,9 @@ EXPORTS = ["pt_workspace_bytes", "pt_init", "pt_sweep", "pt_exchange", "pt_run",
            "pt_free",
            "pt_strerror", "pt_last_error",
            "pt_threshold", "pt_threshold_device", "pt_mlp_param_count",
-           "pt_mlp_workspace_bytes", "pt_mlp_forward", "pt_mlp_loss_grad", "pt_mlp_adam"]
+           "pt_mlp_workspace_bytes", "pt_mlp_forward", "pt_mlp_forward_static",
+           "pt_mlp_loss_grad", "pt_mlp_adam"]
+MLP_STATIC_MAX_BATCH = 4096  # PT_MLP_STATIC_MAX_BATCH
 
 
 class PTError(RuntimeError):
@@ -123,6 +125,7 @@ def lib():
         L.pt_mlp_workspace_bytes.argtypes = [i32]
         L.pt_mlp_workspace_bytes.restype = C.c_size_t
         L.pt_mlp_forward.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.pt_mlp_forward_static.argtypes = [vp, vp, vp, i32, vp]
         L.pt_mlp_loss_grad.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
         L.pt_mlp_adam.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float,
                                   C.c_float, i32, vp]
