@@ -255,7 +255,15 @@ def main():
         avg_sweep_s = launch_s / cycles_per_launch  # one cycle, its exchange included
     else:
         avg_sweep_s = cal["sweep_ms"] / max(1, cal["sweep_launches"]) / 1e3
-        if packed:
+        if packed and cal["oct_blocks"] > 0 and cal["oct_tiles"] == 0 and cal["class_launches"] == 0:
+            # octet slice blocks: one launch per parity of every sweep
+            kernel = "oct_phase_kernel"
+            launches_per_call = 2 * k
+        elif packed and cal["oct_tiles"] > 0 and cal["oct_blocks"] == 0 and cal["class_launches"] == 0:
+            # whole octets: one launch per call and workgroup size
+            kernel = "oct_tile_kernel"
+            launches_per_call = max(1, cal["oct_tile_launches"])
+        elif packed:
             # one launch per colour class and sweep, plus the two energy launches of the call
             kernel = "bp_sweep_kernel"
             launches_per_call = k * max(1, cal["class_launches"])

@@ -72,8 +72,10 @@ extern "C" {
 #define PT_INT8 0       /* one byte per spin                                                */
 #define PT_BITPACK32 1  /* 32 replica slots per uint32 word: bit (c mod 32) of word group
                            c/32 holds slot c's spin at (k, i); device memory 8x smaller.
-                           Each colour class of a sweep is one launch over the batch that
-                           reads and writes the packed words in device memory; the chain
+                           Instances with +-1 couplings, |h| <= 1, one degree D <= 8 and
+                           M a power-of-two multiple of 8 are swept by octets (8 slots, one
+                           byte of each word) staged in LDS with bit-sliced local fields;
+                           others one colour class per launch in device memory.  The chain
                            is the same as under PT_INT8                                  */
 
 /* Imaginary-time correlation lags: with PT_FLAG_TAU_CORR every exchange step adds, for
@@ -186,6 +188,13 @@ typedef struct {
     int64_t multi_cycles;             /* PT cycles those launches ran                  */
     double multi_ms;                  /* their summed event time under PT_FLAG_TIMING
                                          (not part of sweep_ms / exchange_ms)           */
+    int32_t oct_tiles;                /* PT_BITPACK32: whole octets (8 replica slots of one
+                                         word group) swept resident in LDS, all sweeps of
+                                         a call in one launch                           */
+    int32_t oct_blocks;               /* PT_BITPACK32: octet slice blocks, one launch per
+                                         parity of every sweep                          */
+    int32_t oct_tile_launches;        /* launches per call of the whole octets (one per
+                                         workgroup size)                                */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libptqmc.so")
-SOURCES = ["pt_kernels.hip", "pt_bitpack.hip", "pt_host.hip", "pt_mlp.hip"]
+SOURCES = ["pt_kernels.hip", "pt_bitpack.hip", "pt_octet.hip", "pt_host.hip", "pt_mlp.hip"]
 ARCH = "gfx950"
 
 

@@ -139,17 +139,28 @@ struct InstDesc {
     // (4 * G4), and the instance's first word group in the batch
     int32_t bp_W, bp_row, bp_wg_base;
     int32_t ent_mode;  // EntMode of the fast-path neighbour entries
+    // bit-packed encoding, octet kernels (every |J| = 1, |h| <= 1, one degree D, fast
+    // shape): 1 if they run this instance; its first 16-bit octet neighbour entry and its
+    // first octet table word (kOctTableWords per rung)
+    int32_t oct, oent_base, otbl_base, opad;
 };
+
+// Octet tables: per rung, the acceptance threshold indexed n + 16 sigma + 64 hz, where n is
+// the number of a site's inputs (its D couplings and, when h != 0, its field) that agree with
+// its spin, sigma the number of agreeing time neighbours and hz = [h != 0]; then
+// a = s f = 2 n - D - hz.
+constexpr int kOctTableWords = 128;
 
 // How the byte-SWAR kernels form a site's local field from its neighbour entries.
 //   kEntPerm   32-bit entries (j * Mh) << 16 | w1 << 8 | w0: a v_perm maps each neighbour
 //              spin byte x to its weight w_x (any |J|, padded rows)
-//   kEntXad    the same entries, every |J| = 1 and every site of full degree D: a
-//              neighbour adds its spin byte x, or 1 - x when J < 0, as (x ^ m) + acc with
-//              m = 0x01010101 [J < 0] (one v_xad per word)
-//   kEntXad16  as kEntXad with 16-bit entries (j * Mh) | [J < 0] << 15, for instances
-//              whose one-replica tiles would not otherwise fit two to a compute unit
-enum EntMode { kEntPerm = 0, kEntXad = 1, kEntXad16 = 2 };
+//   kEntXad16  16-bit entries (j * Mh) | [J < 0] << 15, every |J| = 1 and every site of
+//              full degree D: a neighbour adds its spin byte x, or 1 - x when J < 0, as
+//              (x ^ m) + acc with m = 0x01010101 [J < 0].  For instances whose one-replica
+//              tiles would not otherwise fit two to a compute unit (it costs two operations
+//              more per neighbour and lane than kEntPerm, whose v_perm lookups the compiler
+//              sums with three-input adds)
+enum EntMode { kEntPerm = 0, kEntXad16 = 2 };
 
 // 32-bit words of the fast-path neighbour entries of an instance with N sites and row
 // length D (two 16-bit entries per word under kEntXad16).
@@ -215,6 +226,13 @@ struct DevState {
     const int32_t *bp_eblk;
     const int32_t *bp_wg;
     int64_t *bp_part;
+    // bit-packed encoding, octet kernels: 16-bit neighbour entries (j | [J < 0] << 15, D per
+    // site), per-site field codes (bit 0: h < 0, bit 1: h != 0), per-rung tables, and the
+    // work list (instance, word group, octet, first group, groups) of the octet launches
+    const uint16_t *oent;
+    const uint8_t *ohinfo;
+    const uint32_t *otbl;
+    const int32_t *otiles;
     // mutable state
     uint8_t *spins;
     int64_t *E;       // per replica slot

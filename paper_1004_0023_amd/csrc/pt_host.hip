@@ -8,6 +8,7 @@
 // launches, so a PT cycle never crosses PCIe (unlike the per-cycle copies of the
 // paper's Figure 6).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -67,12 +68,23 @@ struct Plan {
     std::vector<int32_t> bp_sblk, bp_eblk, bp_wg;
     std::vector<std::pair<int32_t, int32_t>> bp_colour;
     int32_t bp_n_eblk = 0;
+    // bit-packed encoding, octet kernels: 16-bit entries, field codes, per-rung tables and the
+    // work list (tiles first, then slice blocks; kOctRec ints each)
+    std::vector<uint16_t> oent;
+    std::vector<uint8_t> ohinfo;
+    std::vector<uint32_t> otbl;
+    std::vector<int32_t> otiles;
+    int32_t n_otile = 0, n_oblock = 0;         // whole-octet tiles, octet slice blocks
+    int32_t otile_lds = 0, oblock_lds = 0;     // their largest LDS need
+    int32_t oblock_threads = 256;
+    bool oblock_split = false;                 // slice blocks: two lanes per (site, group)
+    bool bp_generic = false;                   // some packed instance runs the per-class kernel
     int64_t halo_words = 0; // one buffer of slice-block boundary records, at most
     uint64_t flips_per_sweep = 0;
     // byte offsets in the workspace
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
         o_repinst, o_halo, o_itiles, o_icount, o_prog, o_err, o_bp_sblk, o_bp_eblk, o_bp_wg,
-        o_bp_part;
+        o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr, o_sumCt;
@@ -134,6 +146,24 @@ void build_table(uint32_t *out, int F, int M, double b, double K)
             }
         }
     }
+}
+
+// Octet table of one rung (kOctTableWords words): entry n + 16 sigma + 64 hz holds thr(dS) for
+// a = s f = 2 n - D - hz agreeing-minus-disagreeing inputs and sigma agreeing time
+// neighbours, i.e. dE = -2 a and dC = -4 (sigma - 1): the entry build_table holds for x = 1,
+// f = a, tau = sigma, from the same operations.  Unused entries stay 0.
+void build_oct_table(uint32_t *out, int D, double b, double K)
+{
+    for (int k = 0; k < kOctTableWords; ++k) out[k] = 0u;
+    for (int hz = 0; hz < 2; ++hz)
+        for (int sigma = 0; sigma < 3; ++sigma)
+            for (int n = 0; n <= D + hz; ++n) {
+                const int a = 2 * n - D - hz;
+                const int64_t dE = -2 * (int64_t)a;
+                const int64_t dC = -2 * (int64_t)(2 * (sigma - 1));
+                const double dS = b * (double)dE - K * (double)dC;
+                out[n + 16 * sigma + 64 * hz] = threshold(dS);
+            }
 }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -222,19 +252,19 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
         for (int i = 0; i < in.N; ++i) sites[cls[in.color[i]] + cfill[in.color[i]]++] = (uint16_t)i;
         // fast-path rows: D entries per site, (j << ent_sh) << 16 | w1 << 8 | w0 with w0 / w1 the
         // contribution |J| [J < 0] / |J| [J > 0] of a neighbour whose spin byte is 0 / 1;
-        // padding entries point at the site itself with weight 0.  With every |J| = 1 and
-        // every site of degree D the kernels add x ^ m (kEntXad); when moreover a one-replica
-        // tile would take more than half a compute unit's LDS, the entries shrink to 16 bits
-        // (kEntXad16: j * Mh fits 15 bits), so that two such tiles fit one unit.
+        // padding entries point at the site itself with weight 0.  When every |J| = 1, every
+        // site has degree D and a one-replica tile would take more than half a compute
+        // unit's LDS, the entries shrink to 16 bits (kEntXad16: j * Mh fits 15 bits), so
+        // that two such tiles fit one unit.
         d.ent_mode = kEntPerm;
         if (d.fast) {
             bool unit = true, regular = true;
             for (int e = 0; e < in.n_edges; ++e) unit = unit && std::abs((int)in.edge_J[e]) == 1;
             for (int i = 0; i < in.N; ++i) regular = regular && deg[i + 1] - deg[i] == d.D;
-            if (unit && regular && in.n_edges > 0) d.ent_mode = kEntXad;
             int lg = 0;
             while ((1 << lg) < d.Mh) ++lg;
-            if (d.ent_mode == kEntXad && d.ent_sh == lg && (int64_t)(in.N - 1) * d.Mh <= 32767 &&
+            if (unit && regular && in.n_edges > 0 && d.ent_sh == lg &&
+                (int64_t)(in.N - 1) * d.Mh <= 32767 &&
                 d.D >= 4 && d.G4 >= 2 &&
                 !(flags & (PT_FLAG_SLICE_BLOCKS | PT_FLAG_FOUR_SLICE_LANES)) &&
                 sweep_tile_lds_bytes(d, 2 * in.n_edges, 1) > kLdsPerWorkgroup / 2) {
@@ -272,6 +302,37 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
             }
         } else {
             for (int i = 0; i < in.N; ++i) P.bias.push_back(0);
+        }
+        // bit-packed encoding: the octet kernels take +-1 couplings, |h| <= 1 and one degree
+        // D <= 8 on the fast shapes (M a power-of-two multiple of 8)
+        d.oct = 0;
+        if (bp && d.fast && in.n_edges > 0 && in.N <= 32767) {
+            bool ok = D <= 8;
+            for (int e = 0; ok && e < in.n_edges; ++e) ok = std::abs((int)in.edge_J[e]) == 1;
+            for (int i = 0; ok && i < in.N; ++i)
+                ok = std::abs((int)in.h[i]) <= 1 && deg[i + 1] - deg[i] == D;
+            d.oct = ok ? 1 : 0;
+        }
+        if (d.oct) {
+            // entries and field codes padded to 16 bytes per instance (the kernels copy them
+            // in 16-byte pieces)
+            d.oent_base = (int32_t)P.oent.size();
+            for (int i = 0; i < in.N; ++i)
+                for (int e = deg[i]; e < deg[i + 1]; ++e) {
+                    const int j = entries[e] & 0xFFFF;
+                    const int J = entries[e] >> 16;
+                    P.oent.push_back((uint16_t)(j | (J < 0 ? 0x8000 : 0)));
+                }
+            P.oent.resize(align_up(P.oent.size(), 8), 0);
+            d.opad = (int32_t)P.ohinfo.size();
+            for (int i = 0; i < in.N; ++i)
+                P.ohinfo.push_back((uint8_t)((in.h[i] < 0 ? 1 : 0) | (in.h[i] != 0 ? 2 : 0)));
+            P.ohinfo.resize(align_up(P.ohinfo.size(), 16), 0);
+            d.otbl_base = (int32_t)P.otbl.size();
+            P.otbl.resize(P.otbl.size() + (size_t)in.R * kOctTableWords);
+            for (int r = 0; r < in.R; ++r)
+                build_oct_table(P.otbl.data() + d.otbl_base + (size_t)r * kOctTableWords, D,
+                                in.rung_b[r], in.rung_K[r]);
         }
         P.desc.push_back(d);
         P.adj.insert(P.adj.end(), entries.begin(), entries.end());
@@ -325,7 +386,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
             const int32_t first = (int32_t)(P.bp_sblk.size() / 2);
             for (int n = 0; n < n_inst; ++n) {
                 const InstDesc &d = P.desc[n];
-                if (g >= d.n_colors) continue;
+                if (g >= d.n_colors || d.oct) continue;
                 const int64_t sg = P.cls_off[d.cls_base + g + 1] - P.cls_off[d.cls_base + g];
                 const int64_t items = (int64_t)d.bp_W * sg * d.G4 * kBpSweepLanes;
                 for (int64_t it = 0; it < items; it += kBpThreadsHost) {
@@ -353,6 +414,61 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
             }
         }
         P.bp_n_eblk = (int32_t)(P.bp_eblk.size() / 4);
+        // octet work: whole octets where one takes at most half a compute unit's LDS
+        // (largest first), else slice blocks of ng groups, ng about 512 colour-class items
+        // per launch and class
+        std::vector<std::array<int32_t, kOctRec>> tiles, blocks;
+        for (int n = 0; n < n_inst; ++n) {
+            const InstDesc &d = P.desc[n];
+            if (!d.oct) {
+                P.bp_generic = true;
+                continue;
+            }
+            const bool whole = oct_lds_bytes(d, d.G4, false) <= kLdsPerWorkgroup / 2;
+            int ng = d.G4;
+            if (!whole) {
+                ng = 1;
+                while (2 * ng <= d.G4 && (int64_t)2 * ng * d.N <= 512 * (int64_t)d.n_colors &&
+                       oct_lds_bytes(d, 2 * ng, true) <= kLdsPerWorkgroup / 2)
+                    ng *= 2;
+                if (oct_lds_bytes(d, ng, true) > kLdsPerWorkgroup)
+                    return fail(PT_EINVAL, "instance " + std::to_string(n) +
+                                               ": an octet slice block does not fit in LDS");
+            }
+            for (int w = 0; w < d.bp_W; ++w)
+                for (int o = 0; o < 4 && 32 * w + 8 * o < d.R; ++o) {
+                    if (whole) {
+                        tiles.push_back({n, w, o, 0, d.G4});
+                        P.otile_lds = std::max(P.otile_lds, oct_lds_bytes(d, d.G4, false));
+                    } else {
+                        for (int g0 = 0; g0 < d.G4; g0 += ng) blocks.push_back({n, w, o, g0, ng});
+                        P.oblock_lds = std::max(P.oblock_lds, oct_lds_bytes(d, ng, true));
+                    }
+                }
+        }
+        // Whole octets go out in one launch, largest first: the small ones, whose sweeps are
+        // short chains of dependent colour classes, then run beside the large ones (launched
+        // apart, a class of small octets took as long as one octet's chain).
+        std::stable_sort(tiles.begin(), tiles.end(), [&](const std::array<int32_t, kOctRec> &a,
+                                                         const std::array<int32_t, kOctRec> &b) {
+            const InstDesc &da = P.desc[a[0]], &db = P.desc[b[0]];
+            return (int64_t)da.N * da.M > (int64_t)db.N * db.M;
+        });
+        for (const auto &t : tiles) P.otiles.insert(P.otiles.end(), t.begin(), t.end());
+        for (const auto &t : blocks) P.otiles.insert(P.otiles.end(), t.begin(), t.end());
+        P.n_otile = (int32_t)tiles.size();
+        P.n_oblock = (int32_t)blocks.size();
+        // slice blocks: one pass over a colour class of the largest block, with two lanes per
+        // (site, group) when a class has at most 512 of them
+        int most = 1;
+        for (const auto &t : blocks) {
+            const InstDesc &d = P.desc[t[0]];
+            most = std::max<int>(most, (int)std::min<int64_t>(1024, ((int64_t)d.N * t[4] + d.n_colors - 1) / d.n_colors));
+        }
+        P.oblock_split = most <= 512;
+        if (P.oblock_split) most *= 2;
+        P.oblock_threads = 64;
+        while (P.oblock_threads < most && P.oblock_threads < 1024) P.oblock_threads *= 2;
         if (P.bp_sblk.size() / 2 > 0x7fffffff || P.bp_eblk.size() / 4 > 0x7fffffff)
             return fail(PT_EINVAL, "batch too large");
     }
@@ -385,6 +501,10 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
     P.o_bp_eblk = take(P.bp_eblk.size() * 4);
     P.o_bp_wg = take(P.bp_wg.size() * 4);
     P.o_bp_part = take((size_t)P.bp_n_eblk * 32 * 2 * 8);
+    P.o_oent = take(P.oent.size() * 2);
+    P.o_ohinfo = take(P.ohinfo.size());
+    P.o_otbl = take(P.otbl.size() * 4);
+    P.o_otiles = take(P.otiles.size() * 4);
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
     P.o_E = take((size_t)rep * 8);
@@ -800,26 +920,61 @@ int enqueue_bp_sweep(pt_ctx *c, int n_sweeps)
         if (rc) return rc;
         HIP_TRY(hipEventRecord(c->ev_pool[ea], c->stream));
     }
-    int parities = 1;
-    for (const auto &d : P.desc) parities = std::max(parities, d.parities);
-    BpLaunch L{};
-    L.st = c->st;
-    L.key0 = c->key_flip0;
-    L.key1 = c->key_flip1;
-    for (int sw = 0; sw < n_sweeps; ++sw)
-        for (int p = 0; p < parities; ++p)
-            for (int g = 0; g < (int)P.bp_colour.size(); ++g) {
-                L.sweep_off = sw;
-                L.p = p;
-                L.g = g;
-                L.blk0 = P.bp_colour[g].first;
-                L.n_blocks = P.bp_colour[g].second;  // instances with one parity skip p = 1
-                if (L.n_blocks == 0) continue;
-                const hipError_t e = launch_bp_sweep(L, c->stream);
-                if (e != hipSuccess) return hip_fail(e, "bit-packed sweep launch");
+    // octets: whole octets in one launch for all sweeps of the call; slice blocks one launch
+    // per parity of every sweep, their E_cl and C cleared first and summed by the last
+    OctLaunch O{};
+    O.st = c->st;
+    O.key0 = c->key_flip0;
+    O.key1 = c->key_flip1;
+    O.n_sweeps = n_sweeps;
+    if (P.n_otile > 0) {
+        O.tile0 = 0;
+        O.n_tiles = P.n_otile;
+        O.threads = c->block_threads;
+        O.lds_bytes = P.otile_lds;
+        const hipError_t e = launch_oct_tiles(O, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "octet tile launch");
+    }
+    if (P.n_oblock > 0) {
+        O.tile0 = P.n_otile;
+        O.n_tiles = P.n_oblock;
+        O.threads = P.oblock_threads;
+        O.lds_bytes = P.oblock_lds;
+        O.split = P.oblock_split ? 1 : 0;
+        hipError_t e = launch_oct_clear(O, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "octet clear launch");
+        for (int sw = 0; sw < n_sweeps; ++sw)
+            for (int p = 0; p < 2; ++p) {
+                O.sweep_off = sw;
+                O.p = p;
+                O.last = (sw == n_sweeps - 1 && p == 1) ? 1 : 0;
+                e = launch_oct_phase(O, c->stream);
+                if (e != hipSuccess) return hip_fail(e, "octet slice-block launch");
             }
-    const hipError_t e = energies_from_spins(c, 0, (int)P.total_reps);
-    if (e != hipSuccess) return hip_fail(e, "bit-packed energy launch");
+    }
+    if (P.bp_generic) {
+        int parities = 1;
+        for (const auto &d : P.desc) parities = std::max(parities, d.parities);
+        BpLaunch L{};
+        L.st = c->st;
+        L.key0 = c->key_flip0;
+        L.key1 = c->key_flip1;
+        for (int sw = 0; sw < n_sweeps; ++sw)
+            for (int p = 0; p < parities; ++p)
+                for (int g = 0; g < (int)P.bp_colour.size(); ++g) {
+                    L.sweep_off = sw;
+                    L.p = p;
+                    L.g = g;
+                    L.blk0 = P.bp_colour[g].first;
+                    L.n_blocks = P.bp_colour[g].second;  // instances with one parity skip p = 1
+                    if (L.n_blocks == 0) continue;
+                    const hipError_t e = launch_bp_sweep(L, c->stream);
+                    if (e != hipSuccess) return hip_fail(e, "bit-packed sweep launch");
+                }
+        // E_cl and C of every replica (the octets' are recomputed to the same values)
+        const hipError_t e = energies_from_spins(c, 0, (int)P.total_reps);
+        if (e != hipSuccess) return hip_fail(e, "bit-packed energy launch");
+    }
     if (timing) {
         HIP_TRY(hipEventRecord(c->ev_pool[eb], c->stream));
         c->sweep_ev.emplace_back(ea, eb);
@@ -968,17 +1123,20 @@ constexpr size_t kTuneRounds = 3;
 int enqueue_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
 {
     if (n_sweeps <= 0) return PT_OK;
-    if (c->plan.encoding == PT_BITPACK32) return enqueue_bp_sweep(c, n_sweeps);
-    if (!c->tuning) return enqueue_sweep_once(c, n_sweeps, fuse_exchange);
+    const bool bp = c->plan.encoding == PT_BITPACK32;
+    if (!c->tuning) return bp ? enqueue_bp_sweep(c, n_sweeps) : enqueue_sweep_once(c, n_sweeps, fuse_exchange);
     const size_t nc = c->cand.size();
     const size_t k = c->cand_next % nc;
     const auto shape = c->cand[k];
-    int rc = build_tiles(c, 0, shape.first);
-    if (rc) return rc;
+    int rc = PT_OK;
+    if (!bp) {
+        rc = build_tiles(c, 0, shape.first);
+        if (rc) return rc;
+    }
     c->block_threads = shape.second;
     HIP_TRY(hipEventRecord(c->tune_ev[0], c->stream));
     const int fb = c->fallbacks;
-    rc = enqueue_sweep_once(c, n_sweeps, fuse_exchange);
+    rc = bp ? enqueue_bp_sweep(c, n_sweeps) : enqueue_sweep_once(c, n_sweeps, fuse_exchange);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(c->tune_ev[1], c->stream));
     HIP_TRY(hipEventSynchronize(c->tune_ev[1]));
@@ -991,8 +1149,10 @@ int enqueue_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
         for (size_t j = 1; j < nc; ++j)
             if (c->cand_ms[j] < c->cand_ms[best]) best = j;
         c->tuning = false;
-        rc = build_tiles(c, 0, c->cand[best].first);
-        if (rc) return rc;
+        if (!bp) {
+            rc = build_tiles(c, 0, c->cand[best].first);
+            if (rc) return rc;
+        }
         c->block_threads = c->cand[best].second;
     }
     return PT_OK;
@@ -1188,6 +1348,10 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.bp_eblk = (const int32_t *)(w + P.o_bp_eblk);
     st.bp_wg = (const int32_t *)(w + P.o_bp_wg);
     st.bp_part = (int64_t *)(w + P.o_bp_part);
+    st.oent = (const uint16_t *)(w + P.o_oent);
+    st.ohinfo = (const uint8_t *)(w + P.o_ohinfo);
+    st.otbl = (const uint32_t *)(w + P.o_otbl);
+    st.otiles = (const int32_t *)(w + P.o_otiles);
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;
@@ -1214,6 +1378,10 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     put(P.o_bp_sblk, P.bp_sblk.data(), P.bp_sblk.size() * 4);
     put(P.o_bp_eblk, P.bp_eblk.data(), P.bp_eblk.size() * 4);
     put(P.o_bp_wg, P.bp_wg.data(), P.bp_wg.size() * 4);
+    put(P.o_oent, P.oent.data(), P.oent.size() * 2);
+    put(P.o_ohinfo, P.ohinfo.data(), P.ohinfo.size());
+    put(P.o_otbl, P.otbl.data(), P.otbl.size() * 4);
+    put(P.o_otiles, P.otiles.data(), P.otiles.size() * 4);
     for (int n = 0; n < n_inst; ++n) {
         const InstDesc &d = P.desc[n];
         for (int r = 0; r < d.R; ++r) {
@@ -1238,11 +1406,24 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     if (P.encoding == PT_INT8) {
         rc = build_tiles(c, opt->tile_replicas, opt->tile_bytes);
         if (rc) return cleanup(rc);
+    } else {
+        if (P.otile_lds > c->lds_limit || P.oblock_lds > c->lds_limit)
+            return cleanup(fail(PT_EINVAL, "octet work needs more LDS than the device has"));
+        e = oct_kernels_set_lds(P.otile_lds, P.oblock_lds);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "octet kernel LDS attribute"));
     }
-    if (P.encoding == PT_INT8 && opt->tile_replicas == 0 && opt->tile_bytes == 0 &&
-        opt->block_threads == 0) {
-        for (int tb : {8 * 1024, 16 * 1024, 32 * 1024, 64 * 1024, 128 * 1024})
-            for (int th : {256, 512, 1024}) c->cand.emplace_back(tb, th);
+    if (P.encoding == PT_BITPACK32) c->block_threads = opt->block_threads > 0 ? opt->block_threads : 256;
+    const bool tune_int8 = P.encoding == PT_INT8 && opt->tile_replicas == 0 &&
+                           opt->tile_bytes == 0 && opt->block_threads == 0;
+    // packed: the workgroup size of the whole-octet launch
+    const bool tune_bp = P.encoding == PT_BITPACK32 && P.n_otile > 0 && opt->block_threads == 0;
+    if (tune_int8 || tune_bp) {
+        if (tune_int8) {
+            for (int tb : {8 * 1024, 16 * 1024, 32 * 1024, 64 * 1024, 128 * 1024})
+                for (int th : {256, 512, 1024}) c->cand.emplace_back(tb, th);
+        } else {
+            for (int th : {256, 512, 1024}) c->cand.emplace_back(0, th);
+        }
         c->cand_ms.assign(c->cand.size(), 0.0);
         c->tuning = true;
         for (auto &ev : c->tune_ev) {
@@ -1540,7 +1721,10 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->block_tiles = c->n_block_tiles;
     o->block_resident = c->block_persistent;
     o->class_launches = 0;
-    if (c->plan.encoding == PT_BITPACK32) {
+    o->oct_tiles = c->plan.n_otile;
+    o->oct_blocks = c->plan.n_oblock;
+    o->oct_tile_launches = c->plan.n_otile > 0 ? 1 : 0;
+    if (c->plan.encoding == PT_BITPACK32 && c->plan.bp_generic) {
         int parities = 1;
         for (const auto &d : c->plan.desc) parities = std::max(parities, d.parities);
         o->class_launches = parities * (int32_t)c->plan.bp_colour.size();

@@ -42,6 +42,22 @@ struct BpLaunch {
     int32_t sweep_off, p, g, blk0, n_blocks;
 };
 
+// Bit-packed encoding, octet kernels.  An octet is byte o of the 32-slot words of word group
+// w: the 8 replica slots 32 w + 8 o .. 32 w + 8 o + 7.  A work item (five ints in
+// DevState::otiles) is (instance, w, o, first four-slice group g0, groups ng).
+//   tile launches (whole octets, ng = G4): n_sweeps sweeps with the octet resident in LDS,
+//     then its E_cl and C;
+//   phase launches (octet slice blocks): parity p of sweep t + sweep_off; with last, the
+//     blocks add their part of E_cl and C (cleared by launch_oct_clear) at the end.
+struct OctLaunch {
+    DevState st;
+    uint32_t key0, key1;
+    int32_t tile0, n_tiles, threads, lds_bytes;
+    int32_t n_sweeps, sweep_off, p, last;
+    int32_t split;  // slice blocks: two lanes per (site, group), four slots each
+};
+constexpr int kOctRec = 5;  // ints per octet work item
+
 // Each returns the hipError_t of the launch itself (asynchronous execution errors
 // surface at the next synchronisation).
 hipError_t launch_init_spins(const DevState &st, int32_t n_reps, uint32_t key0, uint32_t key1,
@@ -63,6 +79,15 @@ hipError_t launch_bp_init(const DevState &st, int32_t n_eblk, uint32_t key0, uin
                           hipStream_t s);
 hipError_t launch_bp_sweep(const BpLaunch &L, hipStream_t s);
 hipError_t launch_bp_energy(const DevState &st, int32_t n_eblk, int32_t n_reps, hipStream_t s);
+hipError_t launch_oct_tiles(const OctLaunch &L, hipStream_t s);
+hipError_t launch_oct_phase(const OctLaunch &L, hipStream_t s);
+// E_cl and C of the replicas of octet work items [tile0, tile0 + n_tiles) set to zero (the
+// phase launches' last sweep adds to them).
+hipError_t launch_oct_clear(const OctLaunch &L, hipStream_t s);
+// LDS bytes of an octet work item of instance d with ng groups per parity (whole octet:
+// ng = G4) and the phase layout when phase is set.
+int32_t oct_lds_bytes(const InstDesc &d, int32_t ng, bool phase);
+hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes);
 hipError_t launch_threshold_eval(const double *dS, uint32_t *out, int32_t n, hipStream_t s);
 hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes);
 // Slice-block workgroups of `threads` threads and `lds_bytes` of LDS that one compute unit

@@ -428,8 +428,7 @@ struct FastArgs {
 
 // Neighbour entry e of site i's row in LDS as (byte offset of the neighbour's row within a
 // parity plane, weight word): the weight word is the entry itself under kEntPerm (its low
-// bytes are the v_perm table w0, w1), and the mask m = 0x01010101 [J < 0] under kEntXad
-// and kEntXad16.
+// bytes are the v_perm table w0, w1), and the mask m = 0x01010101 [J < 0] under kEntXad16.
 template <int EM>
 __device__ __forceinline__ void fast_entry(const uint32_t *ent, int idx, uint32_t &off, uint32_t &w)
 {
@@ -440,7 +439,7 @@ __device__ __forceinline__ void fast_entry(const uint32_t *ent, int idx, uint32_
     } else {
         const uint32_t v = ent[idx];
         off = v >> 16;
-        w = (EM == kEntXad) ? __builtin_amdgcn_perm(0u, v, 0u) : v;
+        w = v;
     }
 }
 
@@ -597,18 +596,15 @@ __device__ __forceinline__ void fast_sweeps(const SweepLaunch &L, const InstDesc
     // entries (the large replicas they are meant for; the host guarantees it), so only
     // those instantiations carry them
     constexpr bool k16 = WIDE && NW == 2 && (DT == 0 || DT >= 4);
-    if (WIDE && d.ent_mode == kEntXad)
-        run(IntC<WIDE ? kEntXad : kEntPerm>{});
-    else if (k16 && d.ent_mode == kEntXad16)
+    if (k16 && d.ent_mode == kEntXad16)
         run(IntC<k16 ? kEntXad16 : kEntPerm>{});
     else
         run(IntC<kEntPerm>{});
 }
 
-// WIDE: the instantiation carries the kEntXad and kEntXad16 forms.  The multi-cycle kernel
-// does not (with them it would need more registers than its four waves per SIMD allow): it
-// reads kEntXad entries, which have the kEntPerm layout, the kEntPerm way, and its
-// instances fit one tile each, which kEntXad16 instances never do.
+// WIDE: the instantiation carries the kEntXad16 form.  The multi-cycle kernel does not
+// (with it it would need more registers than its four waves per SIMD allow): its instances
+// fit one tile each, which kEntXad16 instances never do.
 template <int NW, bool WIDE>
 __device__ __forceinline__ void fast_dispatch(const SweepLaunch &L, const InstDesc &d,
                                               const Tile &tile, const TileLds &t, uint64_t t0)

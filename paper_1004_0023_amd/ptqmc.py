@@ -78,7 +78,9 @@ class _Info(C.Structure):
                 ("exchange_launches", C.c_int64), ("sweep_groups", C.c_int32),
                 ("block_tiles", C.c_int32), ("block_resident", C.c_int32),
                 ("class_launches", C.c_int32), ("multi_launches", C.c_int64),
-                ("multi_cycles", C.c_int64), ("multi_ms", C.c_double)]
+                ("multi_cycles", C.c_int64), ("multi_ms", C.c_double),
+                ("oct_tiles", C.c_int32), ("oct_blocks", C.c_int32),
+                ("oct_tile_launches", C.c_int32)]
 
 
 _lib = None

@@ -139,10 +139,53 @@ def test_config4_lattice_one_cycle(ptqmc):
     say("case: bit-packed config 4, 1 cycle of 10 sweeps")
     with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, encoding=ptqmc.PT_BITPACK32) as s:
         s.run(1)
-        assert s.info()["class_launches"] == 4
+        info = s.info()
+        # octet slice blocks (a whole octet, N * M bytes, exceeds half a unit's LDS)
+        assert info["oct_blocks"] > 0 and info["oct_tiles"] == 0 and info["class_launches"] == 0
         ref = oracle.OracleChain(inst, seed)
         ref.run(10, 1)
         assert_same(s, 0, ref, "config4")
+
+
+def octet_batch():
+    """Instances the octet kernels take (+-1 couplings, |h| <= 1, one degree, M a
+    power-of-two multiple of 8): the smallest M (8), degree 8 with fields (nine adder-tree
+    inputs), replica counts that leave a word's last octet partly filled (9, 24 + 1 of a
+    second word), config 1, and one octet too large for a workgroup's share of LDS
+    (N = 600, M = 128), which runs as slice blocks; plus an instance with |J| = 2 that
+    goes to the per-class kernel."""
+    rng = np.random.default_rng([1004, 28])
+    return [
+        W.random_small_instance(rng, 6, 8, 9, d=3, jmax=1, hmax=1, name="m8r9"),
+        W.random_small_instance(rng, 31, 16, 33, d=8, jmax=1, hmax=1, name="d8r33"),
+        W.random_small_instance(rng, 50, 64, 16, d=4, jmax=1, hmax=1, name="n50"),
+        W.config1(),
+        W.random_small_instance(rng, 600, 128, 12, d=4, jmax=1, hmax=1, t_min=0.5,
+                                name="blocks"),
+        W.random_small_instance(rng, 12, 16, 6, d=3, jmax=2, hmax=1, name="generic"),
+    ]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_octet_kernels_match_oracle(ptqmc, graph):
+    """Whole octets resident for a call, octet slice blocks launched per parity, and the
+    per-class kernel for the rest, in one batch, against the oracle."""
+    insts = octet_batch()
+    seed = 0x0C7E7
+    k, cycles = 3, 18
+    say(f"case: bit-packed octet batch, {cycles} cycles of {k} sweeps, graph={graph}")
+    refs = oracle_batch(insts, seed, k, cycles)
+    flags = 0 if graph else ptqmc.PT_FLAG_NO_GRAPH
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, encoding=ptqmc.PT_BITPACK32,
+                       flags=flags) as s:
+        info = s.info()
+        assert info["oct_tiles"] > 0 and info["oct_blocks"] > 0 and info["class_launches"] > 0
+        s.run(cycles)
+        s.sweep(2)  # a call of another length (the blocks' last launch sums the energies)
+        for r in refs:
+            r.sweep(2)
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], "octets")
 
 
 def test_checkpoint_and_spins(ptqmc):
