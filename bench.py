@@ -1,6 +1,6 @@
 """Benchmark: spin-flip attempts per second of the parallel-tempering sampler on one GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3] [--encoding int8]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3] [--encoding int8|bitpack]
 
 A step is one PT cycle over the whole batch: sweeps_per_exchange Metropolis sweeps of
 every replica of every instance (with the energy bookkeeping of each replica), then one
@@ -9,8 +9,9 @@ state is resident in device memory when the timed region starts.  Prints one JSO
 
 The default workload is the batched one (512 instances of uneven size in one launch),
 the configuration whose sweep kernel the roofline target refers to; --config 1, 2 or 4
-selects the single-instance workloads.  --encoding bitpack keeps 32 replica slots per
-32-bit word (the same chain; one sweep launch per colour class).
+selects the single-instance workloads.  --encoding int8 keeps one byte per spin,
+--encoding bitpack 32 replica slots per 32-bit word (the same chain either way); the
+default is bitpack for configs 3 and 4 and int8 for configs 1 and 2.
 
     python bench.py --copy-calibration BYTES
 
@@ -35,8 +36,19 @@ sys.path.insert(0, ROOT)
 CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_INT_OPS = CUS * LANES_PER_CU * CLOCK_HZ  # 3.93e13 32-bit VALU lane-ops/s
 
-SWEEP_SOURCE = os.path.join(ROOT, "paper_1004_0023_amd", "csrc", "pt_kernels.hip")
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_fast_kernel_config3_traffic.json")
+# Committed HBM-traffic records (profiler counters, scaled by a copy calibration) per
+# (kernel, workload), each with the source file whose SHA-256 it was measured on.
+_CSRC = os.path.join(ROOT, "paper_1004_0023_amd", "csrc")
+TRAFFIC_RECORDS = {
+    ("sweep_fast_kernel", 3): (os.path.join(ROOT, "profiles", "sweep_fast_kernel_config3_traffic.json"),
+                               os.path.join(_CSRC, "pt_kernels.hip")),
+    ("oct_tile_kernel", 3): (os.path.join(ROOT, "profiles", "oct_tile_kernel_config3_traffic.json"),
+                             os.path.join(_CSRC, "pt_octet.hip")),
+}
+# The encoding each workload runs in unless --encoding says otherwise: the lattice is
+# specified bit-packed; the batch runs in whichever encoding is faster on it (bit-packed,
+# measured); the single small instances are specified as bytes.
+DEFAULT_ENCODING = {1: "int8", 2: "int8", 3: "bitpack", 4: "bitpack"}
 
 
 def ops_per_flip(avg_degree: float) -> float:
@@ -124,13 +136,17 @@ def cpu_baseline(insts, seed, k, budget_s=2.0, max_threads=16):
                       f"{ncpu} CPUs available"}
 
 
-def traffic_per_launch():
-    """HBM bytes per sweep launch from the committed profiler record, or None when the
-    kernel source has changed since the counters were taken."""
+def traffic_per_launch(kernel: str = "sweep_fast_kernel", config: int = 3):
+    """HBM bytes per launch of `kernel` on workload `config` from the committed profiler
+    record, or None when there is none or the kernel source has changed since the
+    counters were taken."""
+    ent = TRAFFIC_RECORDS.get((kernel, config))
+    if ent is None:
+        return None
     try:
-        with open(TRAFFIC_RECORD) as f:
+        with open(ent[0]) as f:
             rec = json.load(f)
-        with open(SWEEP_SOURCE, "rb") as f:
+        with open(ent[1], "rb") as f:
             digest = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
@@ -161,7 +177,8 @@ def main():
     ap.add_argument("--tile-bytes", type=int, default=0)
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0)
-    ap.add_argument("--encoding", choices=["int8", "bitpack"], default="int8")
+    ap.add_argument("--encoding", choices=["int8", "bitpack"], default=None,
+                    help="spin encoding (default: bitpack for configs 3 and 4, int8 otherwise)")
     ap.add_argument("--tau-corr", action="store_true",
                     help="also accumulate imaginary-time correlations at every exchange step")
     args = ap.parse_args()
@@ -178,6 +195,8 @@ def main():
     import workloads as W
     from paper_1004_0023_amd import ptqmc
 
+    if args.encoding is None:
+        args.encoding = DEFAULT_ENCODING.get(args.config, "int8")
     torch.cuda.set_device(0)
     insts, desc = workload(args.config)
     k = W.sweeps_per_exchange(args.config)
@@ -255,7 +274,12 @@ def main():
         avg_sweep_s = launch_s / cycles_per_launch  # one cycle, its exchange included
     else:
         avg_sweep_s = cal["sweep_ms"] / max(1, cal["sweep_launches"]) / 1e3
-        if packed and cal["oct_blocks"] > 0 and cal["oct_tiles"] == 0 and cal["class_launches"] == 0:
+        if (packed and cal["oct_blocks"] > 0 and cal["oct_tiles"] == 0 and
+                cal["class_launches"] == 0 and cal["oct_resident"]):
+            # octet slice blocks, all resident: one launch per call
+            kernel = "oct_resident_kernel"
+            launches_per_call = 1
+        elif packed and cal["oct_blocks"] > 0 and cal["oct_tiles"] == 0 and cal["class_launches"] == 0:
             # octet slice blocks: one launch per parity of every sweep
             kernel = "oct_phase_kernel"
             launches_per_call = 2 * k
@@ -304,7 +328,9 @@ def main():
                    "lds_bytes": info["lds_bytes"], "timed_route": route,
                    "encoding": args.encoding,
                    "tau_corr": bool(args.tau_corr),
-                   "block_resident": bool(cal["block_resident"]) if blocked else None,
+                   "block_resident": (bool(cal["block_resident"]) if blocked else
+                                      bool(cal["oct_resident"]) if packed and cal["oct_blocks"] > 0
+                                      else None),
                    "segment_rates": {"segments": n_seg,
                                      "mean": statistics.mean(seg_rates),
                                      "std": statistics.pstdev(seg_rates),
@@ -319,7 +345,7 @@ def main():
                                    "ops_per_launch": ops_launch}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak,
-                     "traffic": traffic_per_launch() if args.config == 3 and not packed else None,
+                     "traffic": traffic_per_launch(kernel, args.config),
                      "kernel": kernel},
     }
     s.close()

@@ -101,8 +101,9 @@ extern "C" {
                                       LDS always are                                   */
 #define PT_FLAG_FOUR_SLICE_LANES 0x10u /* fast path: one four-slice word per lane instead
                                           of two (same chain; a measurement and test hook) */
-#define PT_FLAG_BLOCK_LAUNCH_PER_SWEEP 0x20u /* slice blocks: one launch per sweep even when
-                                          all blocks could be resident at once (same
+#define PT_FLAG_BLOCK_LAUNCH_PER_SWEEP 0x20u /* slice blocks: one launch per sweep (octet
+                                          slice blocks: per parity of every sweep) even
+                                          when all blocks could be resident at once (same
                                           chain; a measurement and test hook)          */
 #define PT_FLAG_TAU_CORR 0x80u     /* accumulate imaginary-time spin correlations per rung
                                       at every exchange step (pt_obs.sumCt); PT_INT8 only */
@@ -191,10 +192,14 @@ typedef struct {
     int32_t oct_tiles;                /* PT_BITPACK32: whole octets (8 replica slots of one
                                          word group) swept resident in LDS, all sweeps of
                                          a call in one launch                           */
-    int32_t oct_blocks;               /* PT_BITPACK32: octet slice blocks, one launch per
+    int32_t oct_blocks;               /* PT_BITPACK32: octet slice blocks (octets too
+                                         large for one workgroup's LDS, split in time)  */
+    int32_t oct_tile_launches;        /* launches per call of the whole octets (0 or 1) */
+    int32_t oct_resident;             /* 1: the octet slice blocks run all sweeps of a
+                                         call in one launch, every block resident and
+                                         boundary groups passed between neighbouring
+                                         blocks in device memory; 0: one launch per
                                          parity of every sweep                          */
-    int32_t oct_tile_launches;        /* launches per call of the whole octets (one per
-                                         workgroup size)                                */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

@@ -227,12 +227,16 @@ struct DevState {
     const int32_t *bp_wg;
     int64_t *bp_part;
     // bit-packed encoding, octet kernels: 16-bit neighbour entries (j | [J < 0] << 15, D per
-    // site), per-site field codes (bit 0: h < 0, bit 1: h != 0), per-rung tables, and the
-    // work list (instance, word group, octet, first group, groups) of the octet launches
+    // site), per-site field codes (bit 0: h < 0, bit 1: h != 0), per-rung tables, the work
+    // list of the octet launches (kOctRec ints per item), and for resident slice blocks
+    // their boundary records (an R0 region, then an R1 region) and progress counts (two per
+    // work item: parity 0, parity 1)
     const uint16_t *oent;
     const uint8_t *ohinfo;
     const uint32_t *otbl;
     const int32_t *otiles;
+    uint32_t *orec;
+    int32_t *oprog;
     // mutable state
     uint8_t *spins;
     int64_t *E;       // per replica slot

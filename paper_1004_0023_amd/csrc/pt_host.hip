@@ -78,13 +78,15 @@ struct Plan {
     int32_t otile_lds = 0, oblock_lds = 0;     // their largest LDS need
     int32_t oblock_threads = 256;
     bool oblock_split = false;                 // slice blocks: two lanes per (site, group)
+    int32_t oblock_res_lds = 0;                // slice blocks, resident layout
+    int64_t orec_words = 0;                    // words of each boundary-record region
     bool bp_generic = false;                   // some packed instance runs the per-class kernel
     int64_t halo_words = 0; // one buffer of slice-block boundary records, at most
     uint64_t flips_per_sweep = 0;
     // byte offsets in the workspace
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
         o_repinst, o_halo, o_itiles, o_icount, o_prog, o_err, o_bp_sblk, o_bp_eblk, o_bp_wg,
-        o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles;
+        o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles, o_orec, o_oprog;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr, o_sumCt;
@@ -351,8 +353,9 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
         }
         for (int c = 0; c < in.R; ++c) P.rep_inst.push_back(n);
         P.n_adj.push_back(2 * in.n_edges);
-        P.max_tiles += (int64_t)in.R * std::max(1, d.G4);
-        if (d.fast) {
+        // byte-encoding tiles and slice-block records (the bit-packed kernels use neither)
+        if (P.encoding == PT_INT8) P.max_tiles += (int64_t)in.R * std::max(1, d.G4);
+        if (d.fast && P.encoding == PT_INT8) {
             // boundary records for slice blocks: three N-word rows per block, at most one
             // block per four-slice group, for every instance that may run as blocks
             const int lgMh_n = 31 - __builtin_clz((unsigned)d.Mh);
@@ -424,25 +427,28 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
                 P.bp_generic = true;
                 continue;
             }
-            const bool whole = oct_lds_bytes(d, d.G4, false) <= kLdsPerWorkgroup / 2;
+            const bool whole = oct_lds_bytes(d, d.G4, kOctTile) <= kLdsPerWorkgroup / 2;
             int ng = d.G4;
             if (!whole) {
                 ng = 1;
-                while (2 * ng <= d.G4 && (int64_t)2 * ng * d.N <= 512 * (int64_t)d.n_colors &&
-                       oct_lds_bytes(d, 2 * ng, true) <= kLdsPerWorkgroup / 2)
+                while (2 * ng < d.G4 && (int64_t)2 * ng * d.N <= 512 * (int64_t)d.n_colors &&
+                       oct_lds_bytes(d, 2 * ng, kOctResident) <= kLdsPerWorkgroup / 2)
                     ng *= 2;
-                if (oct_lds_bytes(d, ng, true) > kLdsPerWorkgroup)
+                if (oct_lds_bytes(d, ng, kOctResident) > kLdsPerWorkgroup)
                     return fail(PT_EINVAL, "instance " + std::to_string(n) +
                                                ": an octet slice block does not fit in LDS");
             }
             for (int w = 0; w < d.bp_W; ++w)
                 for (int o = 0; o < 4 && 32 * w + 8 * o < d.R; ++o) {
                     if (whole) {
-                        tiles.push_back({n, w, o, 0, d.G4});
-                        P.otile_lds = std::max(P.otile_lds, oct_lds_bytes(d, d.G4, false));
+                        tiles.push_back({n, w, o, 0, d.G4, 0, 0, 0});
+                        P.otile_lds = std::max(P.otile_lds, oct_lds_bytes(d, d.G4, kOctTile));
                     } else {
-                        for (int g0 = 0; g0 < d.G4; g0 += ng) blocks.push_back({n, w, o, g0, ng});
-                        P.oblock_lds = std::max(P.oblock_lds, oct_lds_bytes(d, ng, true));
+                        // the octet's ring of blocks (at least two: ng < G4), consecutive in
+                        // the list; neighbours and record offsets are filled in below
+                        for (int g0 = 0; g0 < d.G4; g0 += ng) blocks.push_back({n, w, o, g0, ng, 0, 0, 0});
+                        P.oblock_lds = std::max(P.oblock_lds, oct_lds_bytes(d, ng, kOctPhase));
+                        P.oblock_res_lds = std::max(P.oblock_res_lds, oct_lds_bytes(d, ng, kOctResident));
                     }
                 }
         }
@@ -454,6 +460,42 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
             const InstDesc &da = P.desc[a[0]], &db = P.desc[b[0]];
             return (int64_t)da.N * da.M > (int64_t)db.N * db.M;
         });
+        // The octets of one word group read the same 16-byte pieces of device memory and
+        // write different bytes of them, so they should share an XCD's L2.  Workgroups go to
+        // the XCDs round robin by index: the word groups (still largest first) are dealt to
+        // per-XCD queues, each to the least loaded, and workgroup 8 s + x takes entry s of
+        // queue x (the last rounds, where queue lengths differ, keep their order only).
+        {
+            constexpr int kXcds = 8;
+            std::vector<std::vector<std::array<int32_t, kOctRec>>> q(kXcds);
+            std::vector<int64_t> load(kXcds, 0);
+            for (size_t k = 0; k < tiles.size();) {
+                size_t e = k + 1;
+                while (e < tiles.size() && tiles[e][0] == tiles[k][0] && tiles[e][1] == tiles[k][1]) ++e;
+                const InstDesc &d = P.desc[tiles[k][0]];
+                const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                for (size_t j = k; j < e; ++j) q[x].push_back(tiles[j]);
+                load[x] += (int64_t)d.N * d.M * (int64_t)(e - k);
+                k = e;
+            }
+            std::vector<std::array<int32_t, kOctRec>> dealt;
+            dealt.reserve(tiles.size());
+            for (size_t r = 0; dealt.size() < tiles.size(); ++r)
+                for (int x = 0; x < kXcds; ++x)
+                    if (r < q[x].size()) dealt.push_back(q[x][r]);
+            tiles.swap(dealt);
+        }
+        for (size_t k = 0; k < blocks.size(); ++k) {
+            auto &t = blocks[k];
+            const InstDesc &d = P.desc[t[0]];
+            const int ring = d.G4 / t[4];              // blocks of the octet
+            const int first = (int)k - t[3] / t[4];    // its block at group 0
+            const int base = (int)tiles.size();        // blocks follow the tiles in the list
+            t[5] = (int32_t)P.orec_words;
+            t[6] = base + first + (t[3] / t[4] + ring - 1) % ring;
+            t[7] = base + first + (t[3] / t[4] + 1) % ring;
+            P.orec_words += d.N;
+        }
         for (const auto &t : tiles) P.otiles.insert(P.otiles.end(), t.begin(), t.end());
         for (const auto &t : blocks) P.otiles.insert(P.otiles.end(), t.begin(), t.end());
         P.n_otile = (int32_t)tiles.size();
@@ -469,7 +511,8 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
         if (P.oblock_split) most *= 2;
         P.oblock_threads = 64;
         while (P.oblock_threads < most && P.oblock_threads < 1024) P.oblock_threads *= 2;
-        if (P.bp_sblk.size() / 2 > 0x7fffffff || P.bp_eblk.size() / 4 > 0x7fffffff)
+        if (P.bp_sblk.size() / 2 > 0x7fffffff || P.bp_eblk.size() / 4 > 0x7fffffff ||
+            P.orec_words > 0x3fffffff)
             return fail(PT_EINVAL, "batch too large");
     }
     // layout
@@ -505,6 +548,8 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
     P.o_ohinfo = take(P.ohinfo.size());
     P.o_otbl = take(P.otbl.size() * 4);
     P.o_otiles = take(P.otiles.size() * 4);
+    P.o_orec = take((size_t)P.orec_words * 2 * 4);
+    P.o_oprog = take((size_t)(P.n_otile + P.n_oblock) * 2 * 4);
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
     P.o_E = take((size_t)rep * 8);
@@ -604,6 +649,7 @@ struct pt_ctx {
     std::pair<int, int> resident_key{-1, -1};
     int resident_per_cu = 0;
     int block_persistent = 0;   // the last slice-block call ran as one resident launch
+    bool oct_resident = false;  // octet slice blocks: one resident launch per call
     int block_threads = 256;
     int tile_bytes = 0;        // target spin bytes per tile in use
     // self-tuning: candidate (tile bytes, threads) shapes timed on the first sweep launches
@@ -883,8 +929,9 @@ hipError_t blocks_resident(pt_ctx *c, bool &resident)
     return hipSuccess;
 }
 
-// Wait for the stream, then fail if a resident slice-block launch gave up a wait (the
-// error word is cleared; the chain state after such a launch is not the sampler's).
+// Wait for the stream, then fail if a kernel set the device error word (a resident
+// slice-block launch that gave up a wait, an octet kernel that refused to run); the word is
+// cleared, and the chain state after such a launch is not the sampler's.
 int sync_and_check(pt_ctx *c)
 {
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -893,6 +940,9 @@ int sync_and_check(pt_ctx *c)
     if (err != 0) {
         const uint32_t zero = 0;
         HIP_TRY(hipMemcpy(c->ws + c->plan.o_err, &zero, 4, hipMemcpyHostToDevice));
+        if (err & kErrLdsBase)
+            return fail(PT_ESTATE, "an octet kernel found its dynamic LDS away from address 0 "
+                                   "and did not run; the state is inconsistent");
         return fail(PT_ESTATE, "a resident slice-block launch waited too long for its "
                                "neighbouring blocks; the state is inconsistent");
     }
@@ -920,8 +970,9 @@ int enqueue_bp_sweep(pt_ctx *c, int n_sweeps)
         if (rc) return rc;
         HIP_TRY(hipEventRecord(c->ev_pool[ea], c->stream));
     }
-    // octets: whole octets in one launch for all sweeps of the call; slice blocks one launch
-    // per parity of every sweep, their E_cl and C cleared first and summed by the last
+    // octets: whole octets in one launch for all sweeps of the call; slice blocks in one
+    // resident launch, or else one launch per parity of every sweep, their E_cl and C
+    // cleared first and summed by the resident launch or the last phase launch
     OctLaunch O{};
     O.st = c->st;
     O.key0 = c->key_flip0;
@@ -943,7 +994,17 @@ int enqueue_bp_sweep(pt_ctx *c, int n_sweeps)
         O.split = P.oblock_split ? 1 : 0;
         hipError_t e = launch_oct_clear(O, c->stream);
         if (e != hipSuccess) return hip_fail(e, "octet clear launch");
-        for (int sw = 0; sw < n_sweeps; ++sw)
+        if (c->oct_resident) {
+            O.lds_bytes = P.oblock_res_lds;
+            O.rec_words = (int32_t)P.orec_words;
+            if (c->opt.flags & PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT) {
+                O.wait_polls = 16;
+                O.wait_extra = 1 << 30;
+            }
+            e = launch_oct_resident(O, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "octet resident launch");
+        }
+        for (int sw = 0; sw < n_sweeps && !c->oct_resident; ++sw)
             for (int p = 0; p < 2; ++p) {
                 O.sweep_off = sw;
                 O.p = p;
@@ -1352,6 +1413,8 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.ohinfo = (const uint8_t *)(w + P.o_ohinfo);
     st.otbl = (const uint32_t *)(w + P.o_otbl);
     st.otiles = (const int32_t *)(w + P.o_otiles);
+    st.orec = (uint32_t *)(w + P.o_orec);
+    st.oprog = (int32_t *)(w + P.o_oprog);
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;
@@ -1407,10 +1470,19 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
         rc = build_tiles(c, opt->tile_replicas, opt->tile_bytes);
         if (rc) return cleanup(rc);
     } else {
-        if (P.otile_lds > c->lds_limit || P.oblock_lds > c->lds_limit)
+        if (P.otile_lds > c->lds_limit || P.oblock_lds > c->lds_limit ||
+            P.oblock_res_lds > c->lds_limit)
             return cleanup(fail(PT_EINVAL, "octet work needs more LDS than the device has"));
-        e = oct_kernels_set_lds(P.otile_lds, P.oblock_lds);
+        e = oct_kernels_set_lds(P.otile_lds, P.oblock_lds, P.oblock_res_lds);
         if (e != hipSuccess) return cleanup(hip_fail(e, "octet kernel LDS attribute"));
+        // octet slice blocks run resident (one launch per call) when every block fits the
+        // compute units at once: blocks wait for their neighbours, which must all have started
+        if (P.n_oblock > 0 && !(opt->flags & PT_FLAG_BLOCK_LAUNCH_PER_SWEEP)) {
+            int32_t per_cu = 0;
+            e = oct_resident_per_cu(P.oblock_threads, P.oblock_res_lds, &per_cu);
+            if (e != hipSuccess) return cleanup(hip_fail(e, "octet occupancy query"));
+            c->oct_resident = (int64_t)P.n_oblock <= (int64_t)per_cu * c->cus;
+        }
     }
     if (P.encoding == PT_BITPACK32) c->block_threads = opt->block_threads > 0 ? opt->block_threads : 256;
     const bool tune_int8 = P.encoding == PT_INT8 && opt->tile_replicas == 0 &&
@@ -1724,6 +1796,7 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->oct_tiles = c->plan.n_otile;
     o->oct_blocks = c->plan.n_oblock;
     o->oct_tile_launches = c->plan.n_otile > 0 ? 1 : 0;
+    o->oct_resident = c->oct_resident ? 1 : 0;
     if (c->plan.encoding == PT_BITPACK32 && c->plan.bp_generic) {
         int parities = 1;
         for (const auto &d : c->plan.desc) parities = std::max(parities, d.parities);

@@ -43,20 +43,36 @@ struct BpLaunch {
 };
 
 // Bit-packed encoding, octet kernels.  An octet is byte o of the 32-slot words of word group
-// w: the 8 replica slots 32 w + 8 o .. 32 w + 8 o + 7.  A work item (five ints in
-// DevState::otiles) is (instance, w, o, first four-slice group g0, groups ng).
+// w: the 8 replica slots 32 w + 8 o .. 32 w + 8 o + 7.  A work item (kOctRec ints in
+// DevState::otiles) is (instance, w, o, first four-slice group g0, groups ng, record
+// offset, previous item, next item); the last three serve resident slice blocks: the
+// offset of the block's two boundary records (N words each) and the blocks that own groups
+// g0 - 1 and g0 + ng of the same octet.
 //   tile launches (whole octets, ng = G4): n_sweeps sweeps with the octet resident in LDS,
 //     then its E_cl and C;
 //   phase launches (octet slice blocks): parity p of sweep t + sweep_off; with last, the
-//     blocks add their part of E_cl and C (cleared by launch_oct_clear) at the end.
+//     blocks add their part of E_cl and C (cleared by launch_oct_clear) at the end;
+//   resident launches (octet slice blocks, all resident at once): n_sweeps sweeps, the
+//     blocks exchanging boundary groups through records and progress counts, then their
+//     parts of E_cl and C.
 struct OctLaunch {
     DevState st;
     uint32_t key0, key1;
     int32_t tile0, n_tiles, threads, lds_bytes;
     int32_t n_sweeps, sweep_off, p, last;
-    int32_t split;  // slice blocks: two lanes per (site, group), four slots each
+    int32_t split;      // slice blocks: two lanes per (site, group), four slots each
+    int32_t rec_words;  // resident: words of the R0 record region (the R1 region follows)
+    // resident: poll bound of a neighbour wait (0: the kernel's default) and an amount added
+    // to every awaited progress count (0; a test hook sets it so that the waits give up)
+    int32_t wait_polls, wait_extra;
 };
-constexpr int kOctRec = 5;  // ints per octet work item
+constexpr int kOctRec = 8;  // ints per octet work item
+enum OctMode { kOctTile = 0, kOctPhase = 1, kOctResident = 2 };
+
+
+// Bits of the device error word (DevState::err), read and cleared by the host after a call.
+constexpr uint32_t kErrWait = 1u;     // a resident slice block gave up waiting for a neighbour
+constexpr uint32_t kErrLdsBase = 2u;  // an octet kernel found its dynamic LDS away from address 0
 
 // Each returns the hipError_t of the launch itself (asynchronous execution errors
 // surface at the next synchronisation).
@@ -81,13 +97,18 @@ hipError_t launch_bp_sweep(const BpLaunch &L, hipStream_t s);
 hipError_t launch_bp_energy(const DevState &st, int32_t n_eblk, int32_t n_reps, hipStream_t s);
 hipError_t launch_oct_tiles(const OctLaunch &L, hipStream_t s);
 hipError_t launch_oct_phase(const OctLaunch &L, hipStream_t s);
+hipError_t launch_oct_resident(const OctLaunch &L, hipStream_t s);
 // E_cl and C of the replicas of octet work items [tile0, tile0 + n_tiles) set to zero (the
-// phase launches' last sweep adds to them).
+// phase launches' last sweep and the resident launch add to them), and their progress
+// counts.
 hipError_t launch_oct_clear(const OctLaunch &L, hipStream_t s);
 // LDS bytes of an octet work item of instance d with ng groups per parity (whole octet:
-// ng = G4) and the phase layout when phase is set.
-int32_t oct_lds_bytes(const InstDesc &d, int32_t ng, bool phase);
-hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes);
+// ng = G4) in layout mode (OctMode).
+int32_t oct_lds_bytes(const InstDesc &d, int32_t ng, int mode);
+hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes, int32_t resident_bytes);
+// Resident octet slice blocks of `threads` threads and `lds_bytes` of LDS that one compute
+// unit holds at once.
+hipError_t oct_resident_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu);
 hipError_t launch_threshold_eval(const double *dS, uint32_t *out, int32_t n, hipStream_t s);
 hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes);
 // Slice-block workgroups of `threads` threads and `lds_bytes` of LDS that one compute unit

@@ -362,6 +362,10 @@ __device__ void exchange_instance(const DevState &st, int n, uint32_t key0, uint
 }
 
 
+// s_waitcnt immediate with the vector-memory count 0 and the export and LDS counts at
+// their maxima (no wait on them): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // End of a tile in a PT cycle: count the tile for its instance and, in the workgroup that
 // completes the instance, run the instance's exchange step.  Every tile's spins and
 // energies are written before its count (agent-scope release), and the completing
@@ -371,9 +375,13 @@ __device__ void exchange_instance(const DevState &st, int n, uint32_t key0, uint
 __device__ __forceinline__ void finish_tile(const SweepLaunch &L, const DevState &st, int n,
                                             long long *flag)
 {
+    // every wave's stores complete (a workgroup barrier does not wait for them), then thread
+    // 0 writes the XCD's L2 back and waits for that write-back before it counts the tile
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
+        __builtin_amdgcn_s_waitcnt(0);
         const uint32_t before = atomicAdd(&st.icount[n], 1u);
         const int done = (before + 1u == (uint32_t)st.itiles[n]) ? 1 : 0;
         if (done) st.icount[n] = 0;
@@ -1103,6 +1111,21 @@ __global__ void block_prepare_kernel(SweepLaunch L)
         }
 }
 
+// Resident slice blocks pass boundary records and progress counts between workgroups on
+// different XCDs, whose L2 caches are not coherent with one another.  Both are read and
+// written only with agent-scope atomic operations, which the hardware performs coherently
+// for the whole device, so no L2 write-back or invalidation is needed: every wave waits for
+// its record stores to complete before the barrier that precedes the count's store, and a
+// block issues its halo loads only after it has seen the counts.
+__device__ __forceinline__ uint32_t rec_ld(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void rec_st(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Stage a slice block into LDS: the owned groups of both planes from the spins (16-byte
 // pieces when VEC, i.e. ng is a multiple of 4), the halos from the neighbours' boundary
 // records, then rows, biases, colour lists and the rung table (a slice block holds one
@@ -1168,9 +1191,9 @@ __device__ __forceinline__ void block_stage(const DevState &st, const InstDesc &
     uint16_t cs0 = 0;
     int32_t co0 = 0;
     if (row0) {
-        h1p = rec_in[tp.hb + 2 * N + tid];
-        h0n = rec_in[tn.hb + tid];
-        h1n = rec_in[tn.hb + N + tid];
+        h1p = rec_ld(rec_in + tp.hb + 2 * N + tid);
+        h0n = rec_ld(rec_in + tn.hb + tid);
+        h1n = rec_ld(rec_in + tn.hb + N + tid);
         bias0 = st.bias[d.site_base + tid];
         cs0 = st.csite[d.site_base + tid];
     }
@@ -1201,9 +1224,9 @@ __device__ __forceinline__ void block_stage(const DevState &st, const InstDesc &
         store_owned();
     }
     for (int i = tid + nt; i < N; i += nt) {
-        const uint32_t x1p = rec_in[tp.hb + 2 * N + i];
-        const uint32_t x0n = rec_in[tn.hb + i];
-        const uint32_t x1n = rec_in[tn.hb + N + i];
+        const uint32_t x1p = rec_ld(rec_in + tp.hb + 2 * N + i);
+        const uint32_t x0n = rec_ld(rec_in + tn.hb + i);
+        const uint32_t x1n = rec_ld(rec_in + tn.hb + N + i);
         sp32[block_at(a, 1, 0, i, 0) >> 2] = x1p;
         sp32[block_at(a, 1, 0, i, ng + 1) >> 2] = x1n;
         sp32[block_at(a, 0, 0, i, ng + 1) >> 2] = x0n;
@@ -1223,16 +1246,11 @@ __device__ __forceinline__ void block_stage(const DevState &st, const InstDesc &
     for (int k = tid + nt; k < tw; k += nt) t.tbl[k] = tbl_src[k];
 }
 
-// Resident slice blocks: wait until both neighbouring blocks have published `need` sweeps
-// (their boundary records of sweep need - 1 are then complete).  Thread 0 polls with
-// relaxed agent-scope loads and takes one acquire fence once both counts are there (an
-// acquire per poll would invalidate the XCD's L2 at every poll).  The wait is bounded,
-// and a block that gives up sets the error word and carries on, so every wave of the
-// launch always exits (the host then reports the call as failed).
+// Wait until both neighbouring blocks have published `need` sweeps (their boundary records
+// of sweep need - 1 are then complete): thread 0 polls while the workgroup waits at a
+// barrier.  The wait is bounded, and a block that gives up sets the error word and carries
+// on, so every wave of the launch always exits (the host then reports the call as failed).
 constexpr int kWaitPolls = 1 << 18;  // the host may lower it (SweepLaunch::wait_polls)
-// s_waitcnt immediate with the vector-memory count 0 and the export and LDS counts at
-// their maxima (no wait on them): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
-constexpr int kWaitVmcnt0 = 0x0F70;
 __device__ __forceinline__ void block_wait(const DevState &st, int ip, int in, int need,
                                            int max_polls)
 {
@@ -1248,7 +1266,6 @@ __device__ __forceinline__ void block_wait(const DevState &st, int ip, int in, i
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
@@ -1331,8 +1348,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
         block_wait(st, ip, in, sw + L.wait_extra, polls);
         const uint32_t *rin = st.halo + (int64_t)((tsw + sw) & 1) * st.halo_words;
         for (int i = tid; i < N; i += nt) {
-            const uint32_t h1p = rin[hbp + 2 * N + i];
-            const uint32_t h1n = rin[hbn + N + i];
+            const uint32_t h1p = rec_ld(rin + hbp + 2 * N + i);
+            const uint32_t h1n = rec_ld(rin + hbn + N + i);
             sp32[block_at(a, 1, 0, i, 0) >> 2] = h1p;
             sp32[block_at(a, 1, 0, i, ng + 1) >> 2] = h1n;
         }
@@ -1352,8 +1369,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
         if (wait) block_wait(st, ip, in, sw + L.wait_extra, polls);
         const uint32_t *rin = st.halo + (int64_t)((tsw + sw) & 1) * st.halo_words;
         const int i = min(tid, N - 1);
-        hreg_p = rin[hbp + 2 * N + i];
-        hreg_n = rin[hbn + N + i];
+        hreg_p = rec_ld(rin + hbp + 2 * N + i);
+        hreg_n = rec_ld(rin + hbn + N + i);
     };
     auto store_halos = [&]() {
         if (tid < N) {
@@ -1363,21 +1380,20 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
         __syncthreads();
     };
     // resident blocks: the parity-1 boundary groups for the neighbours' next sweep, then
-    // progress.  Every wave waits for its record stores to reach the L2 (vmcnt 0; a
-    // workgroup release does not wait for them), then one agent-scope release by thread 0
-    // (one write-back of the XCD's L2) precedes the progress count.
+    // progress.  Every wave waits for its record stores to complete (vmcnt 0; a workgroup
+    // barrier does not wait for them) before thread 0 stores the progress count.
     auto store_records = [&](int sw) {
         uint32_t *rout = st.halo + (int64_t)((tsw + sw + 1) & 1) * st.halo_words + tile.hb;
         for (int i = tid; i < N; i += nt) {
-            rout[N + i] = sp32[block_at(a, 1, 0, i, 1) >> 2];
-            rout[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
+            rec_st(rout + N + i, sp32[block_at(a, 1, 0, i, 1) >> 2]);
+            rec_st(rout + 2 * N + i, sp32[block_at(a, 1, 0, i, ng) >> 2]);
         }
     };
     auto commit = [&](int sw) {
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
         if (tid == 0)
-            __hip_atomic_store(&st.prog[bt], sw + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st.prog[bt], sw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
     auto publish = [&](int sw) {
         store_records(sw);

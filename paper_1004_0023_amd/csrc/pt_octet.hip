@@ -39,13 +39,43 @@ struct IC {
     static constexpr int value = V;
 };
 
-__device__ __forceinline__ uint32_t ld32(const char *base, uint32_t off)
+// LDS words and halfwords by byte address.  These kernels use dynamic LDS only, which
+// starts at address 0 (each kernel checks this on entry), so a layout offset is an LDS
+// address and a computed address needs no base added (a table address comes straight out
+// of one v_perm).
+typedef __attribute__((address_space(3))) uint32_t LdsU32;
+typedef __attribute__((address_space(3))) uint16_t LdsU16;
+typedef __attribute__((address_space(3))) uint8_t LdsU8;
+__device__ __forceinline__ uint32_t ld32(uint32_t a) { return *(const LdsU32 *)(uintptr_t)a; }
+__device__ __forceinline__ void st32(uint32_t a, uint32_t v) { *(LdsU32 *)(uintptr_t)a = v; }
+__device__ __forceinline__ uint32_t ld16(uint32_t a) { return *(const LdsU16 *)(uintptr_t)a; }
+__device__ __forceinline__ uint32_t ld8(uint32_t a) { return *(const LdsU8 *)(uintptr_t)a; }
+
+// Philox4x32-10 (the sampler's generator) with each round key formed in its round: left to
+// itself the compiler keeps all twenty live in scalar registers across the sweep loops.
+__device__ __forceinline__ Words4 philox10_rk(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1)
 {
-    return *reinterpret_cast<const uint32_t *>(base + off);
-}
-__device__ __forceinline__ void st32(char *base, uint32_t off, uint32_t v)
-{
-    *reinterpret_cast<uint32_t *>(base + off) = v;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        __asm__ volatile("" : "+s"(k0), "+s"(k1));
+        const uint64_t pa = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t pb = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    Words4 o;
+    o.w[0] = c0;
+    o.w[1] = c1;
+    o.w[2] = c2;
+    o.w[3] = c3;
+    return o;
 }
 
 // Byte o of each of the four words of v as one word (byte b from word b); sel = (4 + o) << 8
@@ -115,7 +145,7 @@ struct OctSite {
 // those from SPL * half on; with SPL = 4 the two lanes of an item are neighbours and join
 // their flips with one lane exchange (both must call).
 template <int DT, int SPL>
-__device__ __forceinline__ uint32_t oct_update(const char *lds, uint32_t X, uint32_t Tlo,
+__device__ __forceinline__ uint32_t oct_update(uint32_t X, uint32_t Tlo,
                                                uint32_t Thi, const uint32_t (&Y)[DT],
                                                const uint32_t (&nm)[DT], const OctSite &site,
                                                uint32_t ctr0, uint32_t tt, uint32_t cbase,
@@ -148,11 +178,11 @@ __device__ __forceinline__ uint32_t oct_update(const char *lds, uint32_t X, uint
             // table byte offsets 4 (n + 16 sigma) of the four slices of slot sh + r
             const uint32_t idx = place<0>(n0, r) | place<1>(n1, r) | place<2>(n2, r) |
                                  place<3>(n3, r) | place<4>(s0, r) | place<5>(s1, r);
-            const Words4 u = philox10(ctr0, tt, cbase + (uint32_t)(sh + r), n, key0, key1);
+            const Words4 u = philox10_rk(ctr0, tt, cbase + (uint32_t)(sh + r), n, key0, key1);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const uint32_t addr = __builtin_amdgcn_perm(tbase, idx, 0x0C060500u | (uint32_t)b);
-                const uint32_t thr = ld32(lds, addr + 512u * (uint32_t)r);
+                const uint32_t thr = ld32(addr + 512u * (uint32_t)r);
                 flip |= (u.w[b] <= thr ? 1u : 0u) << (8 * b + r);
             }
         }
@@ -180,8 +210,9 @@ __device__ __forceinline__ void batched(int count, Load &&load, Store &&store)
 }
 
 // LDS layout of an octet work item.  Whole octets: sp holds [p][i][g] words (two parities,
-// G4 groups, N * M bytes).  Slice blocks: own holds [i][gl] words of the parity swept (ng
-// groups), oth [i][x] words of the other parity (ng + 1 groups).  Then the eight slots'
+// G4 groups, N * M bytes).  Phase slice blocks: sp holds [i][gl] words of the parity swept
+// (ng groups), oth [i][x] words of the other parity (ng + 1 groups).  Resident slice
+// blocks: sp and oth hold [i][x] words of parities 0 and 1 (ng + 1 groups each).  Then the eight slots'
 // tables (256-byte aligned, 512 bytes each), the 16-bit neighbour entries, field codes,
 // colour lists and a reduction area of 16 int64.
 struct OctLds {
@@ -191,17 +222,18 @@ struct OctLds {
 __host__ __device__ __forceinline__ uint32_t a16u(uint32_t x) { return (x + 15u) & ~15u; }
 __host__ __device__ __forceinline__ uint32_t a256u(uint32_t x) { return (x + 255u) & ~255u; }
 
-__host__ __device__ __forceinline__ OctLds oct_layout(const InstDesc &d, int ng, bool phase)
+__host__ __device__ __forceinline__ OctLds oct_layout(const InstDesc &d, int ng, int mode)
 {
     OctLds o;
     const uint32_t N = (uint32_t)d.N;
     o.sp = 0;
-    if (phase) {
-        o.oth = a16u(N * (uint32_t)ng * 4u);
-        o.tbl = a256u(o.oth + N * (uint32_t)(ng + 1) * 4u);
-    } else {
+    if (mode == kOctTile) {
         o.oth = 0;
         o.tbl = a256u(2u * N * (uint32_t)d.G4 * 4u);
+    } else {
+        // phase: own rows of ng words; resident: P0 rows of ng + 1 words
+        o.oth = a16u(N * (uint32_t)(mode == kOctPhase ? ng : ng + 1) * 4u);
+        o.tbl = a256u(o.oth + N * (uint32_t)(ng + 1) * 4u);
     }
     o.ent = o.tbl + 8u * 512u;
     o.hinfo = a16u(o.ent + N * (uint32_t)d.D * 2u);
@@ -243,9 +275,9 @@ __device__ __forceinline__ void oct_stage_common(const DevState &st, const InstD
     if (tid < 16) red[tid] = 0;
 }
 
-__device__ __forceinline__ OctSite oct_site(const char *lds, const OctLds &o, int i)
+__device__ __forceinline__ OctSite oct_site(const OctLds &o, int i)
 {
-    const uint32_t hb = reinterpret_cast<const uint8_t *>(lds + o.hinfo)[i];
+    const uint32_t hb = ld8(o.hinfo + (uint32_t)i);
     OctSite s;
     s.hneg = (hb & 1u) ? 0xFFFFFFFFu : 0u;
     s.hzm = (hb & 2u) ? 0xFFFFFFFFu : 0u;
@@ -254,10 +286,10 @@ __device__ __forceinline__ OctSite oct_site(const char *lds, const OctLds &o, in
 }
 
 // Neighbour e of site i: its site index and sign mask (~0 when J < 0).
-__device__ __forceinline__ void oct_entry(const char *lds, const OctLds &o, int idx, uint32_t &j,
+__device__ __forceinline__ void oct_entry(const OctLds &o, int idx, uint32_t &j,
                                           uint32_t &nm)
 {
-    const uint32_t v = reinterpret_cast<const uint16_t *>(lds + o.ent)[idx];
+    const uint32_t v = ld16(o.ent + 2u * (uint32_t)idx);
     j = v & 0x7FFFu;
     nm = (uint32_t)((int32_t)(v << 16) >> 31);
 }
@@ -333,74 +365,107 @@ __device__ __forceinline__ void oct_store(uint32_t *row, int g, int o, uint32_t 
     p[12] = (uint8_t)(v >> 24);
 }
 
+// The degree switch and the slots-per-lane choice around a work item's body.
+template <class Body>
+__device__ __forceinline__ void oct_dispatch(int D, bool split, Body &&body)
+{
+    auto go = [&](auto spl) {
+        switch (D) {
+        case 1: body(IC<1>{}, spl); break;
+        case 2: body(IC<2>{}, spl); break;
+        case 3: body(IC<3>{}, spl); break;
+        case 4: body(IC<4>{}, spl); break;
+        case 5: body(IC<5>{}, spl); break;
+        case 6: body(IC<6>{}, spl); break;
+        case 7: body(IC<7>{}, spl); break;
+        default: body(IC<8>{}, spl); break;
+        }
+    };
+    if (split)
+        go(IC<4>{});
+    else
+        go(IC<8>{});
+}
+
 // ------------------------------------------------------------------ whole octets
 
-template <int DT>
-__device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDesc &d, char *lds,
-                                                const OctLds &o, int n, int c0, int nslots,
-                                                uint64_t t0)
+// All sweeps of a call over a whole octet.  SPL: slots per lane (8, or 4 with two lanes per
+// item when the largest colour class has at most half a workgroup of items).
+template <int DT, int SPL>
+__device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDesc &d, const OctLds &o,
+                                                int n, int c0, int nslots, uint64_t t0)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int N = d.N, G4 = d.G4, lgG4 = 31 - __clz(G4);
+    constexpr int lgL = SPL == 8 ? 0 : 1;  // lanes per item
     const uint32_t plane = (uint32_t)N * (uint32_t)G4 * 4u;
-    const uint16_t *cs = reinterpret_cast<const uint16_t *>(lds + o.csite);
-    const int32_t *co = reinterpret_cast<const int32_t *>(lds + o.coff);
     for (int sw = 0; sw < L.n_sweeps; ++sw) {
         const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
         for (int p = 0; p < 2; ++p) {
             const uint32_t pb = (uint32_t)p * plane, ob = (uint32_t)(p ^ 1) * plane;
             for (int g = 0; g < d.n_colors; ++g) {
-                const int s0 = co[g];
-                const int items = (co[g + 1] - s0) << lgG4;
+                const int s0 = (int)ld32(o.coff + 4u * (uint32_t)g);
+                const int items = ((int)ld32(o.coff + 4u * (uint32_t)(g + 1)) - s0) << (lgG4 + lgL);
                 for (int it = tid; it < items; it += nt) {
-                    const int gg = it & (G4 - 1);
-                    const int i = cs[s0 + (it >> lgG4)];
+                    const int half = it & ((1 << lgL) - 1);
+                    const int gg = (it >> lgL) & (G4 - 1);
+                    const int i = (int)ld16(o.csite + 2u * (uint32_t)(s0 + (it >> (lgG4 + lgL))));
                     const uint32_t rowi = (uint32_t)(i << lgG4) * 4u;
-                    const uint32_t X = ld32(lds, pb + rowi + 4u * (uint32_t)gg);
-                    const uint32_t Wc = ld32(lds, ob + rowi + 4u * (uint32_t)gg);
+                    const uint32_t X = ld32(pb + rowi + 4u * (uint32_t)gg);
+                    const uint32_t Wc = ld32(ob + rowi + 4u * (uint32_t)gg);
                     uint32_t Tlo, Thi;
                     if (p == 0) {
-                        Tlo = __builtin_amdgcn_alignbyte(Wc, ld32(lds, ob + rowi + 4u * (uint32_t)((gg - 1) & (G4 - 1))), 3);
+                        Tlo = __builtin_amdgcn_alignbyte(Wc, ld32(ob + rowi + 4u * (uint32_t)((gg - 1) & (G4 - 1))), 3);
                         Thi = Wc;
                     } else {
                         Tlo = Wc;
-                        Thi = __builtin_amdgcn_alignbyte(ld32(lds, ob + rowi + 4u * (uint32_t)((gg + 1) & (G4 - 1))), Wc, 1);
+                        Thi = __builtin_amdgcn_alignbyte(ld32(ob + rowi + 4u * (uint32_t)((gg + 1) & (G4 - 1))), Wc, 1);
                     }
                     uint32_t Y[DT], nm[DT];
 #pragma unroll
                     for (int e = 0; e < DT; ++e) {
                         uint32_t j;
-                        oct_entry(lds, o, i * DT + e, j, nm[e]);
-                        Y[e] = ld32(lds, pb + ((j << lgG4) + (uint32_t)gg) * 4u);
+                        oct_entry(o, i * DT + e, j, nm[e]);
+                        Y[e] = ld32(pb + ((j << lgG4) + (uint32_t)gg) * 4u);
                     }
-                    const OctSite site = oct_site(lds, o, i);
+                    const OctSite site = oct_site(o, i);
                     const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)gg;
-                    st32(lds, pb + rowi + 4u * (uint32_t)gg,
-                         oct_update<DT, 8>(lds, X, Tlo, Thi, Y, nm, site, ctr0, tt, (uint32_t)c0,
-                                           (uint32_t)n, L.key0, L.key1, nslots, 0));
+                    const uint32_t nx = oct_update<DT, SPL>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
+                                                            (uint32_t)c0, (uint32_t)n, L.key0,
+                                                            L.key1, nslots, half);
+                    if (half == 0) st32(pb + rowi + 4u * (uint32_t)gg, nx);
                 }
                 __syncthreads();
             }
         }
     }
-    // E_cl and C of the eight slots
+}
+
+// E_cl and C of the octet's slots from its final spins, into the LDS reduction area.
+template <int DT>
+__device__ __forceinline__ void oct_tile_energy(const OctLaunch &L, const InstDesc &d, char *lds,
+                                                const OctLds &o)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int N = d.N, G4 = d.G4, lgG4 = 31 - __clz(G4);
+    const uint32_t plane = (uint32_t)N * (uint32_t)G4 * 4u;
     int e2[8], cc[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) e2[r] = cc[r] = 0;
     for (int it = tid; it < (N << lgG4); it += nt) {
         const int gg = it & (G4 - 1), i = it >> lgG4;
         const uint32_t rowi = (uint32_t)(i << lgG4) * 4u;
-        const uint32_t X0 = ld32(lds, rowi + 4u * (uint32_t)gg);
-        const uint32_t X1 = ld32(lds, plane + rowi + 4u * (uint32_t)gg);
-        const uint32_t X0n = ld32(lds, rowi + 4u * (uint32_t)((gg + 1) & (G4 - 1)));
+        const uint32_t X0 = ld32(rowi + 4u * (uint32_t)gg);
+        const uint32_t X1 = ld32(plane + rowi + 4u * (uint32_t)gg);
+        const uint32_t X0n = ld32(rowi + 4u * (uint32_t)((gg + 1) & (G4 - 1)));
         uint32_t Y0[DT], Y1[DT], nm[DT];
 #pragma unroll
         for (int e = 0; e < DT; ++e) {
             uint32_t j;
-            oct_entry(lds, o, i * DT + e, j, nm[e]);
+            oct_entry(o, i * DT + e, j, nm[e]);
             const uint32_t a = ((j << lgG4) + (uint32_t)gg) * 4u;
-            Y0[e] = ld32(lds, a);
-            Y1[e] = ld32(lds, plane + a);
+            Y0[e] = ld32(a);
+            Y1[e] = ld32(plane + a);
         }
         const int h = L.st.hfield[d.site_base + i];
         oct_energy_item<DT>(X0, X1, X0n, Y0, Y1, nm, h, e2, cc);
@@ -412,10 +477,14 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 {
     extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
+    if ((uint32_t)(uintptr_t)lds != 0u) {  // the addressing below assumes LDS address 0
+        if (threadIdx.x == 0) atomicOr(st.err, kErrLdsBase);
+        return;
+    }
     const int32_t *rec = st.otiles + (int64_t)(L.tile0 + blockIdx.x) * kOctRec;
     const int n = rec[0], w = rec[1], oct = rec[2];
     const InstDesc d = st.inst[n];
-    const OctLds o = oct_layout(d, d.G4, false);
+    const OctLds o = oct_layout(d, d.G4, kOctTile);
     const int tid = threadIdx.x, nt = blockDim.x;
     const int N = d.N, G4 = d.G4, lgG4 = 31 - __clz(G4);
     const int c0 = 32 * w + 8 * oct;
@@ -429,19 +498,28 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                 const int p = pi >= N ? 1 : 0, i = pi - p * N;
                 return oct_load(oct_row(st, d, w, p, i), g, sel);
             },
-            [&](int k, uint32_t v) { st32(lds, 4u * (uint32_t)k, v); });
+            [&](int k, uint32_t v) { st32(4u * (uint32_t)k, v); });
     oct_stage_common(st, d, lds, o, c0, nslots);
     const uint64_t t0 = st.ctr[n].t;
     __syncthreads();
+    // two lanes per item when every colour class fits half the workgroup
+    int most = 0;
+    for (int g = 0; g < d.n_colors; ++g)
+        most = max(most, (int)(ld32(o.coff + 4u * (uint32_t)(g + 1)) - ld32(o.coff + 4u * (uint32_t)g)));
+    const bool split = (2 * most) << lgG4 <= nt;
+    oct_dispatch(d.D, split, [&](auto dt, auto spl) {
+        constexpr int DT = decltype(dt)::value, SPL = decltype(spl)::value;
+        oct_tile_sweeps<DT, SPL>(L, d, o, n, c0, nslots, t0);
+    });
     switch (d.D) {
-    case 1: oct_tile_sweeps<1>(L, d, lds, o, n, c0, nslots, t0); break;
-    case 2: oct_tile_sweeps<2>(L, d, lds, o, n, c0, nslots, t0); break;
-    case 3: oct_tile_sweeps<3>(L, d, lds, o, n, c0, nslots, t0); break;
-    case 4: oct_tile_sweeps<4>(L, d, lds, o, n, c0, nslots, t0); break;
-    case 5: oct_tile_sweeps<5>(L, d, lds, o, n, c0, nslots, t0); break;
-    case 6: oct_tile_sweeps<6>(L, d, lds, o, n, c0, nslots, t0); break;
-    case 7: oct_tile_sweeps<7>(L, d, lds, o, n, c0, nslots, t0); break;
-    default: oct_tile_sweeps<8>(L, d, lds, o, n, c0, nslots, t0); break;
+    case 1: oct_tile_energy<1>(L, d, lds, o); break;
+    case 2: oct_tile_energy<2>(L, d, lds, o); break;
+    case 3: oct_tile_energy<3>(L, d, lds, o); break;
+    case 4: oct_tile_energy<4>(L, d, lds, o); break;
+    case 5: oct_tile_energy<5>(L, d, lds, o); break;
+    case 6: oct_tile_energy<6>(L, d, lds, o); break;
+    case 7: oct_tile_energy<7>(L, d, lds, o); break;
+    default: oct_tile_energy<8>(L, d, lds, o); break;
     }
     __syncthreads();
     const int64_t *red = reinterpret_cast<const int64_t *>(lds + o.red);
@@ -453,36 +531,40 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     for (int k = tid; k < words; k += nt) {
         const int g = k & (G4 - 1), pi = k >> lgG4;
         const int p = pi >= N ? 1 : 0, i = pi - p * N;
-        oct_store(oct_row(st, d, w, p, i), g, oct, ld32(lds, 4u * (uint32_t)k));
+        oct_store(oct_row(st, d, w, p, i), g, oct, ld32(4u * (uint32_t)k));
     }
 }
 
 // ------------------------------------------------------------------ slice blocks
 
-// SPL: slots per lane (8, or 4 with two lanes per item, for blocks with few items per
-// colour class)
+// A slice block's words of the parity swept ("own") and of the other parity ("oth") in LDS:
+// word (site i, local group x) at base + i * stride + 4 x.  own's x = 0 is the block's first
+// group g0; oth's x = 0 is group g0 - 1 when parity 0 is swept and g0 when parity 1 is.
+struct OctPlanes {
+    uint32_t own, own_stride, oth, oth_stride;
+};
+
+// Every colour class of parity p over the block's ng groups.  SPL: slots per lane (8, or 4
+// with two lanes per item, for blocks with few items per colour class).
 template <int DT, int SPL>
-__device__ __forceinline__ void oct_phase_body(const OctLaunch &L, const InstDesc &d, char *lds,
-                                               const OctLds &o, int n, int c0, int nslots, int g0,
-                                               int ng, uint32_t tt)
+__device__ __forceinline__ void oct_block_sweep(const OctLaunch &L, const InstDesc &d, const OctLds &o,
+                                                const OctPlanes &pl, int p, int n, int c0,
+                                                int nslots, int g0, int ng, uint32_t tt)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int p = L.p, G4 = d.G4, lgng = 31 - __clz(ng);
+    const int G4 = d.G4, lgng = 31 - __clz(ng);
     constexpr int lgL = SPL == 8 ? 0 : 1;  // lanes per item
-    const uint32_t orow = (uint32_t)(ng + 1) * 4u, rowb = (uint32_t)ng * 4u;
-    const uint16_t *cs = reinterpret_cast<const uint16_t *>(lds + o.csite);
-    const int32_t *co = reinterpret_cast<const int32_t *>(lds + o.coff);
     for (int g = 0; g < d.n_colors; ++g) {
-        const int s0 = co[g];
-        const int items = (co[g + 1] - s0) << (lgng + lgL);
+        const int s0 = (int)ld32(o.coff + 4u * (uint32_t)g);
+        const int items = ((int)ld32(o.coff + 4u * (uint32_t)(g + 1)) - s0) << (lgng + lgL);
         for (int it = tid; it < items; it += nt) {
             const int half = it & ((1 << lgL) - 1);
-            const int gl = (it >> lgL) & (ng - 1);
-            const int i = cs[s0 + (it >> (lgng + lgL))];
-            const uint32_t own = (uint32_t)i * rowb + 4u * (uint32_t)gl;
-            const uint32_t oth = o.oth + (uint32_t)i * orow + 4u * (uint32_t)gl;
-            const uint32_t X = ld32(lds, own);
-            const uint32_t W0 = ld32(lds, oth), W1 = ld32(lds, oth + 4u);
+            const uint32_t gl4 = 4u * (uint32_t)((it >> lgL) & (ng - 1));
+            const int i = (int)ld16(o.csite + 2u * (uint32_t)(s0 + (it >> (lgng + lgL))));
+            const uint32_t own = pl.own + (uint32_t)i * pl.own_stride + gl4;
+            const uint32_t oth = pl.oth + (uint32_t)i * pl.oth_stride + gl4;
+            const uint32_t X = ld32(own);
+            const uint32_t W0 = ld32(oth), W1 = ld32(oth + 4u);
             uint32_t Tlo, Thi;
             if (p == 0) {
                 Tlo = __builtin_amdgcn_alignbyte(W1, W0, 3);
@@ -495,36 +577,44 @@ __device__ __forceinline__ void oct_phase_body(const OctLaunch &L, const InstDes
 #pragma unroll
             for (int e = 0; e < DT; ++e) {
                 uint32_t j;
-                oct_entry(lds, o, i * DT + e, j, nm[e]);
-                Y[e] = ld32(lds, j * rowb + 4u * (uint32_t)gl);
+                oct_entry(o, i * DT + e, j, nm[e]);
+                Y[e] = ld32(pl.own + j * pl.own_stride + gl4);
             }
-            const OctSite site = oct_site(lds, o, i);
-            const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)(g0 + gl);
-            const uint32_t nx = oct_update<DT, SPL>(lds, X, Tlo, Thi, Y, nm, site, ctr0, tt,
+            const OctSite site = oct_site(o, i);
+            const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)g0 + (gl4 >> 2);
+            const uint32_t nx = oct_update<DT, SPL>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
                                                     (uint32_t)c0, (uint32_t)n, L.key0, L.key1,
                                                     nslots, half);
-            if (half == 0) st32(lds, own, nx);
+            if (half == 0) st32(own, nx);
         }
         __syncthreads();
     }
-    if (!(L.last && p == 1)) return;
-    // the block's part of E_cl and C: own holds parity 1 (final), oth parity 0 of groups
-    // g0 .. g0 + ng (final)
+}
+
+// The block's part of E_cl and C into its LDS reduction area, from the final spins: p1
+// holds parity 1 of the block's groups (as own), p0 parity 0 of groups g0 .. g0 + ng (as
+// oth of a parity-1 sweep).
+template <int DT>
+__device__ __forceinline__ void oct_block_energy(const OctLaunch &L, const InstDesc &d, char *lds,
+                                                 const OctLds &o, const OctPlanes &p1, int ng)
+{
+    const int tid = threadIdx.x, nt = blockDim.x, lgng = 31 - __clz(ng);
     int e2[8], cc[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) e2[r] = cc[r] = 0;
     for (int it = tid; it < (d.N << lgng); it += nt) {
-        const int gl = it & (ng - 1), i = it >> lgng;
-        const uint32_t X1 = ld32(lds, (uint32_t)i * rowb + 4u * (uint32_t)gl);
-        const uint32_t oth = o.oth + (uint32_t)i * orow + 4u * (uint32_t)gl;
-        const uint32_t X0 = ld32(lds, oth), X0n = ld32(lds, oth + 4u);
+        const uint32_t gl4 = 4u * (uint32_t)(it & (ng - 1));
+        const int i = it >> lgng;
+        const uint32_t X1 = ld32(p1.own + (uint32_t)i * p1.own_stride + gl4);
+        const uint32_t oth = p1.oth + (uint32_t)i * p1.oth_stride + gl4;
+        const uint32_t X0 = ld32(oth), X0n = ld32(oth + 4u);
         uint32_t Y0[DT], Y1[DT], nm[DT];
 #pragma unroll
         for (int e = 0; e < DT; ++e) {
             uint32_t j;
-            oct_entry(lds, o, i * DT + e, j, nm[e]);
-            Y0[e] = ld32(lds, o.oth + j * orow + 4u * (uint32_t)gl);
-            Y1[e] = ld32(lds, j * rowb + 4u * (uint32_t)gl);
+            oct_entry(o, i * DT + e, j, nm[e]);
+            Y0[e] = ld32(p1.oth + j * p1.oth_stride + gl4);
+            Y1[e] = ld32(p1.own + j * p1.own_stride + gl4);
         }
         const int h = L.st.hfield[d.site_base + i];
         oct_energy_item<DT>(X0, X1, X0n, Y0, Y1, nm, h, e2, cc);
@@ -532,82 +622,236 @@ __device__ __forceinline__ void oct_phase_body(const OctLaunch &L, const InstDes
     oct_reduce(lds, o, e2, cc);
 }
 
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) oct_phase_kernel(OctLaunch L)
+// The block's reduced part of 2 E_cl and C added to the replicas' E_cl and C (cleared before
+// the call).  Every block's part of 2 E_cl is even (its bonds come in pairs i-j, j-i and the
+// field term is 2 h s), so the halves add up exactly.
+__device__ __forceinline__ void oct_block_energy_out(const DevState &st, const InstDesc &d,
+                                                     const char *lds, const OctLds &o, int c0,
+                                                     int nslots)
 {
-    extern __shared__ __align__(16) char lds[];
-    const DevState &st = L.st;
-    const int32_t *rec = st.otiles + (int64_t)(L.tile0 + blockIdx.x) * kOctRec;
-    const int n = rec[0], w = rec[1], oct = rec[2], g0 = rec[3], ng = rec[4];
-    const InstDesc d = st.inst[n];
-    const OctLds o = oct_layout(d, ng, true);
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int N = d.N, G4 = d.G4, p = L.p, lgng = 31 - __clz(ng);
-    const int c0 = 32 * w + 8 * oct;
-    const int nslots = min(8, d.R - c0);
-    const uint32_t sel = ((uint32_t)(4 + oct) << 8) | (uint32_t)oct | 0x0C0C0000u;
-    // own: parity p, groups g0 .. g0 + ng - 1; oth: parity 1 - p, groups from g0 - 1 (p = 0)
-    // or g0 (p = 1), ng + 1 of them, cyclically
-    batched(N << lgng,
-            [&](int k) {
-                const int gl = k & (ng - 1), i = k >> lgng;
-                return oct_load(oct_row(st, d, w, p, i), g0 + gl, sel);
-            },
-            [&](int k, uint32_t v) { st32(lds, 4u * (uint32_t)k, v); });
-    const int gb = p == 0 ? g0 - 1 : g0;
-    // the other parity's ng + 1 groups, x-major so that neighbouring threads read
-    // neighbouring rows: LDS word i (ng + 1) + x
-    batched(N * (ng + 1),
-            [&](int k) {
-                const int x = k / N, i = k - x * N;
-                return oct_load(oct_row(st, d, w, p ^ 1, i), (gb + x + G4) & (G4 - 1), sel);
-            },
-            [&](int k, uint32_t v) {
-                const int x = k / N, i = k - x * N;
-                st32(lds, o.oth + 4u * (uint32_t)(i * (ng + 1) + x), v);
-            });
-    oct_stage_common(st, d, lds, o, c0, nslots);
-    const uint32_t tt = (uint32_t)(st.ctr[n].t + (uint64_t)L.sweep_off);
-    __syncthreads();
-    auto body = [&](auto spl) {
-        constexpr int SPL = decltype(spl)::value;
-        switch (d.D) {
-        case 1: oct_phase_body<1, SPL>(L, d, lds, o, n, c0, nslots, g0, ng, tt); break;
-        case 2: oct_phase_body<2, SPL>(L, d, lds, o, n, c0, nslots, g0, ng, tt); break;
-        case 3: oct_phase_body<3, SPL>(L, d, lds, o, n, c0, nslots, g0, ng, tt); break;
-        case 4: oct_phase_body<4, SPL>(L, d, lds, o, n, c0, nslots, g0, ng, tt); break;
-        case 5: oct_phase_body<5, SPL>(L, d, lds, o, n, c0, nslots, g0, ng, tt); break;
-        case 6: oct_phase_body<6, SPL>(L, d, lds, o, n, c0, nslots, g0, ng, tt); break;
-        case 7: oct_phase_body<7, SPL>(L, d, lds, o, n, c0, nslots, g0, ng, tt); break;
-        default: oct_phase_body<8, SPL>(L, d, lds, o, n, c0, nslots, g0, ng, tt); break;
-        }
-    };
-    if (L.split)
-        body(IC<4>{});
-    else
-        body(IC<8>{});
-    __syncthreads();
-    if (L.last && p == 1 && tid < nslots) {
+    const int tid = threadIdx.x;
+    if (tid < nslots) {
         const int64_t *red = reinterpret_cast<const int64_t *>(lds + o.red);
-        // halves of 2 E_cl: every block's sum is even (its bonds come in pairs i-j, j-i
-        // and the field term is 2 h s), so the halves add up exactly
         atomicAdd(reinterpret_cast<unsigned long long *>(&st.E[d.rep_base + c0 + tid]),
                   (unsigned long long)(red[tid] / 2));
         atomicAdd(reinterpret_cast<unsigned long long *>(&st.C[d.rep_base + c0 + tid]),
                   (unsigned long long)red[8 + tid]);
     }
+}
+
+// ng1 consecutive groups of parity p from group gb on (cyclically) into LDS rows of ng1
+// words at base, x-major so that neighbouring threads read neighbouring rows.
+__device__ __forceinline__ void oct_stage_rows(const DevState &st, const InstDesc &d, int w, int p,
+                                               int gb, int ng1, uint32_t base, uint32_t sel)
+{
+    const int N = d.N, G4 = d.G4;
+    batched(N * ng1,
+            [&](int k) {
+                const int x = k / N, i = k - x * N;
+                return oct_load(oct_row(st, d, w, p, i), (gb + x + G4) & (G4 - 1), sel);
+            },
+            [&](int k, uint32_t v) {
+                const int x = k / N, i = k - x * N;
+                st32(base + 4u * (uint32_t)(i * ng1 + x), v);
+            });
+}
+
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) oct_phase_kernel(OctLaunch L)
+{
+    extern __shared__ __align__(16) char lds[];
+    const DevState &st = L.st;
+    if ((uint32_t)(uintptr_t)lds != 0u) {  // the addressing below assumes LDS address 0
+        if (threadIdx.x == 0) atomicOr(st.err, kErrLdsBase);
+        return;
+    }
+    const int32_t *rec = st.otiles + (int64_t)(L.tile0 + blockIdx.x) * kOctRec;
+    const int n = rec[0], w = rec[1], oct = rec[2], g0 = rec[3], ng = rec[4];
+    const InstDesc d = st.inst[n];
+    const OctLds o = oct_layout(d, ng, kOctPhase);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int N = d.N, p = L.p, lgng = 31 - __clz(ng);
+    const int c0 = 32 * w + 8 * oct;
+    const int nslots = min(8, d.R - c0);
+    const uint32_t sel = ((uint32_t)(4 + oct) << 8) | (uint32_t)oct | 0x0C0C0000u;
+    // own: parity p, groups g0 .. g0 + ng - 1; oth: parity 1 - p, ng + 1 groups from g0 - 1
+    // (p = 0) or g0 (p = 1)
+    batched(N << lgng,
+            [&](int k) {
+                const int gl = k & (ng - 1), i = k >> lgng;
+                return oct_load(oct_row(st, d, w, p, i), g0 + gl, sel);
+            },
+            [&](int k, uint32_t v) { st32(o.sp + 4u * (uint32_t)k, v); });
+    oct_stage_rows(st, d, w, p ^ 1, p == 0 ? g0 - 1 : g0, ng + 1, o.oth, sel);
+    oct_stage_common(st, d, lds, o, c0, nslots);
+    const uint32_t tt = (uint32_t)(st.ctr[n].t + (uint64_t)L.sweep_off);
+    __syncthreads();
+    const OctPlanes pl = {o.sp, 4u * (uint32_t)ng, o.oth, 4u * (uint32_t)(ng + 1)};
+    const bool energy = L.last && p == 1;
+    oct_dispatch(d.D, L.split != 0, [&](auto dt, auto spl) {
+        constexpr int DT = decltype(dt)::value, SPL = decltype(spl)::value;
+        oct_block_sweep<DT, SPL>(L, d, o, pl, p, n, c0, nslots, g0, ng, tt);
+        if (energy) oct_block_energy<DT>(L, d, lds, o, pl, ng);
+    });
+    __syncthreads();
+    if (energy) oct_block_energy_out(st, d, lds, o, c0, nslots);
     for (int k = tid; k < (N << lgng); k += nt) {
         const int gl = k & (ng - 1), i = k >> lgng;
-        oct_store(oct_row(st, d, w, p, i), g0 + gl, oct, ld32(lds, 4u * (uint32_t)k));
+        oct_store(oct_row(st, d, w, p, i), g0 + gl, oct, ld32(o.sp + 4u * (uint32_t)k));
     }
 }
 
+// ------------------------------------------------------------------ resident slice blocks
+
+// Boundary records and progress counts pass between workgroups on different XCDs, whose
+// L2 caches are not coherent with one another.  They are read and written only with
+// agent-scope atomic operations, which the hardware performs coherently for the whole
+// device, so no L2 write-back or invalidation is needed: a block's waves each wait for
+// their record stores to complete before the barrier that precedes the count's store, and
+// a reader issues its record loads only after it has seen the count.  (Publishing through
+// an agent-scope release and acquire instead, which write the whole XCD's L2 back and
+// invalidate it, made config 4's sweeps 1.4x slower.)
+constexpr int kOctWaitPolls = 1 << 18;
+// s_waitcnt immediate with the vector-memory count 0 and the export and LDS counts at
+// their maxima (no wait on them): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+__device__ __forceinline__ uint32_t rec_ld(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void rec_st(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 polls *flag until it reaches need while the workgroup waits at a barrier.  The
+// wait is bounded: a block that gives up sets the error word and carries on, so every wave
+// always exits (the host then reports the call as failed); once any block has given up,
+// the others stop waiting too.
+__device__ __forceinline__ void oct_wait(const DevState &st, const int32_t *flag, int need,
+                                         int max_polls)
+{
+    if (threadIdx.x == 0) {
+        int polls = 0;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (++polls > max_polls ||
+                __hip_atomic_load(st.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                atomicOr(st.err, kErrWait);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+}
+
+// After the workgroup's record stores: every wave waits for its own stores to complete
+// (a workgroup barrier does not wait for them), then thread 0 stores v.
+__device__ __forceinline__ void oct_publish(int32_t *flag, int v)
+{
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// All sweeps of a call over one octet slice block, with every block of the launch resident.
+// LDS keeps P0 = parity 0 of groups g0 .. g0 + ng and P1 = parity 1 of groups g0 - 1 ..
+// g0 + ng - 1 (rows of ng + 1 words); the first group of P0 and of P1 are halos owned by
+// the neighbouring blocks of the octet's ring of blocks (prev ends at g0 - 1, next starts at
+// g0 + ng).  Per sweep:
+//   1. (after the first sweep) wait for prev's parity-1 progress of the previous sweep and
+//      take its last parity-1 group as P1's halo;
+//   2. parity 0 over the own groups;
+//   3. publish the first own parity-0 group (record R0) and the parity-0 progress;
+//   4. wait for next's parity-0 progress of this sweep and take its first parity-0 group
+//      as P0's halo;
+//   5. parity 1 over the own groups;
+//   6. (before another sweep) publish the last own parity-1 group (record R1) and the
+//      parity-1 progress.
+// One record buffer of each kind suffices: a block rewrites R0 in step 3 of sweep s + 1
+// only after step 1 has seen prev finish sweep s (whose step 4 read R0), and R1 in step 6 of
+// sweep s + 1 only after step 4 has seen next reach step 3 of sweep s + 1 (after its step 1
+// read R1).  Progress counts are per call (zeroed by oct_clear).  After the last sweep the
+// block adds its part of E_cl and C and writes its own groups back.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) oct_resident_kernel(OctLaunch L)
+{
+    extern __shared__ __align__(16) char lds[];
+    const DevState &st = L.st;
+    if ((uint32_t)(uintptr_t)lds != 0u) {  // the addressing below assumes LDS address 0
+        if (threadIdx.x == 0) atomicOr(st.err, kErrLdsBase);
+        return;
+    }
+    const int b = L.tile0 + (int)blockIdx.x;
+    const int32_t *rec = st.otiles + (int64_t)b * kOctRec;
+    const int n = rec[0], w = rec[1], oct = rec[2], g0 = rec[3], ng = rec[4];
+    const int roff = rec[5], prev = rec[6], next = rec[7];
+    const int roff_prev = st.otiles[(int64_t)prev * kOctRec + 5];
+    const int roff_next = st.otiles[(int64_t)next * kOctRec + 5];
+    const InstDesc d = st.inst[n];
+    const OctLds o = oct_layout(d, ng, kOctResident);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int N = d.N, lgng = 31 - __clz(ng);
+    const int c0 = 32 * w + 8 * oct;
+    const int nslots = min(8, d.R - c0);
+    const uint32_t sel = ((uint32_t)(4 + oct) << 8) | (uint32_t)oct | 0x0C0C0000u;
+    const uint32_t RS = 4u * (uint32_t)(ng + 1), P0 = o.sp, P1 = o.oth;
+    oct_stage_rows(st, d, w, 0, g0, ng + 1, P0, sel);
+    oct_stage_rows(st, d, w, 1, g0 - 1, ng + 1, P1, sel);
+    oct_stage_common(st, d, lds, o, c0, nslots);
+    const uint64_t t0 = st.ctr[n].t;
+    __syncthreads();
+    uint32_t *R0 = st.orec + roff;                   // records: R0 region, then R1 region
+    uint32_t *R1 = st.orec + L.rec_words + roff;
+    const uint32_t *R1prev = st.orec + L.rec_words + roff_prev;
+    const uint32_t *R0next = st.orec + roff_next;
+    int32_t *prog = st.oprog;                        // [2 * work item + parity]
+    const int polls = L.wait_polls > 0 ? L.wait_polls : kOctWaitPolls;
+    const OctPlanes pl0 = {P0, RS, P1, RS}, pl1 = {P1 + 4u, RS, P0, RS};
+    const uint32_t halo1 = P1, halo0 = P0 + 4u * (uint32_t)ng;  // x = 0 of P1, x = ng of P0
+    oct_dispatch(d.D, L.split != 0, [&](auto dt, auto spl) {
+        constexpr int DT = decltype(dt)::value, SPL = decltype(spl)::value;
+        for (int sw = 0; sw < L.n_sweeps; ++sw) {
+            const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
+            if (sw > 0) {
+                oct_wait(st, prog + 2 * prev + 1, sw + L.wait_extra, polls);
+                for (int i = tid; i < N; i += nt) st32(halo1 + (uint32_t)i * RS, rec_ld(R1prev + i));
+                __syncthreads();
+            }
+            oct_block_sweep<DT, SPL>(L, d, o, pl0, 0, n, c0, nslots, g0, ng, tt);
+            for (int i = tid; i < N; i += nt) rec_st(R0 + i, ld32(P0 + (uint32_t)i * RS));
+            oct_publish(prog + 2 * b, sw + 1);
+            oct_wait(st, prog + 2 * next, sw + 1 + L.wait_extra, polls);
+            for (int i = tid; i < N; i += nt) st32(halo0 + (uint32_t)i * RS, rec_ld(R0next + i));
+            __syncthreads();
+            oct_block_sweep<DT, SPL>(L, d, o, pl1, 1, n, c0, nslots, g0, ng, tt);
+            if (sw + 1 < L.n_sweeps) {
+                for (int i = tid; i < N; i += nt)
+                    rec_st(R1 + i, ld32(P1 + (uint32_t)i * RS + 4u * (uint32_t)ng));
+                oct_publish(prog + 2 * b + 1, sw + 1);
+            }
+        }
+        oct_block_energy<DT>(L, d, lds, o, pl1, ng);
+    });
+    __syncthreads();
+    oct_block_energy_out(st, d, lds, o, c0, nslots);
+    for (int k = tid; k < (N << lgng); k += nt) {
+        const int x = k & (ng - 1), i = k >> lgng;
+        oct_store(oct_row(st, d, w, 0, i), g0 + x, oct, ld32(P0 + (uint32_t)i * RS + 4u * (uint32_t)x));
+        oct_store(oct_row(st, d, w, 1, i), g0 + x, oct, ld32(P1 + (uint32_t)i * RS + 4u * (uint32_t)(x + 1)));
+    }
+}
+
+// E_cl and C of the slice-block octets set to zero (the block at group 0 clears its
+// octet's), and every block's progress counts.
 __global__ void oct_clear_kernel(OctLaunch L)
 {
-    const int32_t *rec = L.st.otiles + (int64_t)(L.tile0 + blockIdx.x) * kOctRec;
-    if (rec[3] != 0) return;  // the block at group 0 clears its octet
+    const int b = L.tile0 + (int)blockIdx.x;
+    const int32_t *rec = L.st.otiles + (int64_t)b * kOctRec;
+    const int r = threadIdx.x;
+    if (r < 2) L.st.oprog[2 * b + r] = 0;
+    if (rec[3] != 0) return;
     const InstDesc d = L.st.inst[rec[0]];
     const int c0 = 32 * rec[1] + 8 * rec[2];
-    const int r = threadIdx.x;
     if (r < 8 && c0 + r < d.R) {
         L.st.E[d.rep_base + c0 + r] = 0;
         L.st.C[d.rep_base + c0 + r] = 0;
@@ -616,12 +860,12 @@ __global__ void oct_clear_kernel(OctLaunch L)
 
 }  // namespace
 
-int32_t oct_lds_bytes(const InstDesc &d, int32_t ng, bool phase)
+int32_t oct_lds_bytes(const InstDesc &d, int32_t ng, int mode)
 {
-    return (int32_t)oct_layout(d, ng, phase).end;
+    return (int32_t)oct_layout(d, ng, mode).end;
 }
 
-hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes)
+hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes, int32_t resident_bytes)
 {
     hipError_t e = hipSuccess;
     if (tile_bytes > 0)
@@ -630,7 +874,26 @@ hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes)
     if (e == hipSuccess && phase_bytes > 0)
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_phase_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, phase_bytes);
+    if (e == hipSuccess && resident_bytes > 0)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_resident_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, resident_bytes);
     return e;
+}
+
+hipError_t oct_resident_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu)
+{
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void *>(&oct_resident_kernel), threads, (size_t)lds_bytes);
+    *per_cu = n;
+    return e;
+}
+
+hipError_t launch_oct_resident(const OctLaunch &L, hipStream_t s)
+{
+    if (L.n_tiles <= 0 || L.n_sweeps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(oct_resident_kernel, dim3(L.n_tiles), dim3(L.threads), L.lds_bytes, s, L);
+    return hipGetLastError();
 }
 
 hipError_t launch_oct_tiles(const OctLaunch &L, hipStream_t s)

@@ -80,7 +80,7 @@ class _Info(C.Structure):
                 ("class_launches", C.c_int32), ("multi_launches", C.c_int64),
                 ("multi_cycles", C.c_int64), ("multi_ms", C.c_double),
                 ("oct_tiles", C.c_int32), ("oct_blocks", C.c_int32),
-                ("oct_tile_launches", C.c_int32)]
+                ("oct_tile_launches", C.c_int32), ("oct_resident", C.c_int32)]
 
 
 _lib = None

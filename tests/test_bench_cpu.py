@@ -35,16 +35,18 @@ def test_traffic_record_follows_the_kernel_source(tmp_path, monkeypatch):
     import hashlib
     rec.write_text(json.dumps({"source_sha256": hashlib.sha256(b"kernel v1").hexdigest(),
                                "hbm_bytes_per_launch": 123.0}))
-    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(rec))
-    monkeypatch.setattr(bench, "SWEEP_SOURCE", str(src))
-    assert bench.traffic_per_launch() == 123.0
+    monkeypatch.setattr(bench, "TRAFFIC_RECORDS", {("k", 3): (str(rec), str(src))})
+    assert bench.traffic_per_launch("k", 3) == 123.0
+    assert bench.traffic_per_launch("k", 4) is None
     src.write_bytes(b"kernel v2")
-    assert bench.traffic_per_launch() is None
+    assert bench.traffic_per_launch("k", 3) is None
 
 
-def test_committed_traffic_record_matches_the_source():
-    """The committed HBM-traffic record was measured on the kernel source as it stands."""
-    assert bench.traffic_per_launch() is not None
+@pytest.mark.parametrize("kernel", ["sweep_fast_kernel", "oct_tile_kernel"])
+def test_committed_traffic_record_matches_the_source(kernel):
+    """The committed HBM-traffic records of the config-3 kernels were measured on the
+    kernel sources as they stand."""
+    assert bench.traffic_per_launch(kernel, 3) is not None
 
 
 def test_cpu_baseline_report():

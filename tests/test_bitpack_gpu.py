@@ -131,20 +131,43 @@ def test_config1_run(ptqmc):
         assert_same(s, 0, ref, "config1")
 
 
-def test_config4_lattice_one_cycle(ptqmc):
+@pytest.mark.parametrize("per_sweep", [False, True])
+def test_config4_lattice_one_cycle(ptqmc, per_sweep):
     """The 8x8x16 lattice with its 64 replicas in two words per spin position: one cycle
-    of 10 sweeps and an exchange against the oracle."""
+    of 10 sweeps and an exchange against the oracle, with the octet slice blocks resident
+    for the call and launched per parity of every sweep."""
     inst = W.config4()
     seed = W.sampler_seed(4)
-    say("case: bit-packed config 4, 1 cycle of 10 sweeps")
-    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, encoding=ptqmc.PT_BITPACK32) as s:
+    flags = ptqmc.PT_FLAG_BLOCK_LAUNCH_PER_SWEEP if per_sweep else 0
+    say(f"case: bit-packed config 4, 1 cycle of 10 sweeps, per_sweep={per_sweep}")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, encoding=ptqmc.PT_BITPACK32,
+                       flags=flags) as s:
         s.run(1)
         info = s.info()
         # octet slice blocks (a whole octet, N * M bytes, exceeds half a unit's LDS)
         assert info["oct_blocks"] > 0 and info["oct_tiles"] == 0 and info["class_launches"] == 0
+        assert info["oct_resident"] == (0 if per_sweep else 1)
         ref = oracle.OracleChain(inst, seed)
         ref.run(10, 1)
         assert_same(s, 0, ref, "config4")
+
+
+def test_octet_resident_wait_timeout_is_reported(ptqmc):
+    """Resident octet slice blocks bound their neighbour waits.  Forced from the host
+    (every block waits for a progress count no block publishes, under a poll bound of 16),
+    each wait gives up, every workgroup still exits, and the next synchronising call
+    returns PT_ESTATE once; the error word is then clear."""
+    inst = W.config4()
+    say("case: resident octet slice blocks, forced wait timeout (config 4, 10 sweeps)")
+    with ptqmc.Sampler([inst], 7, sweeps_per_exchange=10, encoding=ptqmc.PT_BITPACK32,
+                       flags=ptqmc.PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT | ptqmc.PT_FLAG_NO_GRAPH) as s:
+        assert s.info()["oct_resident"] == 1
+        s.run(1)
+        with pytest.raises(ptqmc.PTError) as err:
+            s.sync()
+        assert err.value.code == ptqmc.PT_ESTATE
+        assert "waited too long" in str(err.value)
+        s.sync()  # reported once, then clear
 
 
 def octet_batch():
@@ -166,24 +189,30 @@ def octet_batch():
     ]
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_octet_kernels_match_oracle(ptqmc, graph):
-    """Whole octets resident for a call, octet slice blocks launched per parity, and the
-    per-class kernel for the rest, in one batch, against the oracle."""
+@pytest.mark.parametrize("graph,per_sweep", [(False, False), (True, False), (True, True)])
+def test_octet_kernels_match_oracle(ptqmc, graph, per_sweep):
+    """Whole octets resident for a call, octet slice blocks (resident for the call, or
+    launched per parity of every sweep) and the per-class kernel for the rest, in one
+    batch, against the oracle."""
     insts = octet_batch()
     seed = 0x0C7E7
     k, cycles = 3, 18
-    say(f"case: bit-packed octet batch, {cycles} cycles of {k} sweeps, graph={graph}")
+    say(f"case: bit-packed octet batch, {cycles} cycles of {k} sweeps, graph={graph}, "
+        f"per_sweep={per_sweep}")
     refs = oracle_batch(insts, seed, k, cycles)
-    flags = 0 if graph else ptqmc.PT_FLAG_NO_GRAPH
+    flags = (0 if graph else ptqmc.PT_FLAG_NO_GRAPH) | (
+        ptqmc.PT_FLAG_BLOCK_LAUNCH_PER_SWEEP if per_sweep else 0)
     with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, encoding=ptqmc.PT_BITPACK32,
                        flags=flags) as s:
         info = s.info()
         assert info["oct_tiles"] > 0 and info["oct_blocks"] > 0 and info["class_launches"] > 0
+        assert info["oct_resident"] == (0 if per_sweep else 1)
         s.run(cycles)
-        s.sweep(2)  # a call of another length (the blocks' last launch sums the energies)
+        s.sweep(2)  # a call of another length (the blocks sum the energies at its end)
+        s.sweep(1)  # and of one sweep
         for r in refs:
             r.sweep(2)
+            r.sweep(1)
         for n in range(len(insts)):
             assert_same(s, n, refs[n], "octets")
 
