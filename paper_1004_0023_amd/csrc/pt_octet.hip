@@ -121,14 +121,43 @@ __device__ __forceinline__ void count9(const uint32_t (&v)[9], uint32_t &n0, uin
     n3 = fa & fb;
 }
 
-// Bit r of every byte of plane p moved to bit q + 2 of that byte (q + 2 - r is a constant
-// after unrolling).
-template <int Q>
-__device__ __forceinline__ uint32_t place(uint32_t p, int r)
+// Rows a and b of a bit matrix exchange the bits where (a >> sh) and b differ under mask m
+// (one step of a bit-matrix transpose).
+__device__ __forceinline__ void delta_swap(uint32_t &a, uint32_t &b, int sh, uint32_t m)
 {
-    const int sh = Q + 2 - r;
-    const uint32_t v = sh >= 0 ? (p << sh) : (p >> (-sh));
-    return v & (0x01010101u << (Q + 2));
+    const uint32_t t = ((a >> sh) ^ b) & m;
+    b ^= t;
+    a ^= t << sh;
+}
+
+// Table byte offsets 4 (n + 16 sigma) of the four slices of each of the lane's SPL slots:
+// byte b of w[r] takes bit 8 b + r of n0 .. n3, s0, s1 at bits 2 .. 7.  In every byte lane
+// this is the transpose of the 8 x 8 bit matrix with rows (0, 0, n0, n1, n2, n3, s0, s1);
+// with four slots per lane only the first four rows of the result are formed.
+template <int SPL>
+__device__ __forceinline__ void slot_offsets(uint32_t n0, uint32_t n1, uint32_t n2, uint32_t n3,
+                                             uint32_t s0, uint32_t s1, uint32_t (&w)[SPL])
+{
+    uint32_t a[8] = {0u, 0u, n0, n1, n2, n3, s0, s1};
+    if constexpr (SPL == 8) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) delta_swap(a[i], a[i + 4], 4, 0x0F0F0F0Fu);
+#pragma unroll
+        for (int i : {0, 1, 4, 5}) delta_swap(a[i], a[i + 2], 2, 0x33333333u);
+#pragma unroll
+        for (int i : {0, 2, 4, 6}) delta_swap(a[i], a[i + 1], 1, 0x55555555u);
+    } else {
+        // rows 0 .. 3 after the first step: their low nibbles, and the low nibbles of rows
+        // 4 .. 7 as high nibbles
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = (a[i] & 0x0F0F0F0Fu) | ((a[i + 4] << 4) & 0xF0F0F0F0u);
+        delta_swap(a[0], a[2], 2, 0x33333333u);
+        delta_swap(a[1], a[3], 2, 0x33333333u);
+        delta_swap(a[0], a[1], 1, 0x55555555u);
+        delta_swap(a[2], a[3], 1, 0x55555555u);
+    }
+#pragma unroll
+    for (int r = 0; r < SPL; ++r) w[r] = a[r];
 }
 
 // The per-item constants of a site.
@@ -171,13 +200,13 @@ __device__ __forceinline__ uint32_t oct_update(uint32_t X, uint32_t Tlo,
     s0 >>= sh;
     s1 >>= sh;
     const uint32_t tbase = site.hzbase + 512u * (uint32_t)sh;
+    uint32_t offs[SPL];
+    slot_offsets<SPL>(n0, n1, n2, n3, s0, s1, offs);
     uint32_t flip = 0u;
 #pragma unroll
     for (int r = 0; r < SPL; ++r) {
         if (sh + r < nslots) {
-            // table byte offsets 4 (n + 16 sigma) of the four slices of slot sh + r
-            const uint32_t idx = place<0>(n0, r) | place<1>(n1, r) | place<2>(n2, r) |
-                                 place<3>(n3, r) | place<4>(s0, r) | place<5>(s1, r);
+            const uint32_t idx = offs[r];  // table byte offsets of slot sh + r's four slices
             const Words4 u = philox10_rk(ctr0, tt, cbase + (uint32_t)(sh + r), n, key0, key1);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
