@@ -179,6 +179,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0)
     ap.add_argument("--encoding", choices=["int8", "bitpack"], default=None,
                     help="spin encoding (default: bitpack for configs 3 and 4, int8 otherwise)")
+    ap.add_argument("--no-work-queue", action="store_true",
+                    help="bit-packed whole octets: one workgroup per octet, exchange launched apart")
     ap.add_argument("--tau-corr", action="store_true",
                     help="also accumulate imaginary-time correlations at every exchange step")
     args = ap.parse_args()
@@ -206,7 +208,8 @@ def main():
     print(f"bench: {desc}; {steps} steps of {k} sweeps + exchange", file=sys.stderr, flush=True)
 
     encoding = ptqmc.PT_BITPACK32 if args.encoding == "bitpack" else ptqmc.PT_INT8
-    flags = ptqmc.PT_FLAG_TAU_CORR if args.tau_corr else 0
+    flags = (ptqmc.PT_FLAG_TAU_CORR if args.tau_corr else 0) | (
+        ptqmc.PT_FLAG_NO_WORK_QUEUE if args.no_work_queue else 0)
     s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags,
                       tile_bytes=args.tile_bytes, block_threads=args.block_threads,
                       encoding=encoding)
@@ -328,6 +331,8 @@ def main():
                    "lds_bytes": info["lds_bytes"], "timed_route": route,
                    "encoding": args.encoding,
                    "tau_corr": bool(args.tau_corr),
+                   "work_queue": (info["oct_queue"] > 0) if packed else None,
+                   "fused_exchange": bool(info["oct_fused"]) if packed else None,
                    "block_resident": (bool(cal["block_resident"]) if blocked else
                                       bool(cal["oct_resident"]) if packed and cal["oct_blocks"] > 0
                                       else None),

@@ -46,9 +46,13 @@
  * thread-local message for the last failure on the calling thread.  A context is used
  * by one host thread at a time.  All calls that launch work are asynchronous on the
  * context's stream; pt_observables, pt_get_spins, pt_save and pt_sync synchronise it.
- * Those four also return PT_ESTATE if, since the last of them, a slice-block launch
- * with resident blocks gave up waiting for a neighbouring block (its waits are bounded
- * so that every launch ends; the chain state is then not the sampler's).
+ * A slice-block launch with resident blocks bounds its waits for neighbouring blocks so
+ * that every launch ends; if one gave up since the last of those four calls, the next of
+ * them restores the state of the last clean synchronisation (a device copy the context
+ * keeps when resident launches are possible), replays the calls since with slice blocks
+ * launched per sweep (or per parity), and then runs them that way for the rest of the
+ * context (pt_info.recoveries counts this).  PT_ESTATE is returned only if that replay
+ * fails too.
  */
 #ifndef PTQMC_H
 #define PTQMC_H
@@ -107,10 +111,16 @@ extern "C" {
                                           chain; a measurement and test hook)          */
 #define PT_FLAG_TAU_CORR 0x80u     /* accumulate imaginary-time spin correlations per rung
                                       at every exchange step (pt_obs.sumCt); PT_INT8 only */
+#define PT_FLAG_NO_WORK_QUEUE 0x100u /* PT_BITPACK32: one workgroup per whole octet instead of
+                                          workgroups taking octets from the device work
+                                          queue (which also runs an instance's exchange
+                                          step in the octet that completes it); the same
+                                          chain (a measurement and test hook)          */
 #define PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT 0x40u /* test hook: resident slice blocks wait for a
                                           progress count that never comes, under a tiny
-                                          poll bound, so every wait gives up and the next
-                                          synchronising call returns PT_ESTATE          */
+                                          poll bound, so every wait gives up; the next
+                                          synchronising call recovers (pt_info.recoveries)
+                                          */
 
 typedef struct pt_ctx pt_ctx;
 
@@ -200,6 +210,16 @@ typedef struct {
                                          boundary groups passed between neighbouring
                                          blocks in device memory; 0: one launch per
                                          parity of every sweep                          */
+    int32_t oct_queue;                /* whole octets: workgroups of the device work queue
+                                         (0: one workgroup per octet)                   */
+    int32_t oct_fused;                /* 1: a PT cycle of the batch is one launch, the
+                                         exchange step run by the octet that completes
+                                         each instance                                  */
+    int64_t recoveries;               /* synchronising calls that found a resident
+                                         launch's wait given up, restored the state of
+                                         the last clean synchronisation and replayed
+                                         the calls since with slice blocks launched per
+                                         sweep (resident launches stay off after one)   */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

@@ -237,6 +237,9 @@ struct DevState {
     const int32_t *otiles;
     uint32_t *orec;
     int32_t *oprog;
+    // whole octets from the device work queue: the next list position and the workgroups
+    // that found the queue empty (the last of them resets both for the next launch)
+    int32_t *oqueue;
     // mutable state
     uint8_t *spins;
     int64_t *E;       // per replica slot

@@ -86,7 +86,7 @@ struct Plan {
     // byte offsets in the workspace
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
         o_repinst, o_halo, o_itiles, o_icount, o_prog, o_err, o_bp_sblk, o_bp_eblk, o_bp_wg,
-        o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles, o_orec, o_oprog;
+        o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles, o_orec, o_oprog, o_oqueue;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr, o_sumCt;
@@ -442,7 +442,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
                 for (int o = 0; o < 4 && 32 * w + 8 * o < d.R; ++o) {
                     if (whole) {
                         tiles.push_back({n, w, o, 0, d.G4, 0, 0, 0});
-                        P.otile_lds = std::max(P.otile_lds, oct_lds_bytes(d, d.G4, kOctTile));
+                        P.otile_lds = std::max(P.otile_lds, oct_lds_bytes(d, d.G4, kOctTile) + kOctQueueLds);
                     } else {
                         // the octet's ring of blocks (at least two: ng < G4), consecutive in
                         // the list; neighbours and record offsets are filled in below
@@ -550,6 +550,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
     P.o_otiles = take(P.otiles.size() * 4);
     P.o_orec = take((size_t)P.orec_words * 2 * 4);
     P.o_oprog = take((size_t)(P.n_otile + P.n_oblock) * 2 * 4);
+    P.o_oqueue = take(2 * 4);  // zero in the uploaded image
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
     P.o_E = take((size_t)rep * 8);
@@ -650,6 +651,18 @@ struct pt_ctx {
     int resident_per_cu = 0;
     int block_persistent = 0;   // the last slice-block call ran as one resident launch
     bool oct_resident = false;  // octet slice blocks: one resident launch per call
+    // Recovery when a resident launch's wait gave up: a device copy of the state region at
+    // the last clean synchronisation, the calls queued since (kind, count: 0 pt_sweep,
+    // 1 pt_exchange, 2 pt_run), and whether resident launches are off since a recovery.
+    char *shadow = nullptr;
+    std::vector<std::pair<int, int>> journal;
+    bool replaying = false, resident_off = false;
+    int64_t recoveries = 0;
+    // whole octets from the device work queue; the exchange fused into the octet that
+    // completes an instance (every instance of the batch in whole octets)
+    bool oct_queue = false, oct_fuse = false;
+    std::pair<int, int> oct_queue_key{-1, -1};  // (threads, LDS) of oct_queue_grid
+    int32_t oct_queue_grid = 0;
     int block_threads = 256;
     int tile_bytes = 0;        // target spin bytes per tile in use
     // self-tuning: candidate (tile bytes, threads) shapes timed on the first sweep launches
@@ -917,7 +930,7 @@ std::vector<LaunchGroup> launch_groups(const pt_ctx *c)
 hipError_t blocks_resident(pt_ctx *c, bool &resident)
 {
     resident = false;
-    if (c->opt.flags & PT_FLAG_BLOCK_LAUNCH_PER_SWEEP) return hipSuccess;
+    if ((c->opt.flags & PT_FLAG_BLOCK_LAUNCH_PER_SWEEP) || c->resident_off) return hipSuccess;
     if (c->resident_key != std::make_pair(c->block_threads, c->lds_block)) {
         int32_t per_cu = 0;
         const hipError_t e = block_resident_per_cu(c->block_threads, c->lds_block, &per_cu);
@@ -929,9 +942,30 @@ hipError_t blocks_resident(pt_ctx *c, bool &resident)
     return hipSuccess;
 }
 
-// Wait for the stream, then fail if a kernel set the device error word (a resident
-// slice-block launch that gave up a wait, an octet kernel that refused to run); the word is
-// cleared, and the chain state after such a launch is not the sampler's.
+int recover(pt_ctx *c);
+
+// The state region copied to the shadow copy, the journal cleared (stream-ordered: the
+// copy reads the state as the calls queued so far leave it).
+hipError_t take_snapshot(pt_ctx *c)
+{
+    c->journal.clear();
+    if (!c->shadow) return hipSuccess;
+    return hipMemcpyAsync(c->shadow, c->ws + c->plan.o_state, c->plan.state_bytes,
+                          hipMemcpyDeviceToDevice, c->stream);
+}
+
+void journal_add(pt_ctx *c, int kind, int n)
+{
+    if (c->shadow && !c->replaying) c->journal.emplace_back(kind, n);
+}
+
+// Wait for the stream, then check the device error word (a resident slice-block launch
+// that gave up a wait, an octet kernel that refused to run).  After a wait that gave up,
+// the state is restored from the copy of the last clean synchronisation and the calls
+// queued since are replayed with every slice block launched per sweep (or per parity),
+// which gives the chain's state again; otherwise the call fails with PT_ESTATE (the word
+// is cleared, and the chain state after such a launch is not the sampler's).  A clean
+// synchronisation after new calls takes a new copy.
 int sync_and_check(pt_ctx *c)
 {
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -943,9 +977,11 @@ int sync_and_check(pt_ctx *c)
         if (err & kErrLdsBase)
             return fail(PT_ESTATE, "an octet kernel found its dynamic LDS away from address 0 "
                                    "and did not run; the state is inconsistent");
+        if (c->shadow && !c->replaying) return recover(c);
         return fail(PT_ESTATE, "a resident slice-block launch waited too long for its "
                                "neighbouring blocks; the state is inconsistent");
     }
+    if (!c->journal.empty() && !c->replaying) HIP_TRY(take_snapshot(c));
     return PT_OK;
 }
 
@@ -958,9 +994,24 @@ hipError_t energies_from_spins(pt_ctx *c, int rep_first, int n)
     return launch_energy(c->st, rep_first, n, c->stream);
 }
 
+// Whole octets from the device work queue: as many workgroups as the compute units hold at
+// once for the current block size (at most one per octet).
+hipError_t oct_queue_shape(pt_ctx *c)
+{
+    const Plan &P = c->plan;
+    const auto key = std::make_pair(c->block_threads, P.otile_lds);
+    if (c->oct_queue_key == key) return hipSuccess;
+    int32_t per_cu = 0;
+    const hipError_t e = oct_tile_per_cu(key.first, key.second, &per_cu);
+    if (e != hipSuccess) return e;
+    c->oct_queue_key = key;
+    c->oct_queue_grid = std::min<int32_t>(P.n_otile, std::max(1, per_cu) * c->cus);
+    return hipSuccess;
+}
+
 // Bit-packed encoding: n_sweeps sweeps as one launch per colour class (parity, colour) of
 // every instance, then E_cl and C of every replica.
-int enqueue_bp_sweep(pt_ctx *c, int n_sweeps)
+int enqueue_bp_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
 {
     const Plan &P = c->plan;
     const bool timing = (c->opt.flags & PT_FLAG_TIMING) != 0;
@@ -983,8 +1034,22 @@ int enqueue_bp_sweep(pt_ctx *c, int n_sweeps)
         O.n_tiles = P.n_otile;
         O.threads = c->block_threads;
         O.lds_bytes = P.otile_lds;
-        const hipError_t e = launch_oct_tiles(O, c->stream);
+        int32_t grid = P.n_otile;
+        if (c->oct_queue) {
+            const hipError_t e = oct_queue_shape(c);
+            if (e != hipSuccess) return hip_fail(e, "octet occupancy query");
+            O.queue = 1;
+            grid = c->oct_queue_grid;
+        }
+        if (fuse_exchange) {
+            O.fuse = 1;
+            O.swap_key0 = c->key_swap0;
+            O.swap_key1 = c->key_swap1;
+            O.t_add = (uint32_t)n_sweeps;
+        }
+        const hipError_t e = launch_oct_tiles(O, grid, c->stream);
         if (e != hipSuccess) return hip_fail(e, "octet tile launch");
+        O.queue = O.fuse = 0;
     }
     if (P.n_oblock > 0) {
         O.tile0 = P.n_otile;
@@ -1185,7 +1250,9 @@ int enqueue_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
 {
     if (n_sweeps <= 0) return PT_OK;
     const bool bp = c->plan.encoding == PT_BITPACK32;
-    if (!c->tuning) return bp ? enqueue_bp_sweep(c, n_sweeps) : enqueue_sweep_once(c, n_sweeps, fuse_exchange);
+    if (!c->tuning)
+        return bp ? enqueue_bp_sweep(c, n_sweeps, fuse_exchange)
+                  : enqueue_sweep_once(c, n_sweeps, fuse_exchange);
     const size_t nc = c->cand.size();
     const size_t k = c->cand_next % nc;
     const auto shape = c->cand[k];
@@ -1197,7 +1264,8 @@ int enqueue_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
     c->block_threads = shape.second;
     HIP_TRY(hipEventRecord(c->tune_ev[0], c->stream));
     const int fb = c->fallbacks;
-    rc = bp ? enqueue_bp_sweep(c, n_sweeps) : enqueue_sweep_once(c, n_sweeps, fuse_exchange);
+    rc = bp ? enqueue_bp_sweep(c, n_sweeps, fuse_exchange)
+            : enqueue_sweep_once(c, n_sweeps, fuse_exchange);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(c->tune_ev[1], c->stream));
     HIP_TRY(hipEventSynchronize(c->tune_ev[1]));
@@ -1267,7 +1335,7 @@ int enqueue_cycle(pt_ctx *c)
 {
     const int k = c->opt.sweeps_per_exchange;
     int rc;
-    if (c->plan.encoding == PT_INT8 && c->tiles.size() <= kFuseMaxTiles) {
+    if ((c->plan.encoding == PT_INT8 && c->tiles.size() <= kFuseMaxTiles) || c->oct_fuse) {
         rc = enqueue_sweep(c, k, true);
     } else {
         rc = enqueue_sweep(c, k, false);
@@ -1415,6 +1483,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.otiles = (const int32_t *)(w + P.o_otiles);
     st.orec = (uint32_t *)(w + P.o_orec);
     st.oprog = (int32_t *)(w + P.o_oprog);
+    st.oqueue = (int32_t *)(w + P.o_oqueue);
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;
@@ -1475,6 +1544,17 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
             return cleanup(fail(PT_EINVAL, "octet work needs more LDS than the device has"));
         e = oct_kernels_set_lds(P.otile_lds, P.oblock_lds, P.oblock_res_lds);
         if (e != hipSuccess) return cleanup(hip_fail(e, "octet kernel LDS attribute"));
+        // whole octets from the device work queue, and the exchange step in the octet that
+        // completes an instance when every instance is in whole octets
+        c->oct_queue = P.n_otile > 0 && !(opt->flags & PT_FLAG_NO_WORK_QUEUE);
+        c->oct_fuse = c->oct_queue && P.n_oblock == 0 && !P.bp_generic;
+        if (c->oct_fuse) {
+            c->itiles.assign(P.desc.size(), 0);
+            for (int32_t k = 0; k < P.n_otile; ++k) c->itiles[P.otiles[(size_t)k * kOctRec]] += 1;
+            e = hipMemcpyAsync(c->ws + P.o_itiles, c->itiles.data(), c->itiles.size() * 4,
+                               hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) return cleanup(hip_fail(e, "octet counts upload"));
+        }
         // octet slice blocks run resident (one launch per call) when every block fits the
         // compute units at once: blocks wait for their neighbours, which must all have started
         if (P.n_oblock > 0 && !(opt->flags & PT_FLAG_BLOCK_LAUNCH_PER_SWEEP)) {
@@ -1484,7 +1564,13 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
             c->oct_resident = (int64_t)P.n_oblock <= (int64_t)per_cu * c->cus;
         }
     }
-    if (P.encoding == PT_BITPACK32) c->block_threads = opt->block_threads > 0 ? opt->block_threads : 256;
+    if (P.encoding == PT_BITPACK32) {
+        c->block_threads = opt->block_threads > 0 ? opt->block_threads : 256;
+        if (c->oct_queue) {
+            e = oct_queue_shape(c);
+            if (e != hipSuccess) return cleanup(hip_fail(e, "octet occupancy query"));
+        }
+    }
     const bool tune_int8 = P.encoding == PT_INT8 && opt->tile_replicas == 0 &&
                            opt->tile_bytes == 0 && opt->block_threads == 0;
     // packed: the workgroup size of the whole-octet launch
@@ -1503,6 +1589,16 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
             if (e != hipSuccess) return cleanup(hip_fail(e, "hipEventCreate"));
         }
     }
+    // a resident slice-block launch may give up a wait: keep a copy of the state to restore
+    if (P.halo_words > 0 || P.n_oblock > 0) {
+        e = hipMalloc((void **)&c->shadow, std::max<size_t>(P.state_bytes, 1));
+        if (e != hipSuccess) {
+            c->shadow = nullptr;
+            return cleanup(hip_fail(e, "hipMalloc (state copy)"));
+        }
+        e = take_snapshot(c);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "state copy"));
+    }
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return cleanup(hip_fail(e, "init synchronise"));
     *out = c;
@@ -1514,6 +1610,7 @@ int pt_sweep(pt_ctx *c, int32_t n_sweeps)
     if (!c) return fail(PT_EINVAL, "null context");
     if (n_sweeps < 0) return fail(PT_EINVAL, "n_sweeps < 0");
     if (n_sweeps == 0) return PT_OK;
+    journal_add(c, 0, n_sweeps);
     int rc = enqueue_sweep(c, n_sweeps, false);
     if (rc) return rc;
     hipError_t e = launch_advance(c->st, n_inst_of(c), (uint32_t)n_sweeps, c->stream);
@@ -1524,6 +1621,7 @@ int pt_sweep(pt_ctx *c, int32_t n_sweeps)
 int pt_exchange(pt_ctx *c)
 {
     if (!c) return fail(PT_EINVAL, "null context");
+    journal_add(c, 1, 0);
     int rc = enqueue_exchange(c, 0);
     if (rc) return rc;
     return enqueue_tau_corr(c);
@@ -1533,6 +1631,7 @@ int pt_run(pt_ctx *c, int32_t n_cycles)
 {
     if (!c) return fail(PT_EINVAL, "null context");
     if (n_cycles < 0) return fail(PT_EINVAL, "n_cycles < 0");
+    if (n_cycles > 0) journal_add(c, 2, n_cycles);
     // Batches whose instances each fit one whole-replica tile run up to kLaunchCycles
     // cycles per launch, each workgroup doing its instance's exchange steps itself (no
     // launch per cycle, no graph).  Not with the correlations (a launch of their own per
@@ -1592,6 +1691,39 @@ int pt_run(pt_ctx *c, int32_t n_cycles)
     }
     return PT_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// After a resident launch gave up a wait: restore the state of the last clean
+// synchronisation, turn resident launches off (and drop the captured graph, which holds
+// them), and replay the calls queued since; the result is the chain's state.
+int recover(pt_ctx *c)
+{
+    HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_state, c->shadow, c->plan.state_bytes,
+                           hipMemcpyDeviceToDevice, c->stream));
+    c->resident_off = true;
+    c->oct_resident = false;
+    drop_graph(c);
+    const auto calls = c->journal;
+    c->replaying = true;
+    int rc = PT_OK;
+    for (const auto &op : calls) {
+        rc = op.first == 0 ? pt_sweep(c, op.second) : op.first == 1 ? pt_exchange(c) : pt_run(c, op.second);
+        if (rc) break;
+    }
+    if (rc == PT_OK) rc = sync_and_check(c);
+    c->replaying = false;
+    if (rc) return rc;
+    c->recoveries += 1;
+    HIP_TRY(take_snapshot(c));
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int pt_sync(pt_ctx *c)
 {
@@ -1722,6 +1854,7 @@ int pt_set_spins(pt_ctx *c, int32_t inst, const int8_t *in)
     }
     hipError_t e = energies_from_spins(c, d.rep_base, d.R);
     if (e != hipSuccess) return hip_fail(e, "energy launch");
+    HIP_TRY(take_snapshot(c));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return PT_OK;
 }
@@ -1753,6 +1886,7 @@ int pt_load(pt_ctx *c, const void *buf, size_t len)
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(c->ws + c->plan.o_state, (const char *)buf + sizeof(CkptHeader),
                            c->plan.state_bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(take_snapshot(c));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return PT_OK;
 }
@@ -1797,6 +1931,9 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->oct_blocks = c->plan.n_oblock;
     o->oct_tile_launches = c->plan.n_otile > 0 ? 1 : 0;
     o->oct_resident = c->oct_resident ? 1 : 0;
+    o->oct_queue = c->oct_queue ? c->oct_queue_grid : 0;
+    o->oct_fused = c->oct_fuse ? 1 : 0;
+    o->recoveries = c->recoveries;
     if (c->plan.encoding == PT_BITPACK32 && c->plan.bp_generic) {
         int parities = 1;
         for (const auto &d : c->plan.desc) parities = std::max(parities, d.parities);
@@ -1835,6 +1972,7 @@ void pt_free(pt_ctx *c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
+    if (c->shadow) (void)hipFree(c->shadow);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     for (auto e : c->tune_ev)
         if (e) (void)hipEventDestroy(e);

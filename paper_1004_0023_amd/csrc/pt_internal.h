@@ -61,6 +61,11 @@ struct OctLaunch {
     int32_t tile0, n_tiles, threads, lds_bytes;
     int32_t n_sweeps, sweep_off, p, last;
     int32_t split;      // slice blocks: two lanes per (site, group), four slots each
+    // whole octets: queue = the workgroups take octets from the device work queue
+    // (DevState::oqueue) in list order until it runs dry; fuse = the octet that completes
+    // an instance (DevState::icount against itiles) then runs its exchange step
+    int32_t queue, fuse;
+    uint32_t swap_key0, swap_key1, t_add;
     int32_t rec_words;  // resident: words of the R0 record region (the R1 region follows)
     // resident: poll bound of a neighbour wait (0: the kernel's default) and an amount added
     // to every awaited progress count (0; a test hook sets it so that the waits give up)
@@ -95,7 +100,7 @@ hipError_t launch_bp_init(const DevState &st, int32_t n_eblk, uint32_t key0, uin
                           hipStream_t s);
 hipError_t launch_bp_sweep(const BpLaunch &L, hipStream_t s);
 hipError_t launch_bp_energy(const DevState &st, int32_t n_eblk, int32_t n_reps, hipStream_t s);
-hipError_t launch_oct_tiles(const OctLaunch &L, hipStream_t s);
+hipError_t launch_oct_tiles(const OctLaunch &L, int32_t grid, hipStream_t s);
 hipError_t launch_oct_phase(const OctLaunch &L, hipStream_t s);
 hipError_t launch_oct_resident(const OctLaunch &L, hipStream_t s);
 // E_cl and C of the replicas of octet work items [tile0, tile0 + n_tiles) set to zero (the
@@ -109,6 +114,10 @@ hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes, int32_t 
 // Resident octet slice blocks of `threads` threads and `lds_bytes` of LDS that one compute
 // unit holds at once.
 hipError_t oct_resident_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu);
+// Whole-octet workgroups (queue mode) that one compute unit holds at once.
+hipError_t oct_tile_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu);
+// LDS bytes the queue mode adds after the largest octet (the pulled index and a flag).
+constexpr int32_t kOctQueueLds = 16;
 hipError_t launch_threshold_eval(const double *dS, uint32_t *out, int32_t n, hipStream_t s);
 hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes);
 // Slice-block workgroups of `threads` threads and `lds_bytes` of LDS that one compute unit

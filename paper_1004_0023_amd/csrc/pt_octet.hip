@@ -25,6 +25,7 @@
 //              four-slice groups of the parity swept and ng + 1 of the other; the last
 //              launch of a call adds each block's part of E_cl and C
 //   oct_clear  E_cl and C of the slice-block octets set to zero before a call
+#include "pt_exchange.h"
 #include "pt_internal.h"
 
 #pragma clang fp contract(off)
@@ -50,6 +51,10 @@ __device__ __forceinline__ uint32_t ld32(uint32_t a) { return *(const LdsU32 *)(
 __device__ __forceinline__ void st32(uint32_t a, uint32_t v) { *(LdsU32 *)(uintptr_t)a = v; }
 __device__ __forceinline__ uint32_t ld16(uint32_t a) { return *(const LdsU16 *)(uintptr_t)a; }
 __device__ __forceinline__ uint32_t ld8(uint32_t a) { return *(const LdsU8 *)(uintptr_t)a; }
+
+// s_waitcnt immediate with the vector-memory count 0 and the export and LDS counts at
+// their maxima (no wait on them): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+constexpr int kOctWaitVmcnt0 = 0x0F70;
 
 // Philox4x32-10 (the sampler's generator) with each round key formed in its round: left to
 // itself the compiler keeps all twenty live in scalar registers across the sweep loops.
@@ -502,15 +507,13 @@ __device__ __forceinline__ void oct_tile_energy(const OctLaunch &L, const InstDe
     oct_reduce(lds, o, e2, cc);
 }
 
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) oct_tile_kernel(OctLaunch L)
+// One whole octet (work item `item`): stage, all sweeps of the call, E_cl and C, write-back;
+// with L.fuse, count the octet for its instance and run the instance's exchange step in
+// the workgroup that completes it.  flag: an LDS word past the octet's layout.
+__device__ __forceinline__ void oct_tile_item(const OctLaunch &L, char *lds, int item, uint32_t flag)
 {
-    extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
-    if ((uint32_t)(uintptr_t)lds != 0u) {  // the addressing below assumes LDS address 0
-        if (threadIdx.x == 0) atomicOr(st.err, kErrLdsBase);
-        return;
-    }
-    const int32_t *rec = st.otiles + (int64_t)(L.tile0 + blockIdx.x) * kOctRec;
+    const int32_t *rec = st.otiles + (int64_t)item * kOctRec;
     const int n = rec[0], w = rec[1], oct = rec[2];
     const InstDesc d = st.inst[n];
     const OctLds o = oct_layout(d, d.G4, kOctTile);
@@ -553,14 +556,77 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     __syncthreads();
     const int64_t *red = reinterpret_cast<const int64_t *>(lds + o.red);
     if (tid < nslots) {
-        st.E[d.rep_base + c0 + tid] = red[tid] / 2;
-        st.C[d.rep_base + c0 + tid] = red[8 + tid];
+        if (L.fuse) {
+            // read by the exchange step in this launch, possibly on another XCD
+            __hip_atomic_store(&st.E[d.rep_base + c0 + tid], red[tid] / 2, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st.C[d.rep_base + c0 + tid], red[8 + tid], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            st.E[d.rep_base + c0 + tid] = red[tid] / 2;
+            st.C[d.rep_base + c0 + tid] = red[8 + tid];
+        }
     }
     // write the octet's bytes back
     for (int k = tid; k < words; k += nt) {
         const int g = k & (G4 - 1), pi = k >> lgG4;
         const int p = pi >= N ? 1 : 0, i = pi - p * N;
         oct_store(oct_row(st, d, w, p, i), g, oct, ld32(4u * (uint32_t)k));
+    }
+    if (!L.fuse) return;
+    // every wave's E_cl, C stores complete before the count (a barrier does not wait for
+    // them); the completing workgroup reads them with agent-scope atomic loads
+    __builtin_amdgcn_s_waitcnt(kOctWaitVmcnt0);
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t before =
+            __hip_atomic_fetch_add(&st.icount[n], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t done = before + 1u == (uint32_t)st.itiles[n] ? 1u : 0u;
+        if (done) __hip_atomic_store(&st.icount[n], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st32(flag, done);
+    }
+    __syncthreads();
+    if (ld32(flag)) exchange_instance<true>(st, n, L.swap_key0, L.swap_key1, L.t_add);
+}
+
+// Whole octets.  Without the queue, workgroup b takes list position tile0 + b.  With it
+// (QUEUE), as many workgroups as the compute units hold take positions from the device work
+// queue in list order (largest first) until it runs dry.  The queue's loop keeps more state
+// live across an octet's sweeps: that instantiation is held to four waves per SIMD (at
+// eight it spills to scratch).
+template <bool QUEUE>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(QUEUE ? 4 : 8))) oct_tile_kernel(OctLaunch L)
+{
+    extern __shared__ __align__(16) char lds[];
+    const DevState &st = L.st;
+    if ((uint32_t)(uintptr_t)lds != 0u) {  // the addressing below assumes LDS address 0
+        if (threadIdx.x == 0) atomicOr(st.err, kErrLdsBase);
+        return;
+    }
+    // two LDS words past every octet's layout: the pulled position and the exchange flag
+    const uint32_t slot = (uint32_t)L.lds_bytes - (uint32_t)kOctQueueLds;
+    auto pull = [&]() {
+        if (threadIdx.x == 0)
+            st32(slot, (uint32_t)__hip_atomic_fetch_add(&st.oqueue[0], 1, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT));
+        __syncthreads();
+        const int k = (int)ld32(slot);
+        __syncthreads();
+        return k;
+    };
+    if constexpr (!QUEUE) {
+        (void)pull;
+        oct_tile_item(L, lds, L.tile0 + (int)blockIdx.x, slot + 4u);
+        return;
+    }
+    for (int k = pull(); k < L.n_tiles; k = pull()) oct_tile_item(L, lds, L.tile0 + k, slot + 4u);
+    // the last workgroup to find the queue empty resets it: every other one has made its
+    // last pull by then
+    if (threadIdx.x == 0 &&
+        __hip_atomic_fetch_add(&st.oqueue[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+            (int)gridDim.x - 1) {
+        __hip_atomic_store(&st.oqueue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&st.oqueue[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -740,10 +806,6 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 // an agent-scope release and acquire instead, which write the whole XCD's L2 back and
 // invalidate it, made config 4's sweeps 1.4x slower.)
 constexpr int kOctWaitPolls = 1 << 18;
-// s_waitcnt immediate with the vector-memory count 0 and the export and LDS counts at
-// their maxima (no wait on them): vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
-constexpr int kWaitVmcnt0 = 0x0F70;
-
 __device__ __forceinline__ uint32_t rec_ld(const uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -778,7 +840,7 @@ __device__ __forceinline__ void oct_wait(const DevState &st, const int32_t *flag
 // (a workgroup barrier does not wait for them), then thread 0 stores v.
 __device__ __forceinline__ void oct_publish(int32_t *flag, int v)
 {
-    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __builtin_amdgcn_s_waitcnt(kOctWaitVmcnt0);
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(flag, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -898,7 +960,10 @@ hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes, int32_t 
 {
     hipError_t e = hipSuccess;
     if (tile_bytes > 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_tile_kernel),
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_tile_kernel<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, tile_bytes);
+    if (e == hipSuccess && tile_bytes > 0)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_tile_kernel<true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, tile_bytes);
     if (e == hipSuccess && phase_bytes > 0)
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_phase_kernel),
@@ -925,10 +990,23 @@ hipError_t launch_oct_resident(const OctLaunch &L, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_oct_tiles(const OctLaunch &L, hipStream_t s)
+hipError_t oct_tile_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu)
+{
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void *>(&oct_tile_kernel<true>), threads, (size_t)lds_bytes);
+    *per_cu = n;
+    return e;
+}
+
+// grid: the workgroups of a queue launch (n_tiles otherwise)
+hipError_t launch_oct_tiles(const OctLaunch &L, int32_t grid, hipStream_t s)
 {
     if (L.n_tiles <= 0 || L.n_sweeps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(oct_tile_kernel, dim3(L.n_tiles), dim3(L.threads), L.lds_bytes, s, L);
+    if (L.queue)
+        hipLaunchKernelGGL(oct_tile_kernel<true>, dim3(grid), dim3(L.threads), L.lds_bytes, s, L);
+    else
+        hipLaunchKernelGGL(oct_tile_kernel<false>, dim3(L.n_tiles), dim3(L.threads), L.lds_bytes, s, L);
     return hipGetLastError();
 }
 

@@ -152,22 +152,31 @@ def test_config4_lattice_one_cycle(ptqmc, per_sweep):
         assert_same(s, 0, ref, "config4")
 
 
-def test_octet_resident_wait_timeout_is_reported(ptqmc):
+def test_octet_resident_wait_timeout_recovers(ptqmc):
     """Resident octet slice blocks bound their neighbour waits.  Forced from the host
     (every block waits for a progress count no block publishes, under a poll bound of 16),
-    each wait gives up, every workgroup still exits, and the next synchronising call
-    returns PT_ESTATE once; the error word is then clear."""
+    each wait gives up and every workgroup still exits; the next synchronising call
+    restores the state of the last clean synchronisation and replays the calls since with
+    per-parity launches: the state is the oracle's and one recovery is counted."""
     inst = W.config4()
-    say("case: resident octet slice blocks, forced wait timeout (config 4, 10 sweeps)")
-    with ptqmc.Sampler([inst], 7, sweeps_per_exchange=10, encoding=ptqmc.PT_BITPACK32,
-                       flags=ptqmc.PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT | ptqmc.PT_FLAG_NO_GRAPH) as s:
+    seed = 7
+    say("case: resident octet slice blocks, forced wait timeout (config 4), recovery")
+    ref = oracle.OracleChain(inst, seed)
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, encoding=ptqmc.PT_BITPACK32,
+                       flags=ptqmc.PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT) as s:
         assert s.info()["oct_resident"] == 1
+        s.run(2)
+        s.sweep(1)
+        s.sync()
+        ref.run(10, 2)
+        ref.sweep(1)
+        info = s.info()
+        assert info["recoveries"] == 1 and info["oct_resident"] == 0
+        assert_same(s, 0, ref, "recovered")
         s.run(1)
-        with pytest.raises(ptqmc.PTError) as err:
-            s.sync()
-        assert err.value.code == ptqmc.PT_ESTATE
-        assert "waited too long" in str(err.value)
-        s.sync()  # reported once, then clear
+        ref.run(10, 1)
+        assert_same(s, 0, ref, "after recovery")
+        assert s.info()["recoveries"] == 1
 
 
 def octet_batch():
@@ -215,6 +224,41 @@ def test_octet_kernels_match_oracle(ptqmc, graph, per_sweep):
             r.sweep(1)
         for n in range(len(insts)):
             assert_same(s, n, refs[n], "octets")
+
+
+@pytest.mark.parametrize("queue", [True, False])
+def test_whole_octet_cycles_match_oracle(ptqmc, queue):
+    """A batch whose instances are all whole octets: with the device work queue a PT cycle
+    is one launch, the octet that completes an instance running its exchange step; without
+    it, one workgroup per octet and a separate exchange launch.  Three replays of the
+    16-cycle graph with eager sweeps and exchanges between them, each against the oracle."""
+    insts = octet_batch()[:4]
+    seed = 0x0C7E8
+    k = 2
+    flags = 0 if queue else ptqmc.PT_FLAG_NO_WORK_QUEUE
+    say(f"case: whole octets, graph replays, queue={queue}")
+    refs = [oracle.OracleChain(inst, seed, index=n) for n, inst in enumerate(insts)]
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, encoding=ptqmc.PT_BITPACK32,
+                       flags=flags, block_threads=256) as s:
+        info = s.info()
+        assert info["oct_tiles"] > 0 and info["oct_blocks"] == 0 and info["class_launches"] == 0
+        assert (info["oct_queue"] > 0) == queue and info["oct_fused"] == (1 if queue else 0)
+        for rep in range(3):
+            s.run(16)
+            s.sync()
+            for r in refs:
+                r.run(k, 16)
+            for n in range(len(insts)):
+                assert_same(s, n, refs[n], f"replay {rep}")
+            s.sweep(1)
+            s.exchange()
+            s.run(1)
+            for r in refs:
+                r.sweep(1)
+                r.exchange()
+                r.run(k, 1)
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], "after eager calls")
 
 
 def test_checkpoint_and_spins(ptqmc):

@@ -323,6 +323,34 @@ def test_config3_full_batch_digests(ptqmc, config3_batch, tile_bytes, block_thre
     assert not bad, f"{len(bad)} instances differ from the oracle, first {bad[:8]}"
 
 
+@pytest.mark.parametrize("block_threads,queue", [(1024, True), (256, False), (0, True)])
+def test_config3_bitpack_digests(ptqmc, config3_batch, block_threads, queue):
+    """The batched workload in the bit-packed encoding (every instance whole octets) for
+    the stored 16 cycles: with the device work queue and the exchange run by the octet
+    that completes each instance (the benchmark's route at its tuned 1024 threads, and
+    under the tuner), and with one workgroup per octet and separate exchange launches.
+    Every instance's final state has the oracle's digest."""
+    gold = golden.load_golden("config3")
+    insts = config3_batch
+    seed = W.sampler_seed(3)
+    k, cycles = gold["sweeps_per_exchange"], gold["cycles"]
+    flags = 0 if queue else ptqmc.PT_FLAG_NO_WORK_QUEUE
+    say(f"case: config 3 bit-packed, {cycles} cycles, block_threads={block_threads} queue={queue}")
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, encoding=ptqmc.PT_BITPACK32,
+                       block_threads=block_threads, flags=flags) as s:
+        info = s.info()
+        assert info["oct_tiles"] > 0 and info["oct_blocks"] == 0 and info["class_launches"] == 0
+        assert info["oct_fused"] == (1 if queue else 0)
+        if block_threads:
+            s.run(cycles)
+        else:
+            for _ in range(cycles):
+                s.run(1)
+        bad = [n for n in range(len(insts))
+               if golden.state_digest(s.spins(n), s.observables(n)) != gold["digests"][n]]
+    assert not bad, f"{len(bad)} instances differ from the oracle, first {bad[:8]}"
+
+
 @pytest.mark.parametrize("per_sweep", [False, True])
 @pytest.mark.parametrize("tile_bytes,block_threads", [(0, 256), (4096, 1024)])
 def test_slice_blocks_match_oracle(ptqmc, tile_bytes, block_threads, per_sweep):
@@ -419,22 +447,35 @@ def test_config4_lattice_one_cycle(ptqmc, per_sweep):
         assert_same(s, 0, ref, "config4")
 
 
-def test_resident_block_wait_timeout_is_reported(ptqmc):
+def test_resident_block_wait_timeout_recovers(ptqmc):
     """Resident slice blocks bound their neighbour waits.  Forced from the host (every
     block waits for a progress count no block ever publishes, under a poll bound of 16),
-    each wait gives up, every workgroup still exits, and the next synchronising call
-    returns PT_ESTATE once; the error word is then clear."""
+    each wait gives up and every workgroup still exits; the next synchronising call
+    restores the state of the last clean synchronisation, replays the calls since with a
+    launch per sweep and succeeds: the state is the oracle's, one recovery is counted,
+    and the calls that follow run without resident launches."""
     inst = W.config4()
-    say("case: resident slice blocks, forced wait timeout (config 4, 10 sweeps)")
-    with ptqmc.Sampler([inst], 7, sweeps_per_exchange=10, tile_bytes=131072, block_threads=1024,
+    seed = 7
+    say("case: resident slice blocks, forced wait timeout (config 4), recovery")
+    ref = oracle.OracleChain(inst, seed)
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, tile_bytes=131072, block_threads=1024,
                        flags=ptqmc.PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT | ptqmc.PT_FLAG_NO_GRAPH) as s:
         s.run(1)
-        with pytest.raises(ptqmc.PTError) as err:
-            s.sync()
-        assert err.value.code == ptqmc.PT_ESTATE
-        assert "waited too long" in str(err.value)
         assert s.info()["block_resident"] == 1
-        s.sync()  # reported once, then clear
+        s.sweep(3)
+        s.exchange()
+        s.sync()
+        ref.run(10, 1)
+        ref.sweep(3)
+        ref.exchange()
+        info = s.info()
+        assert info["recoveries"] == 1
+        assert_same(s, 0, ref, "recovered")
+        s.run(1)
+        ref.run(10, 1)
+        assert s.info()["block_resident"] == 0
+        assert_same(s, 0, ref, "after recovery")
+        assert s.info()["recoveries"] == 1
 
 
 def test_maximum_sizes(ptqmc):
