@@ -103,8 +103,13 @@ extern "C" {
 #define PT_FLAG_SLICE_BLOCKS 0x8u  /* split every replica that could use them into slice
                                       blocks, as replicas too large for one workgroup's
                                       LDS always are                                   */
-#define PT_FLAG_FOUR_SLICE_LANES 0x10u /* fast path: one four-slice word per lane instead
-                                          of two (same chain; a measurement and test hook) */
+#define PT_FLAG_FOUR_SLICE_LANES 0x10u /* fast path: one four-slice word per lane (the
+                                          default only for batches too small to give every
+                                          SIMD a wave per colour class; same chain; a
+                                          measurement and test hook)                   */
+#define PT_FLAG_TWO_WORD_LANES 0x200u /* fast path: two four-slice words per lane whatever
+                                          the batch size (same chain; a measurement and
+                                          test hook)                                   */
 #define PT_FLAG_BLOCK_LAUNCH_PER_SWEEP 0x20u /* slice blocks: one launch per sweep (octet
                                           slice blocks: per parity of every sweep) even
                                           when all blocks could be resident at once (same
@@ -220,6 +225,9 @@ typedef struct {
                                          the last clean synchronisation and replayed
                                          the calls since with slice blocks launched per
                                          sweep (resident launches stay off after one)   */
+    int32_t lane_words;               /* PT_INT8 whole-replica tiles: four-slice words per
+                                         lane (2, or 1 for batches too small to give
+                                         every SIMD one wave per colour class)          */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

@@ -650,6 +650,7 @@ struct pt_ctx {
     std::pair<int, int> resident_key{-1, -1};
     int resident_per_cu = 0;
     int block_persistent = 0;   // the last slice-block call ran as one resident launch
+    int lane_words = 2;         // whole-replica tiles: four-slice words per lane
     bool oct_resident = false;  // octet slice blocks: one resident launch per call
     // Recovery when a resident launch's wait gave up: a device copy of the state region at
     // the last clean synchronisation, the calls queued since (kind, count: 0 pt_sweep,
@@ -827,6 +828,24 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
     HIP_TRY(hipMemcpyAsync(c->ws + P.o_itiles, c->itiles.data(), c->itiles.size() * 4,
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(sweep_kernels_set_lds(c->lds_fast, c->lds_generic, c->lds_block));
+    // Whole-replica tiles: two four-slice words per lane, unless the batch's lanes of one
+    // colour class at that width would not give every SIMD of the device one wave; then
+    // the sweep is a chain of short, barely parallel class steps, and one word per lane
+    // (twice the lanes, half the dependent work each) shortens every step (measured on
+    // config 2, 2304 lanes per class: 3.6e10 attempts/s against 3.0e10).
+    int64_t lanes = 0;
+    for (int k = 0; k < c->n_fast_tiles; ++k) {
+        const Tile &t = c->tiles[k];
+        const InstDesc &d = P.desc[t.inst];
+        int64_t most = 0;
+        for (int g = 0; g < d.n_colors; ++g)
+            most = std::max<int64_t>(most, P.cls_off[d.cls_base + g + 1] - P.cls_off[d.cls_base + g]);
+        lanes += (int64_t)t.P * most * std::max(1, d.G4 / 2);
+    }
+    c->lane_words = (c->opt.flags & PT_FLAG_FOUR_SLICE_LANES) ? 1
+                    : (c->opt.flags & PT_FLAG_TWO_WORD_LANES)  ? 2
+                    : lanes < (int64_t)c->cus * 256             ? 1
+                                                                : 2;
     return PT_OK;
 }
 
@@ -1142,7 +1161,7 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange, int cycles =
         L.key1 = c->key_flip1;
         L.n_sweeps = n_sweeps;
         L.block_threads = c->block_threads;
-        L.lane_words = (c->opt.flags & PT_FLAG_FOUR_SLICE_LANES) ? 1 : 2;
+        L.lane_words = c->lane_words;
         L.fuse_exchange = fuse_exchange ? 1 : 0;
         L.swap_key0 = c->key_swap0;
         L.swap_key1 = c->key_swap1;
@@ -1934,6 +1953,7 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->oct_queue = c->oct_queue ? c->oct_queue_grid : 0;
     o->oct_fused = c->oct_fuse ? 1 : 0;
     o->recoveries = c->recoveries;
+    o->lane_words = c->lane_words;
     if (c->plan.encoding == PT_BITPACK32 && c->plan.bp_generic) {
         int parities = 1;
         for (const auto &d : c->plan.desc) parities = std::max(parities, d.parities);

@@ -173,18 +173,24 @@ def test_config2_truncated(ptqmc):
         assert_same(s, 0, ref, "config2")
 
 
+@pytest.mark.parametrize("two_words", [False, True])
 @pytest.mark.parametrize("batch", ["edge", "fast", "mixed"])
 @pytest.mark.parametrize("tile_replicas,block_threads",
                          [(0, 0), (1, 64), (3, 512), (2, 1024), (4, 192), (0, 320)])
-def test_batch_launch_shapes(ptqmc, batch, tile_replicas, block_threads):
+def test_batch_launch_shapes(ptqmc, batch, tile_replicas, block_threads, two_words):
+    """Every launch shape, at the lane width the library picks for these small batches
+    (one four-slice word per lane) and with two words per lane forced."""
     insts = {"edge": edge_batch, "fast": fast_batch,
              "mixed": lambda: fast_batch()[:4] + edge_batch()[:4]}[batch]()
     seed = 0x10040023
     k, cycles = 3, 25
-    say(f"case: {batch} batch, tile_replicas={tile_replicas} block_threads={block_threads}")
+    say(f"case: {batch} batch, tile_replicas={tile_replicas} block_threads={block_threads} "
+        f"two_words={two_words}")
     refs = oracle_batch(insts, seed, k, cycles)
     with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_replicas=tile_replicas,
-                       block_threads=block_threads) as s:
+                       block_threads=block_threads,
+                       flags=ptqmc.PT_FLAG_TWO_WORD_LANES if two_words else 0) as s:
+        assert s.info()["lane_words"] == (2 if two_words else 1)
         s.run(cycles)
         for n in range(len(insts)):
             assert_same(s, n, refs[n], f"shape({tile_replicas},{block_threads})")
