@@ -181,6 +181,8 @@ def main():
                     help="spin encoding (default: bitpack for configs 3 and 4, int8 otherwise)")
     ap.add_argument("--no-work-queue", action="store_true",
                     help="bit-packed whole octets: one workgroup per octet, exchange launched apart")
+    ap.add_argument("--no-latency-path", action="store_true",
+                    help="byte tiles of small batches: sweep without forming next items ahead")
     ap.add_argument("--tau-corr", action="store_true",
                     help="also accumulate imaginary-time correlations at every exchange step")
     args = ap.parse_args()
@@ -209,7 +211,8 @@ def main():
 
     encoding = ptqmc.PT_BITPACK32 if args.encoding == "bitpack" else ptqmc.PT_INT8
     flags = (ptqmc.PT_FLAG_TAU_CORR if args.tau_corr else 0) | (
-        ptqmc.PT_FLAG_NO_WORK_QUEUE if args.no_work_queue else 0)
+        ptqmc.PT_FLAG_NO_WORK_QUEUE if args.no_work_queue else 0) | (
+        ptqmc.PT_FLAG_NO_LATENCY_PATH if args.no_latency_path else 0)
     s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags,
                       tile_bytes=args.tile_bytes, block_threads=args.block_threads,
                       encoding=encoding)
@@ -333,6 +336,8 @@ def main():
                    "tau_corr": bool(args.tau_corr),
                    "work_queue": (info["oct_queue"] > 0) if packed else None,
                    "fused_exchange": bool(info["oct_fused"]) if packed else None,
+                   "latency_path": None if packed else bool(info["latency_path"]),
+                   "lane_words": None if packed else info["lane_words"],
                    "block_resident": (bool(cal["block_resident"]) if blocked else
                                       bool(cal["oct_resident"]) if packed and cal["oct_blocks"] > 0
                                       else None),

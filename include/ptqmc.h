@@ -121,6 +121,10 @@ extern "C" {
                                           queue (which also runs an instance's exchange
                                           step in the octet that completes it); the same
                                           chain (a measurement and test hook)          */
+#define PT_FLAG_NO_LATENCY_PATH 0x400u /* fast path: sweep batches of at most one tile per
+                                          compute unit like any other instead of forming
+                                          each thread's next item during the current one
+                                          (same chain; a measurement and test hook)    */
 #define PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT 0x40u /* test hook: resident slice blocks wait for a
                                           progress count that never comes, under a tiny
                                           poll bound, so every wait gives up; the next
@@ -227,7 +231,17 @@ typedef struct {
                                          sweep (resident launches stay off after one)   */
     int32_t lane_words;               /* PT_INT8 whole-replica tiles: four-slice words per
                                          lane (2, or 1 for batches too small to give
-                                         every SIMD one wave per colour class)          */
+                                         every SIMD one wave per colour class; always 2
+                                         when an instance has 16-bit entries)           */
+    int32_t ent16_instances;          /* PT_INT8 instances whose neighbour entries are
+                                         16 bits (regular, unit |J|, replicas of more
+                                         than half a compute unit's LDS)                */
+    int32_t latency_path;             /* 1: whole-replica tiles sweep on the latency path
+                                         (at most one tile per compute unit; tiles whose
+                                         colour classes fit one pass of the workgroup
+                                         form each thread's next item, site, entries and
+                                         Philox words, while the current one is in
+                                         flight)                                        */
 } pt_info;
 
 /* Device bytes pt_init needs for these instances and options (for a caller-provided

@@ -651,6 +651,7 @@ struct pt_ctx {
     int resident_per_cu = 0;
     int block_persistent = 0;   // the last slice-block call ran as one resident launch
     int lane_words = 2;         // whole-replica tiles: four-slice words per lane
+    bool lat = false;           // whole-replica tiles: the latency path
     bool oct_resident = false;  // octet slice blocks: one resident launch per call
     // Recovery when a resident launch's wait gave up: a device copy of the state region at
     // the last clean synchronisation, the calls queued since (kind, count: 0 pt_sweep,
@@ -832,20 +833,29 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
     // colour class at that width would not give every SIMD of the device one wave; then
     // the sweep is a chain of short, barely parallel class steps, and one word per lane
     // (twice the lanes, half the dependent work each) shortens every step (measured on
-    // config 2, 2304 lanes per class: 3.6e10 attempts/s against 3.0e10).
+    // config 2, 2304 lanes per class: 3.6e10 attempts/s against 3.0e10).  Instances with
+    // 16-bit neighbour entries are swept by the two-word instantiations only, so any such
+    // instance keeps the batch at two words.
     int64_t lanes = 0;
+    bool ent16 = false;
     for (int k = 0; k < c->n_fast_tiles; ++k) {
         const Tile &t = c->tiles[k];
         const InstDesc &d = P.desc[t.inst];
+        ent16 = ent16 || d.ent_mode == kEntXad16;
         int64_t most = 0;
         for (int g = 0; g < d.n_colors; ++g)
             most = std::max<int64_t>(most, P.cls_off[d.cls_base + g + 1] - P.cls_off[d.cls_base + g]);
         lanes += (int64_t)t.P * most * std::max(1, d.G4 / 2);
     }
     c->lane_words = (c->opt.flags & PT_FLAG_FOUR_SLICE_LANES) ? 1
-                    : (c->opt.flags & PT_FLAG_TWO_WORD_LANES)  ? 2
-                    : lanes < (int64_t)c->cus * 256             ? 1
-                                                                : 2;
+                    : ((c->opt.flags & PT_FLAG_TWO_WORD_LANES) || ent16) ? 2
+                    : lanes < (int64_t)c->cus * 256 ? 1
+                                                    : 2;
+    // At most one whole-replica tile per compute unit: no other workgroup's waves overlap a
+    // tile's class steps, so the kernel forms each thread's next item while the current one
+    // is in flight (the tiles whose classes fit one pass of the workgroup).
+    c->lat = !(c->opt.flags & PT_FLAG_NO_LATENCY_PATH) && c->n_fast_tiles > 0 &&
+             c->n_fast_tiles <= c->cus;
     return PT_OK;
 }
 
@@ -1145,6 +1155,34 @@ bool whole_instance_tiles(const pt_ctx *c)
     return true;
 }
 
+// Whether the whole-replica tiles sweep on the latency path with workgroups of `threads`:
+// at most one tile per compute unit (no other workgroup overlaps a tile's class steps),
+// and in some tile every step of the pipelined order (class k of parity 0 with class k - 1
+// of parity 1) fits one pass of the workgroup, at least two classes and a degree of at
+// most eight.  The kernel checks the per-tile condition again and sweeps the other tiles
+// as usual.
+bool latency_path(const pt_ctx *c, int threads)
+{
+    if (!c->lat) return false;
+    bool any = false;
+    for (int k = 0; k < c->n_fast_tiles && !any; ++k) {
+        const Tile &t = c->tiles[k];
+        const InstDesc &d = c->plan.desc[t.inst];
+        if (d.n_colors < 2 || d.D < 1 || d.D > 8) continue;
+        const int nw = (c->lane_words == 2 && d.G4 >= 2) ? 2 : 1;
+        const int64_t lanes = (int64_t)t.P * (d.G4 / nw);  // per site
+        if (lanes > threads) continue;
+        const int32_t *off = c->plan.cls_off.data() + d.cls_base;
+        int most = 0;
+        for (int g = 0; g < d.n_colors; ++g) {
+            const int gb = (g == 0 ? d.n_colors : g) - 1;
+            most = std::max(most, off[g + 1] - off[g] + off[gb + 1] - off[gb]);
+        }
+        any = (int64_t)most * lanes <= threads;
+    }
+    return any;
+}
+
 // enqueue_sweep_once with cycles > 1 found the tiles no longer whole instances (after a
 // launch-failure fallback): nothing was queued, run the cycles one by one.
 constexpr int kCycleByCycle = 1;
@@ -1162,6 +1200,7 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange, int cycles =
         L.n_sweeps = n_sweeps;
         L.block_threads = c->block_threads;
         L.lane_words = c->lane_words;
+        L.lat = latency_path(c, c->block_threads) ? 1 : 0;
         L.fuse_exchange = fuse_exchange ? 1 : 0;
         L.swap_key0 = c->key_swap0;
         L.swap_key1 = c->key_swap1;
@@ -1954,6 +1993,9 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->oct_fused = c->oct_fuse ? 1 : 0;
     o->recoveries = c->recoveries;
     o->lane_words = c->lane_words;
+    o->latency_path = latency_path(c, c->block_threads) ? 1 : 0;
+    o->ent16_instances = 0;
+    for (const auto &d : c->plan.desc) o->ent16_instances += (d.fast && d.ent_mode == kEntXad16) ? 1 : 0;
     if (c->plan.encoding == PT_BITPACK32 && c->plan.bp_generic) {
         int parities = 1;
         for (const auto &d : c->plan.desc) parities = std::max(parities, d.parities);

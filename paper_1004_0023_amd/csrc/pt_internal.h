@@ -29,6 +29,9 @@ struct SweepLaunch {
     // fused whole-replica launches whose tiles each hold a whole instance: PT cycles run by
     // the launch (0 or 1: one)
     int32_t cycles;
+    // fast tiles: the latency path (at most one tile per compute unit; tiles whose colour
+    // classes do not fit one pass of the workgroup sweep as usual)
+    int32_t lat;
 };
 
 // Lanes per 32-slot word in the bit-packed sweep (each serves 32 / kBpSweepLanes slots).

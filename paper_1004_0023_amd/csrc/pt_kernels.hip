@@ -394,24 +394,18 @@ __device__ __forceinline__ uint32_t fast_add(uint32_t acc, uint32_t w, uint32_t 
         return (y ^ w) + acc;  // v_xad_u32
 }
 
-// One lane's update of site i, replica q, slice groups g4 .. g4 + NW - 1 of parity PAR:
-// 4 * NW Metropolis attempts served by NW Philox calls.  DT > 0 fixes the (padded) degree
-// at compile time so the neighbour loads are issued together; EM is the instance's
-// EntMode.
-template <int DT, int NW, int PAR, int EM>
-__device__ __forceinline__ void fast_item(const FastArgs &a, const TileLds &t, int D, int i,
-                                          int q, int g4)
+// A lane's own words X (slice groups g4 .. g4 + NW - 1 of parity PAR at byte offset own)
+// and their time fields: byte b of T[k] is x(2m+PAR-1) + x(2m+PAR+1), read from the other
+// parity's row at oth_row.
+template <int NW, int PAR>
+__device__ __forceinline__ void fast_own_time(const FastArgs &a, const TileLds &t, uint32_t own,
+                                              uint32_t oth_row, int g4, uint32_t (&X)[NW],
+                                              uint32_t (&T)[NW])
 {
     const int G4 = a.G4;
-    const uint32_t qbase = (uint32_t)q * a.rs;
-    const uint32_t irow = (uint32_t)i << a.lgMh;
-    const uint32_t nb_base = qbase + (uint32_t)PAR * a.NMh + 4u * (uint32_t)g4;
-    const uint32_t own = nb_base + irow;
-    const uint32_t oth_row = qbase + (uint32_t)(PAR ^ 1) * a.NMh + irow;
-    uint32_t X[NW], Wc[NW], T[NW];
+    uint32_t Wc[NW];
     ldsw<NW>(t.sp, own, X);
     ldsw<NW>(t.sp, oth_row + 4u * (uint32_t)g4, Wc);
-    // time neighbours live in the other parity: byte b of T[k] is x(2m+PAR-1) + x(2m+PAR+1)
     if constexpr (PAR == 0) {
         const uint32_t Wp = lds32(t.sp, oth_row + 4u * (uint32_t)((g4 - 1) & (G4 - 1)));
         T[0] = __builtin_amdgcn_alignbyte(Wc[0], Wp, 3) + Wc[0];
@@ -425,6 +419,47 @@ __device__ __forceinline__ void fast_item(const FastArgs &a, const TileLds &t, i
             T[0] = __builtin_amdgcn_alignbyte(Wn, Wc[0], 1) + Wc[0];
         }
     }
+}
+
+// The updated words of a lane: per slice byte, the table index 3V + tau with
+// V = x(2F+1) + f + F (f from the weighted neighbour count acc and the bias) selects the
+// replica's threshold in tb, and the byte flips when the draw is at most that threshold.
+// draw(k) gives the Philox words of word k.
+template <int NW, typename Draw>
+__device__ __forceinline__ void fast_flip(const FastArgs &a, const uint32_t *tb, const uint32_t (&X)[NW],
+                                          const uint32_t (&acc)[NW], const uint32_t (&T)[NW],
+                                          uint32_t bias, Draw draw, uint32_t (&out)[NW])
+{
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const Words4 u = draw(k);
+        const uint32_t V = __builtin_amdgcn_perm(0u, a.sel_x, X[k]) + (acc[k] << 1) + bias;
+        const uint32_t IDX = V + (V << 1) + T[k];  // 3V + tau in every byte
+        uint32_t flip = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t thr = tb[(IDX >> (8 * b)) & 0xFFu];
+            flip |= (u.w[b] <= thr ? 1u : 0u) << (8 * b);
+        }
+        out[k] = X[k] ^ flip;
+    }
+}
+
+// One lane's update of site i, replica q, slice groups g4 .. g4 + NW - 1 of parity PAR:
+// 4 * NW Metropolis attempts served by NW Philox calls.  DT > 0 fixes the (padded) degree
+// at compile time so the neighbour loads are issued together; EM is the instance's
+// EntMode.
+template <int DT, int NW, int PAR, int EM>
+__device__ __forceinline__ void fast_item(const FastArgs &a, const TileLds &t, int D, int i,
+                                          int q, int g4)
+{
+    const uint32_t qbase = (uint32_t)q * a.rs;
+    const uint32_t irow = (uint32_t)i << a.lgMh;
+    const uint32_t nb_base = qbase + (uint32_t)PAR * a.NMh + 4u * (uint32_t)g4;
+    const uint32_t own = nb_base + irow;
+    const uint32_t oth_row = qbase + (uint32_t)(PAR ^ 1) * a.NMh + irow;
+    uint32_t X[NW], T[NW];
+    fast_own_time<NW, PAR>(a, t, own, oth_row, g4, X, T);
     // weighted count of neighbours per slice byte
     const int e0 = i * D;
     uint32_t acc[NW];
@@ -449,23 +484,11 @@ __device__ __forceinline__ void fast_item(const FastArgs &a, const TileLds &t, i
             for (int k = 0; k < NW; ++k) acc[k] = fast_add<EM>(acc[k], wt, w[k]);
         }
     }
-    const uint32_t bias = t.bias[i];
-    const uint32_t *tb = t.tbl + q * a.tbl_words;
     const uint32_t ctr = ((uint32_t)(2 * i + PAR) << a.lgG4) + (uint32_t)g4;
     uint32_t out[NW];
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-        const Words4 u = philox10(ctr + (uint32_t)k, a.tt, a.c0 + (uint32_t)q, a.n, a.key0, a.key1);
-        const uint32_t V = __builtin_amdgcn_perm(0u, a.sel_x, X[k]) + (acc[k] << 1) + bias;
-        const uint32_t IDX = V + (V << 1) + T[k];  // 3V + tau in every byte
-        uint32_t flip = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t thr = tb[(IDX >> (8 * b)) & 0xFFu];
-            flip |= (u.w[b] <= thr ? 1u : 0u) << (8 * b);
-        }
-        out[k] = X[k] ^ flip;
-    }
+    fast_flip<NW>(a, t.tbl + q * a.tbl_words, X, acc, T, t.bias[i],
+                  [&](int k) { return philox10(ctr + (uint32_t)k, a.tt, a.c0 + (uint32_t)q, a.n, a.key0, a.key1); },
+                  out);
     stsw<NW>(t.sp, own, out);
 }
 
@@ -507,7 +530,174 @@ __device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d,
     }
 }
 
-template <int DT, int NW, bool WIDE>
+// ------------------------------------------------------------------ latency path
+//
+// A batch of at most one tile per compute unit leaves each tile's sweep a chain of short
+// class steps that no other workgroup overlaps.  Two things shorten that chain:
+//  * Class k of parity 0 and class k - 1 of parity 1 (k - 1 taken mod the class count, and
+//    from the previous sweep when k = 0) touch disjoint words: each writes its own sites'
+//    slices of its parity and reads the other parity only at those sites, while the classes
+//    are different, so no site is in both.  Every update still reads exactly the values it
+//    reads in the plain order (all parity-0 classes, then all parity-1 classes), so the
+//    chain is unchanged, and a sweep takes one step per class instead of two.
+//  * The spin-independent part of a thread's next item (site, neighbour entries, bias and
+//    Philox words) is formed while the current item's loads and lookups are in flight.
+// Waves with no item in a step skip it.  Needs two classes at least and every step's
+// items within one pass of the workgroup (one item per thread).
+
+// Per-thread constants: replica q and first slice group g4 of the thread's items, its site
+// slot within a step, and whether any lane of its wave has an item in a step starting at a
+// given site slot (the wave's first slot).
+struct LatLane {
+    int q, g4, s, wave_s;
+    uint32_t qbase;
+    const uint32_t *tb;
+};
+
+// The spin-independent part of a thread's item: parity par, site row irow, entries, bias
+// and draws (on = false: no item; it then stands on site 0 and stores nothing).
+template <int DT, int NW>
+struct LatItem {
+    uint32_t irow, par;
+    uint32_t off[DT], wt[DT];
+    uint32_t bias;
+    Words4 u[NW];
+    bool on;
+};
+
+// Step (sw, k) holds class k of parity 0 at sweep sw (when sw < n_sweeps) followed, in
+// lane order, by class k - 1 of parity 1 at sweep sw - [k == 0] (when that sweep is in
+// range).  Sites of the step before the thread's slot: nA of the first part, nB of both.
+struct LatStep {
+    int a0, nA, b0, nB, swB;
+};
+
+__device__ __forceinline__ LatStep lat_step(const TileLds &t, int nc, int n_sweeps, int sw, int k)
+{
+    LatStep z;
+    const int kB = (k == 0 ? nc : k) - 1;
+    z.swB = sw - (k == 0 ? 1 : 0);
+    // class bounds are the same in every lane: keep them scalar
+    z.a0 = __builtin_amdgcn_readfirstlane(t.coff[k]);
+    const int a1 = __builtin_amdgcn_readfirstlane(t.coff[k + 1]);
+    z.b0 = __builtin_amdgcn_readfirstlane(t.coff[kB]);
+    const int b1 = __builtin_amdgcn_readfirstlane(t.coff[kB + 1]);
+    z.nA = sw < n_sweeps ? a1 - z.a0 : 0;
+    z.nB = (z.swB >= 0 && z.swB < n_sweeps) ? b1 - z.b0 : 0;
+    return z;
+}
+
+template <int DT, int NW, int EM>
+__device__ __forceinline__ void lat_prep(const FastArgs &a, const TileLds &t, const LatLane &ln,
+                                         const LatStep &z, uint64_t t0, int sw, LatItem<DT, NW> &p)
+{
+    const bool inA = ln.s < z.nA;
+    p.on = ln.s < z.nA + z.nB;
+    p.par = inA ? 0u : 1u;
+    const int i = t.csite[inA ? z.a0 + ln.s : p.on ? z.b0 + ln.s - z.nA : 0];
+    const uint32_t tt = (uint32_t)(t0 + (uint64_t)(inA ? sw : z.swB));
+    p.irow = (uint32_t)i << a.lgMh;
+#pragma unroll
+    for (int e = 0; e < DT; ++e) fast_entry<EM>(t.ent, i * DT + e, p.off[e], p.wt[e]);
+    p.bias = t.bias[i];
+    const uint32_t ctr = (((uint32_t)(2 * i) + p.par) << a.lgG4) + (uint32_t)ln.g4;
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+        p.u[k] = philox10(ctr + (uint32_t)k, tt, a.c0 + (uint32_t)ln.q, a.n, a.key0, a.key1);
+}
+
+// The spin-dependent part: fast_item's update, with the parity taken per lane.
+template <int DT, int NW, int EM>
+__device__ __forceinline__ void lat_apply(const FastArgs &a, const TileLds &t, const LatLane &ln,
+                                          const LatItem<DT, NW> &p)
+{
+    const int G4 = a.G4, g4 = ln.g4;
+    const uint32_t nb_base = ln.qbase + (p.par ? a.NMh : 0u) + 4u * (uint32_t)g4;
+    const uint32_t own = nb_base + p.irow;
+    const uint32_t oth_row = ln.qbase + (p.par ? 0u : a.NMh) + p.irow;
+    uint32_t X[NW], Wc[NW], T[NW], acc[NW], ws[DT][NW], out[NW];
+    ldsw<NW>(t.sp, own, X);
+    ldsw<NW>(t.sp, oth_row + 4u * (uint32_t)g4, Wc);
+    // the other parity's word before the lane's (parity 0) or after it (parity 1)
+    const uint32_t Wx = lds32(t.sp, oth_row + 4u * (uint32_t)((g4 + (p.par ? NW : -1)) & (G4 - 1)));
+#pragma unroll
+    for (int e = 0; e < DT; ++e) ldsw<NW>(t.sp, nb_base + p.off[e], ws[e]);
+    if constexpr (NW == 2) {
+        T[0] = (p.par ? __builtin_amdgcn_alignbyte(Wc[1], Wc[0], 1)
+                      : __builtin_amdgcn_alignbyte(Wc[0], Wx, 3)) + Wc[0];
+        T[1] = (p.par ? __builtin_amdgcn_alignbyte(Wx, Wc[1], 1)
+                      : __builtin_amdgcn_alignbyte(Wc[1], Wc[0], 3)) + Wc[1];
+    } else {
+        T[0] = (p.par ? __builtin_amdgcn_alignbyte(Wx, Wc[0], 1)
+                      : __builtin_amdgcn_alignbyte(Wc[0], Wx, 3)) + Wc[0];
+    }
+#pragma unroll
+    for (int k = 0; k < NW; ++k) acc[k] = 0;
+#pragma unroll
+    for (int e = 0; e < DT; ++e)
+#pragma unroll
+        for (int k = 0; k < NW; ++k) acc[k] = fast_add<EM>(acc[k], p.wt[e], ws[e][k]);
+    fast_flip<NW>(a, ln.tb, X, acc, T, p.bias, [&](int k) { return p.u[k]; }, out);
+    if (p.on) stsw<NW>(t.sp, own, out);
+}
+
+// n_sweeps sweeps of a tile on the latency path (the caller checked that it applies).
+template <int DT, int NW, int EM>
+__device__ __forceinline__ void lat_sweeps(const FastArgs &a, const InstDesc &d, const TileLds &t,
+                                           int lgGW, int lgL, int n_sweeps, uint64_t t0)
+{
+    const int tid = threadIdx.x;
+    LatLane ln;
+    const int r = tid & ((1 << lgL) - 1);
+    ln.q = r >> lgGW;
+    ln.g4 = NW * (r & ((1 << lgGW) - 1));
+    ln.s = tid >> lgL;
+    ln.wave_s = __builtin_amdgcn_readfirstlane(tid >> lgL);  // lane 0's slot: the wave's first
+    ln.qbase = (uint32_t)ln.q * a.rs;
+    ln.tb = t.tbl + ln.q * a.tbl_words;
+    const int nc = d.n_colors;
+    const int steps = nc * n_sweeps + 1;
+    LatItem<DT, NW> cur, nxt;
+    LatStep z = lat_step(t, nc, n_sweeps, 0, 0);
+    bool wcur = ln.wave_s < z.nA + z.nB;
+    if (wcur) lat_prep<DT, NW, EM>(a, t, ln, z, t0, 0, cur);
+    int sw = 0, k = 0;
+    for (int step = 0; step < steps; ++step) {
+        if (++k == nc) {
+            k = 0;
+            ++sw;
+        }
+        z = lat_step(t, nc, n_sweeps, sw, k);
+        const bool wnext = ln.wave_s < z.nA + z.nB;
+        if (wcur && wnext) {
+            lat_prep<DT, NW, EM>(a, t, ln, z, t0, sw, nxt);
+            lat_apply<DT, NW, EM>(a, t, ln, cur);
+        } else if (wcur) {
+            lat_apply<DT, NW, EM>(a, t, ln, cur);
+        } else if (wnext) {
+            lat_prep<DT, NW, EM>(a, t, ln, z, t0, sw, nxt);
+        }
+        __syncthreads();
+        cur = nxt;
+        wcur = wnext;
+    }
+}
+
+// Whether a tile takes the latency path with this workgroup: two classes at least, and
+// every step's sites (class k plus class k - 1, cyclically) within one pass.
+__device__ __forceinline__ bool lat_fits(const InstDesc &d, const TileLds &t, int lgL)
+{
+    const int nc = d.n_colors;
+    if (nc < 2 || (1 << lgL) > (int)blockDim.x) return false;
+    int most = 0;
+    for (int k = 0; k < nc; ++k) {
+        const int kB = (k == 0 ? nc : k) - 1;
+        most = max(most, t.coff[k + 1] - t.coff[k] + t.coff[kB + 1] - t.coff[kB]);
+    }
+    return most <= ((int)blockDim.x >> lgL);
+}
+
+template <int DT, int NW, bool WIDE, bool LAT>
 __device__ __forceinline__ void fast_sweeps(const SweepLaunch &L, const InstDesc &d,
                                             const Tile &tile, const TileLds &t, uint64_t t0)
 {
@@ -525,8 +715,16 @@ __device__ __forceinline__ void fast_sweeps(const SweepLaunch &L, const InstDesc
     a.tbl_words = d.tbl_words;
     const int lgGW = ilog2(d.G4 / NW);
     const int lgL = ilog2(tile.P) + lgGW;  // lanes per site: P * G4 / NW
+    bool lat = false;
+    if constexpr (LAT && DT > 0) lat = lat_fits(d, t, lgL);
     auto run = [&](auto em) {
         constexpr int EM = decltype(em)::value;
+        if constexpr (LAT && DT > 0) {
+            if (lat) {
+                lat_sweeps<DT, NW, EM>(a, d, t, lgGW, lgL, L.n_sweeps, t0);
+                return;
+            }
+        }
         for (int sw = 0; sw < L.n_sweeps; ++sw) {
             a.tt = (uint32_t)(t0 + (uint64_t)sw);
             fast_phase<DT, NW, 0, EM>(a, d, t, lgGW, lgL);
@@ -546,20 +744,20 @@ __device__ __forceinline__ void fast_sweeps(const SweepLaunch &L, const InstDesc
 // WIDE: the instantiation carries the kEntXad16 form.  The multi-cycle kernel does not
 // (with it it would need more registers than its four waves per SIMD allow): its instances
 // fit one tile each, which kEntXad16 instances never do.
-template <int NW, bool WIDE>
+template <int NW, bool WIDE, bool LAT = false>
 __device__ __forceinline__ void fast_dispatch(const SweepLaunch &L, const InstDesc &d,
                                               const Tile &tile, const TileLds &t, uint64_t t0)
 {
     switch (d.D) {
-    case 1: fast_sweeps<1, NW, WIDE>(L, d, tile, t, t0); break;
-    case 2: fast_sweeps<2, NW, WIDE>(L, d, tile, t, t0); break;
-    case 3: fast_sweeps<3, NW, WIDE>(L, d, tile, t, t0); break;
-    case 4: fast_sweeps<4, NW, WIDE>(L, d, tile, t, t0); break;
-    case 5: fast_sweeps<5, NW, WIDE>(L, d, tile, t, t0); break;
-    case 6: fast_sweeps<6, NW, WIDE>(L, d, tile, t, t0); break;
-    case 7: fast_sweeps<7, NW, WIDE>(L, d, tile, t, t0); break;
-    case 8: fast_sweeps<8, NW, WIDE>(L, d, tile, t, t0); break;
-    default: fast_sweeps<0, NW, WIDE>(L, d, tile, t, t0); break;
+    case 1: fast_sweeps<1, NW, WIDE, LAT>(L, d, tile, t, t0); break;
+    case 2: fast_sweeps<2, NW, WIDE, LAT>(L, d, tile, t, t0); break;
+    case 3: fast_sweeps<3, NW, WIDE, LAT>(L, d, tile, t, t0); break;
+    case 4: fast_sweeps<4, NW, WIDE, LAT>(L, d, tile, t, t0); break;
+    case 5: fast_sweeps<5, NW, WIDE, LAT>(L, d, tile, t, t0); break;
+    case 6: fast_sweeps<6, NW, WIDE, LAT>(L, d, tile, t, t0); break;
+    case 7: fast_sweeps<7, NW, WIDE, LAT>(L, d, tile, t, t0); break;
+    case 8: fast_sweeps<8, NW, WIDE, LAT>(L, d, tile, t, t0); break;
+    default: fast_sweeps<0, NW, WIDE, LAT>(L, d, tile, t, t0); break;
     }
 }
 
@@ -671,8 +869,10 @@ __device__ __forceinline__ void fast_energy(const DevState &st, const InstDesc &
 
 // MULTI: a fused launch of L.cycles PT cycles (its own instantiation, bounded at four
 // waves per SIMD: the exchange step in the loop needs more registers than eight allow).
-template <bool FUSE, bool MULTI = false>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MULTI ? 4 : 8))) sweep_fast_kernel(SweepLaunch L)
+// LAT: the latency path for tiles whose colour classes fit one pass of the workgroup (its
+// own instantiation at four waves per SIMD, for batches of at most one tile per unit).
+template <bool FUSE, bool MULTI = false, bool LAT = false>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MULTI || LAT ? 4 : 8))) sweep_fast_kernel(SweepLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
@@ -690,9 +890,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(MULTI
     // the replicas' new rungs and reads the advanced sweep counter.
     for (int cyc = 0;; ++cyc) {
         if (L.lane_words == 2 && d.G4 >= 2)
-            fast_dispatch<2, !MULTI>(L, d, tile, t, t0);
+            fast_dispatch<2, !MULTI, LAT>(L, d, tile, t, t0);
         else
-            fast_dispatch<1, !MULTI>(L, d, tile, t, t0);
+            fast_dispatch<1, !MULTI, LAT>(L, d, tile, t, t0);
 
         switch (d.D) {
         case 1: fast_energy<1>(st, d, tile, t); break;
@@ -1773,6 +1973,8 @@ hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int3
         {reinterpret_cast<const void *>(&sweep_fast_kernel<false>), fast_bytes},
         {reinterpret_cast<const void *>(&sweep_fast_kernel<true>), fast_bytes},
         {reinterpret_cast<const void *>(&sweep_fast_kernel<true, true>), fast_bytes},
+        {reinterpret_cast<const void *>(&sweep_fast_kernel<false, false, true>), fast_bytes},
+        {reinterpret_cast<const void *>(&sweep_fast_kernel<true, false, true>), fast_bytes},
         {reinterpret_cast<const void *>(&sweep_generic_kernel<false>), generic_bytes},
         {reinterpret_cast<const void *>(&sweep_generic_kernel<true>), generic_bytes},
     };
@@ -1820,6 +2022,10 @@ hipError_t launch_sweep(const SweepLaunch &L, int kind, hipStream_t s)
     if (kind == kTileFast) {
         if (fuse && L.cycles > 1)
             hipLaunchKernelGGL((sweep_fast_kernel<true, true>), grid, block, L.lds_bytes, s, L);
+        else if (L.lat && fuse)
+            hipLaunchKernelGGL((sweep_fast_kernel<true, false, true>), grid, block, L.lds_bytes, s, L);
+        else if (L.lat)
+            hipLaunchKernelGGL((sweep_fast_kernel<false, false, true>), grid, block, L.lds_bytes, s, L);
         else if (fuse)
             hipLaunchKernelGGL(sweep_fast_kernel<true>, grid, block, L.lds_bytes, s, L);
         else

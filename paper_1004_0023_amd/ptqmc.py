@@ -25,6 +25,7 @@ PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT = 0x40
 PT_FLAG_TAU_CORR = 0x80
 PT_FLAG_NO_WORK_QUEUE = 0x100
 PT_FLAG_TWO_WORD_LANES = 0x200
+PT_FLAG_NO_LATENCY_PATH = 0x400
 TAU_LAGS = 8  # PT_TAU_LAGS
 PT_FLAG_SLICE_BLOCKS = 0x8
 LABEL_NONE, LABEL_UP, LABEL_DOWN = 0, 1, 2
@@ -84,7 +85,8 @@ class _Info(C.Structure):
                 ("oct_tiles", C.c_int32), ("oct_blocks", C.c_int32),
                 ("oct_tile_launches", C.c_int32), ("oct_resident", C.c_int32),
                 ("oct_queue", C.c_int32), ("oct_fused", C.c_int32), ("recoveries", C.c_int64),
-                ("lane_words", C.c_int32)]
+                ("lane_words", C.c_int32), ("ent16_instances", C.c_int32),
+                ("latency_path", C.c_int32)]
 
 
 _lib = None

@@ -148,15 +148,23 @@ def test_config1_full_run(ptqmc, block_threads):
         assert s.info()["multi_launches"] > before
 
 
-def test_config2_long_run_digest(ptqmc):
+@pytest.mark.parametrize("shape,latency", [((0, 0), None), ((1, 1024), 1), ((1, 512), 0)])
+def test_config2_long_run_digest(ptqmc, shape, latency):
     """Config 2 (N=128, M=64, R=32, exchange every 10 sweeps) for 1000 cycles (10^4
-    sweeps): the final state's digest equals the oracle's stored one."""
+    sweeps): the final state's digest equals the oracle's stored one.  With the tuned
+    launch shape, with 1024 threads per replica (the pipelined latency path: the largest
+    step of class k of parity 0 with class k - 1 of parity 1 holds 72 sites x 8 lanes) and
+    with 512 threads (too few for it: classes one by one)."""
     gold = golden.load_golden("config2")
     inst = W.config2()
     seed = W.sampler_seed(2)
     assert gold["seed"] == seed and gold["sweeps_per_exchange"] == 10
-    say(f"case: config 2, {gold['cycles']} cycles of 10 sweeps, against the stored digest")
-    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10) as s:
+    say(f"case: config 2, {gold['cycles']} cycles of 10 sweeps, shape {shape}, "
+        f"against the stored digest")
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, tile_replicas=shape[0],
+                       block_threads=shape[1]) as s:
+        if latency is not None:
+            assert s.info()["latency_path"] == latency
         s.run(gold["cycles"])
         got = golden.state_digest(s.spins(0), s.observables(0))
     assert got == gold["digests"][0]
@@ -210,6 +218,51 @@ def test_four_slice_lanes(ptqmc, tile_replicas, block_threads):
         s.run(cycles)
         for n in range(len(insts)):
             assert_same(s, n, refs[n], "four-slice lanes")
+
+
+@pytest.mark.parametrize("batch,two_words,no_latency",
+                         [("fast", False, False), ("fast", True, False), ("mixed", False, False),
+                          ("fast", False, True)])
+def test_latency_path_matches_oracle(ptqmc, batch, two_words, no_latency):
+    """Small batches at one replica and 1024 threads per workgroup, where the classes of
+    most tiles fit the pipelined latency path (one step per class: class k of parity 0
+    with class k - 1 of parity 1); the lone-spin instance has one class and sweeps class
+    by class in the same launch.  The same with the path switched off."""
+    insts = {"fast": fast_batch, "mixed": lambda: fast_batch()[:4] + edge_batch()[:4]}[batch]()
+    seed = 0x1A7E
+    k, cycles = 3, 20
+    flags = (ptqmc.PT_FLAG_TWO_WORD_LANES if two_words else 0) | (
+        ptqmc.PT_FLAG_NO_LATENCY_PATH if no_latency else 0)
+    say(f"case: latency path, {batch} batch, two_words={two_words} off={no_latency}")
+    refs = oracle_batch(insts, seed, k, cycles)
+    # one replica per tile, so that pt_run does not take the multi-cycle launches of
+    # whole-instance tiles
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, tile_replicas=1, block_threads=1024,
+                       flags=flags) as s:
+        assert s.info()["latency_path"] == (0 if no_latency else 1)
+        s.run(cycles)
+        s.sweep(5)
+        for n in range(len(insts)):
+            refs[n].sweep(5)
+            assert_same(s, n, refs[n], "latency path")
+
+
+def test_sixteen_bit_entries_in_small_batch(ptqmc):
+    """A lone large regular +-1 instance (N = 512, M = 128, degree 8: a replica of more
+    than half a compute unit's LDS, so its neighbour entries are 16 bits) with two
+    replicas: too few lanes for two words each, yet the batch keeps two-word lanes, which
+    are the only ones that read 16-bit entries."""
+    rng = np.random.default_rng([1004, 27])
+    inst = W.random_small_instance(rng, 512, 128, 2, d=8, jmax=1, hmax=1, name="ent16")
+    seed = 0x16E
+    k, cycles = 2, 3
+    say("case: 16-bit entries, N=512 M=128 R=2")
+    refs = oracle_batch([inst], seed, k, cycles)
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=k) as s:
+        info = s.info()
+        assert info["ent16_instances"] == 1 and info["lane_words"] == 2
+        s.run(cycles)
+        assert_same(s, 0, refs[0], "16-bit entries")
 
 
 def test_split_calls_graph_and_eager_agree(ptqmc):
