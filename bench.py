@@ -179,8 +179,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0)
     ap.add_argument("--encoding", choices=["int8", "bitpack"], default=None,
                     help="spin encoding (default: bitpack for configs 3 and 4, int8 otherwise)")
-    ap.add_argument("--no-work-queue", action="store_true",
-                    help="bit-packed whole octets: one workgroup per octet, exchange launched apart")
+    ap.add_argument("--work-queue", action="store_true",
+                    help="bit-packed whole octets: workgroups take octets from the device work queues")
     ap.add_argument("--no-latency-path", action="store_true",
                     help="byte tiles of small batches: sweep without forming next items ahead")
     ap.add_argument("--tau-corr", action="store_true",
@@ -211,7 +211,7 @@ def main():
 
     encoding = ptqmc.PT_BITPACK32 if args.encoding == "bitpack" else ptqmc.PT_INT8
     flags = (ptqmc.PT_FLAG_TAU_CORR if args.tau_corr else 0) | (
-        ptqmc.PT_FLAG_NO_WORK_QUEUE if args.no_work_queue else 0) | (
+        ptqmc.PT_FLAG_WORK_QUEUE if args.work_queue else 0) | (
         ptqmc.PT_FLAG_NO_LATENCY_PATH if args.no_latency_path else 0)
     s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags,
                       tile_bytes=args.tile_bytes, block_threads=args.block_threads,
@@ -334,7 +334,7 @@ def main():
                    "lds_bytes": info["lds_bytes"], "timed_route": route,
                    "encoding": args.encoding,
                    "tau_corr": bool(args.tau_corr),
-                   "work_queue": (info["oct_queue"] > 0) if packed else None,
+                   "work_queue": bool(info["oct_queue"]) if packed else None,
                    "fused_exchange": bool(info["oct_fused"]) if packed else None,
                    "latency_path": None if packed else bool(info["latency_path"]),
                    "lane_words": None if packed else info["lane_words"],

@@ -237,9 +237,11 @@ struct DevState {
     const int32_t *otiles;
     uint32_t *orec;
     int32_t *oprog;
-    // whole octets from the device work queue: the next list position and the workgroups
-    // that found the queue empty (the last of them resets both for the next launch)
+    // whole octets from the device work queues: positions taken from each XCD's queue
+    // (8 counts) and workgroups that have taken theirs (the last resets all nine for the
+    // next launch); oqitems: the queues' 9 offsets, then their list positions
     int32_t *oqueue;
+    const int32_t *oqitems;
     // mutable state
     uint8_t *spins;
     int64_t *E;       // per replica slot

@@ -75,6 +75,9 @@ struct Plan {
     std::vector<uint32_t> otbl;
     std::vector<int32_t> otiles;
     int32_t n_otile = 0, n_oblock = 0;         // whole-octet tiles, octet slice blocks
+    // the whole-octet work queues: offsets of the 8 per-XCD queues (9 ints), then each
+    // queue's list positions, largest octet first
+    std::vector<int32_t> oqitems;
     int32_t otile_lds = 0, oblock_lds = 0;     // their largest LDS need
     int32_t oblock_threads = 256;
     bool oblock_split = false;                 // slice blocks: two lanes per (site, group)
@@ -86,7 +89,7 @@ struct Plan {
     // byte offsets in the workspace
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
         o_repinst, o_halo, o_itiles, o_icount, o_prog, o_err, o_bp_sblk, o_bp_eblk, o_bp_wg,
-        o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles, o_orec, o_oprog, o_oqueue;
+        o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles, o_orec, o_oprog, o_oqueue, o_oqitems;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr, o_sumCt;
@@ -480,10 +483,19 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
             }
             std::vector<std::array<int32_t, kOctRec>> dealt;
             dealt.reserve(tiles.size());
+            std::vector<std::vector<int32_t>> pos(kXcds);
             for (size_t r = 0; dealt.size() < tiles.size(); ++r)
                 for (int x = 0; x < kXcds; ++x)
-                    if (r < q[x].size()) dealt.push_back(q[x][r]);
+                    if (r < q[x].size()) {
+                        pos[x].push_back((int32_t)dealt.size());
+                        dealt.push_back(q[x][r]);
+                    }
             tiles.swap(dealt);
+            // the same queues for the work-queue launch, whose workgroups take positions
+            // from their own XCD's queue
+            P.oqitems.assign(kXcds + 1, 0);
+            for (int x = 0; x < kXcds; ++x) P.oqitems[x + 1] = P.oqitems[x] + (int32_t)pos[x].size();
+            for (int x = 0; x < kXcds; ++x) P.oqitems.insert(P.oqitems.end(), pos[x].begin(), pos[x].end());
         }
         for (size_t k = 0; k < blocks.size(); ++k) {
             auto &t = blocks[k];
@@ -550,7 +562,8 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
     P.o_otiles = take(P.otiles.size() * 4);
     P.o_orec = take((size_t)P.orec_words * 2 * 4);
     P.o_oprog = take((size_t)(P.n_otile + P.n_oblock) * 2 * 4);
-    P.o_oqueue = take(2 * 4);  // zero in the uploaded image
+    P.o_oqueue = take(9 * 4);  // zero in the uploaded image
+    P.o_oqitems = take(P.oqitems.size() * 4);
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
     P.o_E = take((size_t)rep * 8);
@@ -663,8 +676,6 @@ struct pt_ctx {
     // whole octets from the device work queue; the exchange fused into the octet that
     // completes an instance (every instance of the batch in whole octets)
     bool oct_queue = false, oct_fuse = false;
-    std::pair<int, int> oct_queue_key{-1, -1};  // (threads, LDS) of oct_queue_grid
-    int32_t oct_queue_grid = 0;
     int block_threads = 256;
     int tile_bytes = 0;        // target spin bytes per tile in use
     // self-tuning: candidate (tile bytes, threads) shapes timed on the first sweep launches
@@ -1006,6 +1017,9 @@ int sync_and_check(pt_ctx *c)
         if (err & kErrLdsBase)
             return fail(PT_ESTATE, "an octet kernel found its dynamic LDS away from address 0 "
                                    "and did not run; the state is inconsistent");
+        if (err & kErrQueue)
+            return fail(PT_ESTATE, "a whole-octet workgroup found every work queue empty; the "
+                                   "state is inconsistent");
         if (c->shadow && !c->replaying) return recover(c);
         return fail(PT_ESTATE, "a resident slice-block launch waited too long for its "
                                "neighbouring blocks; the state is inconsistent");
@@ -1025,19 +1039,6 @@ hipError_t energies_from_spins(pt_ctx *c, int rep_first, int n)
 
 // Whole octets from the device work queue: as many workgroups as the compute units hold at
 // once for the current block size (at most one per octet).
-hipError_t oct_queue_shape(pt_ctx *c)
-{
-    const Plan &P = c->plan;
-    const auto key = std::make_pair(c->block_threads, P.otile_lds);
-    if (c->oct_queue_key == key) return hipSuccess;
-    int32_t per_cu = 0;
-    const hipError_t e = oct_tile_per_cu(key.first, key.second, &per_cu);
-    if (e != hipSuccess) return e;
-    c->oct_queue_key = key;
-    c->oct_queue_grid = std::min<int32_t>(P.n_otile, std::max(1, per_cu) * c->cus);
-    return hipSuccess;
-}
-
 // Bit-packed encoding: n_sweeps sweeps as one launch per colour class (parity, colour) of
 // every instance, then E_cl and C of every replica.
 int enqueue_bp_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
@@ -1063,20 +1064,14 @@ int enqueue_bp_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
         O.n_tiles = P.n_otile;
         O.threads = c->block_threads;
         O.lds_bytes = P.otile_lds;
-        int32_t grid = P.n_otile;
-        if (c->oct_queue) {
-            const hipError_t e = oct_queue_shape(c);
-            if (e != hipSuccess) return hip_fail(e, "octet occupancy query");
-            O.queue = 1;
-            grid = c->oct_queue_grid;
-        }
+        O.queue = c->oct_queue ? 1 : 0;
         if (fuse_exchange) {
             O.fuse = 1;
             O.swap_key0 = c->key_swap0;
             O.swap_key1 = c->key_swap1;
             O.t_add = (uint32_t)n_sweeps;
         }
-        const hipError_t e = launch_oct_tiles(O, grid, c->stream);
+        const hipError_t e = launch_oct_tiles(O, c->stream);
         if (e != hipSuccess) return hip_fail(e, "octet tile launch");
         O.queue = O.fuse = 0;
     }
@@ -1542,6 +1537,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.orec = (uint32_t *)(w + P.o_orec);
     st.oprog = (int32_t *)(w + P.o_oprog);
     st.oqueue = (int32_t *)(w + P.o_oqueue);
+    st.oqitems = (const int32_t *)(w + P.o_oqitems);
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;
@@ -1572,6 +1568,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     put(P.o_ohinfo, P.ohinfo.data(), P.ohinfo.size());
     put(P.o_otbl, P.otbl.data(), P.otbl.size() * 4);
     put(P.o_otiles, P.otiles.data(), P.otiles.size() * 4);
+    put(P.o_oqitems, P.oqitems.data(), P.oqitems.size() * 4);
     for (int n = 0; n < n_inst; ++n) {
         const InstDesc &d = P.desc[n];
         for (int r = 0; r < d.R; ++r) {
@@ -1602,10 +1599,10 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
             return cleanup(fail(PT_EINVAL, "octet work needs more LDS than the device has"));
         e = oct_kernels_set_lds(P.otile_lds, P.oblock_lds, P.oblock_res_lds);
         if (e != hipSuccess) return cleanup(hip_fail(e, "octet kernel LDS attribute"));
-        // whole octets from the device work queue, and the exchange step in the octet that
-        // completes an instance when every instance is in whole octets
-        c->oct_queue = P.n_otile > 0 && !(opt->flags & PT_FLAG_NO_WORK_QUEUE);
-        c->oct_fuse = c->oct_queue && P.n_oblock == 0 && !P.bp_generic;
+        // whole octets in list order (or from the device work queues), and the exchange step
+        // in the octet that completes an instance when every instance is in whole octets
+        c->oct_queue = P.n_otile > 0 && (opt->flags & PT_FLAG_WORK_QUEUE);
+        c->oct_fuse = P.n_otile > 0 && P.n_oblock == 0 && !P.bp_generic;
         if (c->oct_fuse) {
             c->itiles.assign(P.desc.size(), 0);
             for (int32_t k = 0; k < P.n_otile; ++k) c->itiles[P.otiles[(size_t)k * kOctRec]] += 1;
@@ -1624,10 +1621,6 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     }
     if (P.encoding == PT_BITPACK32) {
         c->block_threads = opt->block_threads > 0 ? opt->block_threads : 256;
-        if (c->oct_queue) {
-            e = oct_queue_shape(c);
-            if (e != hipSuccess) return cleanup(hip_fail(e, "octet occupancy query"));
-        }
     }
     const bool tune_int8 = P.encoding == PT_INT8 && opt->tile_replicas == 0 &&
                            opt->tile_bytes == 0 && opt->block_threads == 0;
@@ -1989,7 +1982,7 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->oct_blocks = c->plan.n_oblock;
     o->oct_tile_launches = c->plan.n_otile > 0 ? 1 : 0;
     o->oct_resident = c->oct_resident ? 1 : 0;
-    o->oct_queue = c->oct_queue ? c->oct_queue_grid : 0;
+    o->oct_queue = c->oct_queue ? 1 : 0;
     o->oct_fused = c->oct_fuse ? 1 : 0;
     o->recoveries = c->recoveries;
     o->lane_words = c->lane_words;

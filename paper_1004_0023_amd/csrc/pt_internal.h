@@ -64,8 +64,8 @@ struct OctLaunch {
     int32_t tile0, n_tiles, threads, lds_bytes;
     int32_t n_sweeps, sweep_off, p, last;
     int32_t split;      // slice blocks: two lanes per (site, group), four slots each
-    // whole octets: queue = the workgroups take octets from the device work queue
-    // (DevState::oqueue) in list order until it runs dry; fuse = the octet that completes
+    // whole octets: queue = each workgroup takes its octet from the device work queues
+    // (DevState::oqitems, counts in oqueue) when it starts; fuse = the octet that completes
     // an instance (DevState::icount against itiles) then runs its exchange step
     int32_t queue, fuse;
     uint32_t swap_key0, swap_key1, t_add;
@@ -81,6 +81,7 @@ enum OctMode { kOctTile = 0, kOctPhase = 1, kOctResident = 2 };
 // Bits of the device error word (DevState::err), read and cleared by the host after a call.
 constexpr uint32_t kErrWait = 1u;     // a resident slice block gave up waiting for a neighbour
 constexpr uint32_t kErrLdsBase = 2u;  // an octet kernel found its dynamic LDS away from address 0
+constexpr uint32_t kErrQueue = 4u;    // a whole-octet workgroup found every work queue empty
 
 // Each returns the hipError_t of the launch itself (asynchronous execution errors
 // surface at the next synchronisation).
@@ -103,7 +104,7 @@ hipError_t launch_bp_init(const DevState &st, int32_t n_eblk, uint32_t key0, uin
                           hipStream_t s);
 hipError_t launch_bp_sweep(const BpLaunch &L, hipStream_t s);
 hipError_t launch_bp_energy(const DevState &st, int32_t n_eblk, int32_t n_reps, hipStream_t s);
-hipError_t launch_oct_tiles(const OctLaunch &L, int32_t grid, hipStream_t s);
+hipError_t launch_oct_tiles(const OctLaunch &L, hipStream_t s);
 hipError_t launch_oct_phase(const OctLaunch &L, hipStream_t s);
 hipError_t launch_oct_resident(const OctLaunch &L, hipStream_t s);
 // E_cl and C of the replicas of octet work items [tile0, tile0 + n_tiles) set to zero (the
@@ -117,9 +118,8 @@ hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes, int32_t 
 // Resident octet slice blocks of `threads` threads and `lds_bytes` of LDS that one compute
 // unit holds at once.
 hipError_t oct_resident_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu);
-// Whole-octet workgroups (queue mode) that one compute unit holds at once.
-hipError_t oct_tile_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu);
-// LDS bytes the queue mode adds after the largest octet (the pulled index and a flag).
+// LDS bytes the whole-octet kernel adds after the largest octet (the taken list position
+// and a flag).
 constexpr int32_t kOctQueueLds = 16;
 hipError_t launch_threshold_eval(const double *dS, uint32_t *out, int32_t n, hipStream_t s);
 hipError_t sweep_kernels_set_lds(int32_t fast_bytes, int32_t generic_bytes, int32_t block_bytes);

@@ -589,13 +589,37 @@ __device__ __forceinline__ void oct_tile_item(const OctLaunch &L, char *lds, int
     if (ld32(flag)) exchange_instance<true>(st, n, L.swap_key0, L.swap_key1, L.t_add);
 }
 
-// Whole octets.  Without the queue, workgroup b takes list position tile0 + b.  With it
-// (QUEUE), as many workgroups as the compute units hold take positions from the device work
-// queue in list order (largest first) until it runs dry.  The queue's loop keeps more state
-// live across an octet's sweeps: that instantiation is held to four waves per SIMD (at
-// eight it spills to scratch).
-template <bool QUEUE>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(QUEUE ? 4 : 8))) oct_tile_kernel(OctLaunch L)
+// The list position a workgroup of a work-queue launch sweeps: the next one of its XCD's
+// queue (the word groups were dealt to the XCDs' queues largest first, so that the octets
+// of a word group share one L2), else of the next XCD's queue that has one left.  The launch
+// has one workgroup per position, so each finds one.  The last workgroup to take its
+// position resets the counts for the next launch (every other has taken its own by then).
+// Returns -1 only if every queue was empty.
+__device__ __forceinline__ int oct_ticket(const DevState &st, int grid)
+{
+    const int x0 = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7;  // XCC_ID (4 bits)
+    const int32_t *q = st.oqitems;
+    int got = -1;
+    for (int j = 0; j < 8 && got < 0; ++j) {
+        const int x = (x0 + j) & 7;
+        const int len = q[x + 1] - q[x];
+        if (__hip_atomic_load(&st.oqueue[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len)
+            continue;
+        const int t = __hip_atomic_fetch_add(&st.oqueue[x], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t < len) got = q[9 + q[x] + t];
+    }
+    if (__hip_atomic_fetch_add(&st.oqueue[8], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == grid - 1)
+        for (int x = 0; x < 9; ++x)
+            __hip_atomic_store(&st.oqueue[x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return got;
+}
+
+// Whole octets, one workgroup each.  Workgroup b sweeps list position tile0 + b: the
+// hardware hands workgroups to each XCD in index order as its units free up, and the list
+// is dealt to the XCDs largest first, so that order already runs the largest octets first.
+// With L.queue the workgroup instead takes its position from the work queues as it starts
+// (each start then waits for device-scope atomics).
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) oct_tile_kernel(OctLaunch L)
 {
     extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
@@ -603,31 +627,21 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(QUEUE
         if (threadIdx.x == 0) atomicOr(st.err, kErrLdsBase);
         return;
     }
-    // two LDS words past every octet's layout: the pulled position and the exchange flag
+    // two LDS words past every octet's layout: the taken position and the exchange flag
     const uint32_t slot = (uint32_t)L.lds_bytes - (uint32_t)kOctQueueLds;
-    auto pull = [&]() {
-        if (threadIdx.x == 0)
-            st32(slot, (uint32_t)__hip_atomic_fetch_add(&st.oqueue[0], 1, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT));
+    int k = (int)blockIdx.x;
+    if (L.queue) {
+        if (threadIdx.x == 0) st32(slot, (uint32_t)oct_ticket(st, (int)gridDim.x));
         __syncthreads();
-        const int k = (int)ld32(slot);
-        __syncthreads();
-        return k;
-    };
-    if constexpr (!QUEUE) {
-        (void)pull;
-        oct_tile_item(L, lds, L.tile0 + (int)blockIdx.x, slot + 4u);
-        return;
+        // the same in every lane: scalar, so that everything derived from the octet's
+        // record (its instance descriptor above all) stays in scalar registers
+        k = __builtin_amdgcn_readfirstlane((int)ld32(slot));
+        if (k < 0) {
+            if (threadIdx.x == 0) atomicOr(st.err, kErrQueue);
+            return;
+        }
     }
-    for (int k = pull(); k < L.n_tiles; k = pull()) oct_tile_item(L, lds, L.tile0 + k, slot + 4u);
-    // the last workgroup to find the queue empty resets it: every other one has made its
-    // last pull by then
-    if (threadIdx.x == 0 &&
-        __hip_atomic_fetch_add(&st.oqueue[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-            (int)gridDim.x - 1) {
-        __hip_atomic_store(&st.oqueue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&st.oqueue[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    oct_tile_item(L, lds, L.tile0 + k, slot + 4u);
 }
 
 // ------------------------------------------------------------------ slice blocks
@@ -960,10 +974,7 @@ hipError_t oct_kernels_set_lds(int32_t tile_bytes, int32_t phase_bytes, int32_t 
 {
     hipError_t e = hipSuccess;
     if (tile_bytes > 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_tile_kernel<false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, tile_bytes);
-    if (e == hipSuccess && tile_bytes > 0)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_tile_kernel<true>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_tile_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, tile_bytes);
     if (e == hipSuccess && phase_bytes > 0)
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&oct_phase_kernel),
@@ -990,23 +1001,10 @@ hipError_t launch_oct_resident(const OctLaunch &L, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t oct_tile_per_cu(int32_t threads, int32_t lds_bytes, int32_t *per_cu)
-{
-    int n = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void *>(&oct_tile_kernel<true>), threads, (size_t)lds_bytes);
-    *per_cu = n;
-    return e;
-}
-
-// grid: the workgroups of a queue launch (n_tiles otherwise)
-hipError_t launch_oct_tiles(const OctLaunch &L, int32_t grid, hipStream_t s)
+hipError_t launch_oct_tiles(const OctLaunch &L, hipStream_t s)
 {
     if (L.n_tiles <= 0 || L.n_sweeps <= 0) return hipSuccess;
-    if (L.queue)
-        hipLaunchKernelGGL(oct_tile_kernel<true>, dim3(grid), dim3(L.threads), L.lds_bytes, s, L);
-    else
-        hipLaunchKernelGGL(oct_tile_kernel<false>, dim3(L.n_tiles), dim3(L.threads), L.lds_bytes, s, L);
+    hipLaunchKernelGGL(oct_tile_kernel, dim3(L.n_tiles), dim3(L.threads), L.lds_bytes, s, L);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ PT_FLAG_FOUR_SLICE_LANES = 0x10
 PT_FLAG_BLOCK_LAUNCH_PER_SWEEP = 0x20
 PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT = 0x40
 PT_FLAG_TAU_CORR = 0x80
-PT_FLAG_NO_WORK_QUEUE = 0x100
+PT_FLAG_WORK_QUEUE = 0x100
 PT_FLAG_TWO_WORD_LANES = 0x200
 PT_FLAG_NO_LATENCY_PATH = 0x400
 TAU_LAGS = 8  # PT_TAU_LAGS

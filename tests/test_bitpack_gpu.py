@@ -228,21 +228,21 @@ def test_octet_kernels_match_oracle(ptqmc, graph, per_sweep):
 
 @pytest.mark.parametrize("queue", [True, False])
 def test_whole_octet_cycles_match_oracle(ptqmc, queue):
-    """A batch whose instances are all whole octets: with the device work queue a PT cycle
-    is one launch, the octet that completes an instance running its exchange step; without
-    it, one workgroup per octet and a separate exchange launch.  Three replays of the
-    16-cycle graph with eager sweeps and exchanges between them, each against the oracle."""
+    """A batch whose instances are all whole octets: a PT cycle is one launch, the octet
+    that completes an instance running its exchange step, with workgroups in list order
+    and taking octets from the device work queues.  Three replays of the 16-cycle graph
+    with eager sweeps and exchanges between them, each against the oracle."""
     insts = octet_batch()[:4]
     seed = 0x0C7E8
     k = 2
-    flags = 0 if queue else ptqmc.PT_FLAG_NO_WORK_QUEUE
+    flags = ptqmc.PT_FLAG_WORK_QUEUE if queue else 0
     say(f"case: whole octets, graph replays, queue={queue}")
     refs = [oracle.OracleChain(inst, seed, index=n) for n, inst in enumerate(insts)]
     with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, encoding=ptqmc.PT_BITPACK32,
                        flags=flags, block_threads=256) as s:
         info = s.info()
         assert info["oct_tiles"] > 0 and info["oct_blocks"] == 0 and info["class_launches"] == 0
-        assert (info["oct_queue"] > 0) == queue and info["oct_fused"] == (1 if queue else 0)
+        assert info["oct_queue"] == (1 if queue else 0) and info["oct_fused"] == 1
         for rep in range(3):
             s.run(16)
             s.sync()

@@ -382,24 +382,24 @@ def test_config3_full_batch_digests(ptqmc, config3_batch, tile_bytes, block_thre
     assert not bad, f"{len(bad)} instances differ from the oracle, first {bad[:8]}"
 
 
-@pytest.mark.parametrize("block_threads,queue", [(1024, True), (256, False), (0, True)])
+@pytest.mark.parametrize("block_threads,queue", [(1024, False), (256, True), (0, False)])
 def test_config3_bitpack_digests(ptqmc, config3_batch, block_threads, queue):
     """The batched workload in the bit-packed encoding (every instance whole octets) for
-    the stored 16 cycles: with the device work queue and the exchange run by the octet
-    that completes each instance (the benchmark's route at its tuned 1024 threads, and
-    under the tuner), and with one workgroup per octet and separate exchange launches.
+    the stored 16 cycles, a PT cycle one launch with the exchange run by the octet that
+    completes each instance: workgroups in list order (the benchmark's route at its tuned
+    1024 threads, and under the tuner) and taking octets from the device work queues.
     Every instance's final state has the oracle's digest."""
     gold = golden.load_golden("config3")
     insts = config3_batch
     seed = W.sampler_seed(3)
     k, cycles = gold["sweeps_per_exchange"], gold["cycles"]
-    flags = 0 if queue else ptqmc.PT_FLAG_NO_WORK_QUEUE
+    flags = ptqmc.PT_FLAG_WORK_QUEUE if queue else 0
     say(f"case: config 3 bit-packed, {cycles} cycles, block_threads={block_threads} queue={queue}")
     with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, encoding=ptqmc.PT_BITPACK32,
                        block_threads=block_threads, flags=flags) as s:
         info = s.info()
         assert info["oct_tiles"] > 0 and info["oct_blocks"] == 0 and info["class_launches"] == 0
-        assert info["oct_fused"] == (1 if queue else 0)
+        assert info["oct_fused"] == 1 and info["oct_queue"] == (1 if queue else 0)
         if block_threads:
             s.run(cycles)
         else:
