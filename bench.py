@@ -181,6 +181,8 @@ def main():
                     help="spin encoding (default: bitpack for configs 3 and 4, int8 otherwise)")
     ap.add_argument("--work-queue", action="store_true",
                     help="bit-packed whole octets: workgroups take octets from the device work queues")
+    ap.add_argument("--device-scope-records", action="store_true",
+                    help="resident octet slice blocks: records through device-scope operations")
     ap.add_argument("--no-latency-path", action="store_true",
                     help="byte tiles of small batches: sweep without forming next items ahead")
     ap.add_argument("--tau-corr", action="store_true",
@@ -212,7 +214,8 @@ def main():
     encoding = ptqmc.PT_BITPACK32 if args.encoding == "bitpack" else ptqmc.PT_INT8
     flags = (ptqmc.PT_FLAG_TAU_CORR if args.tau_corr else 0) | (
         ptqmc.PT_FLAG_WORK_QUEUE if args.work_queue else 0) | (
-        ptqmc.PT_FLAG_NO_LATENCY_PATH if args.no_latency_path else 0)
+        ptqmc.PT_FLAG_NO_LATENCY_PATH if args.no_latency_path else 0) | (
+        ptqmc.PT_FLAG_DEVICE_SCOPE_RECORDS if args.device_scope_records else 0)
     s = ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags,
                       tile_bytes=args.tile_bytes, block_threads=args.block_threads,
                       encoding=encoding)
@@ -336,6 +339,7 @@ def main():
                    "tau_corr": bool(args.tau_corr),
                    "work_queue": bool(info["oct_queue"]) if packed else None,
                    "fused_exchange": bool(info["oct_fused"]) if packed else None,
+                   "ring_xcd": bool(info["oct_ring_xcd"]) if packed else None,
                    "latency_path": None if packed else bool(info["latency_path"]),
                    "lane_words": None if packed else info["lane_words"],
                    "block_resident": (bool(cal["block_resident"]) if blocked else

@@ -127,6 +127,10 @@ extern "C" {
                                           compute unit like any other instead of forming
                                           each thread's next item during the current one
                                           (same chain; a measurement and test hook)    */
+#define PT_FLAG_DEVICE_SCOPE_RECORDS 0x800u /* resident octet slice blocks: pass boundary
+                                          records with device-scope operations even
+                                          when every ring of blocks sits on one XCD (same
+                                          chain; a measurement and test hook)          */
 #define PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT 0x40u /* test hook: resident slice blocks wait for a
                                           progress count that never comes, under a tiny
                                           poll bound, so every wait gives up; the next
@@ -228,6 +232,12 @@ typedef struct {
     int32_t oct_fused;                /* 1: a PT cycle of the batch is one launch, the
                                          exchange step run by the octet that completes
                                          each instance                                  */
+    int32_t oct_ring_xcd;             /* 1: resident octet slice blocks take their work
+                                         from per-XCD lists, every ring of blocks on one
+                                         XCD, and pass boundary records through that
+                                         XCD's L2 (a block that has to take work from
+                                         another XCD's list fails the call, which then
+                                         recovers as after a wait that gave up)         */
     int64_t recoveries;               /* synchronising calls that found a resident
                                          launch's wait given up, restored the state of
                                          the last clean synchronisation and replayed
@@ -240,6 +250,12 @@ typedef struct {
     int32_t ent16_instances;          /* PT_INT8 instances whose neighbour entries are
                                          16 bits (regular, unit |J|, replicas of more
                                          than half a compute unit's LDS)                */
+    uint32_t last_device_error;       /* the device error word the last failed
+                                         synchronisation found (0: none): 1 a resident
+                                         wait gave up, 2 an octet kernel found its LDS
+                                         away from address 0, 4 a whole-octet workgroup
+                                         found the work queues empty, 8 a resident block
+                                         took its work from another XCD's list          */
     int32_t latency_path;             /* 1: whole-replica tiles sweep on the latency path
                                          (at most one tile per compute unit; tiles whose
                                          colour classes fit one pass of the workgroup

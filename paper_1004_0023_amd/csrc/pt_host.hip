@@ -78,6 +78,10 @@ struct Plan {
     // the whole-octet work queues: offsets of the 8 per-XCD queues (9 ints), then each
     // queue's list positions, largest octet first
     std::vector<int32_t> oqitems;
+    // resident octet slice blocks: every ring of blocks dealt whole to one XCD's list
+    // (offsets of the 8 lists, then their block positions)
+    bool oblock_xcd = false;
+    std::vector<int32_t> oblock_xq;
     int32_t otile_lds = 0, oblock_lds = 0;     // their largest LDS need
     int32_t oblock_threads = 256;
     bool oblock_split = false;                 // slice blocks: two lanes per (site, group)
@@ -89,7 +93,8 @@ struct Plan {
     // byte offsets in the workspace
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
         o_repinst, o_halo, o_itiles, o_icount, o_prog, o_err, o_bp_sblk, o_bp_eblk, o_bp_wg,
-        o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles, o_orec, o_oprog, o_oqueue, o_oqitems;
+        o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles, o_orec, o_oprog, o_oqueue, o_oqitems,
+        o_oxq;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr, o_sumCt;
@@ -451,7 +456,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
                         // the list; neighbours and record offsets are filled in below
                         for (int g0 = 0; g0 < d.G4; g0 += ng) blocks.push_back({n, w, o, g0, ng, 0, 0, 0});
                         P.oblock_lds = std::max(P.oblock_lds, oct_lds_bytes(d, ng, kOctPhase));
-                        P.oblock_res_lds = std::max(P.oblock_res_lds, oct_lds_bytes(d, ng, kOctResident));
+                        P.oblock_res_lds = std::max(P.oblock_res_lds, oct_lds_bytes(d, ng, kOctResident) + kOctQueueLds);
                     }
                 }
         }
@@ -497,16 +502,67 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
             for (int x = 0; x < kXcds; ++x) P.oqitems[x + 1] = P.oqitems[x] + (int32_t)pos[x].size();
             for (int x = 0; x < kXcds; ++x) P.oqitems.insert(P.oqitems.end(), pos[x].begin(), pos[x].end());
         }
+        // Resident slice blocks pass boundary records to their ring neighbours twice per
+        // sweep.  When the rings can be dealt to the 8 XCDs whole, each XCD taking exactly an
+        // eighth of the blocks, every block of the resident launch takes its slice block from
+        // its own XCD's list as it starts, so each ring runs on one XCD and the records pass
+        // through that XCD's L2 instead of device-scope operations.
+        const int base = (int)tiles.size();  // blocks follow the tiles in the list
+        std::vector<int32_t> prev(blocks.size()), next(blocks.size());
+        for (size_t k = 0; k < blocks.size(); ++k) {
+            const auto &t = blocks[k];
+            const int ring = P.desc[t[0]].G4 / t[4];   // blocks of the octet
+            const int first = (int)k - t[3] / t[4];    // its block at group 0
+            prev[k] = first + (t[3] / t[4] + ring - 1) % ring;
+            next[k] = first + (t[3] / t[4] + 1) % ring;
+        }
+        P.oblock_xcd = false;
+        P.oblock_xq.clear();
+        if (!blocks.empty() && blocks.size() % 8 == 0) {
+            constexpr int kXcds = 8;
+            const int nb = (int)blocks.size();
+            std::vector<std::pair<int, int>> rings;  // [first, end) in blocks
+            for (int k = 0; k < nb;) {
+                int e = k + 1;
+                while (e < nb && blocks[e][0] == blocks[k][0] && blocks[e][1] == blocks[k][1] &&
+                       blocks[e][2] == blocks[k][2])
+                    ++e;
+                rings.emplace_back(k, e);
+                k = e;
+            }
+            std::vector<int> cap(kXcds, nb / kXcds), order(rings.size());
+            for (size_t r = 0; r < rings.size(); ++r) order[r] = (int)r;
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+                return rings[x].second - rings[x].first > rings[y].second - rings[y].first;
+            });
+            std::vector<std::vector<int32_t>> lists(kXcds);
+            bool ok = true;
+            for (int r : order) {
+                const int sz = rings[r].second - rings[r].first;
+                int best = -1;
+                for (int x = 0; x < kXcds; ++x)
+                    if (cap[x] >= sz && (best < 0 || cap[x] > cap[best])) best = x;
+                if (best < 0) {
+                    ok = false;
+                    break;
+                }
+                cap[best] -= sz;
+                for (int k = rings[r].first; k < rings[r].second; ++k) lists[best].push_back(k);
+            }
+            if (ok) {
+                P.oblock_xq.assign(kXcds + 1, 0);
+                for (int x = 0; x < kXcds; ++x) P.oblock_xq[x + 1] = P.oblock_xq[x] + (int32_t)lists[x].size();
+                for (int x = 0; x < kXcds; ++x)
+                    P.oblock_xq.insert(P.oblock_xq.end(), lists[x].begin(), lists[x].end());
+                P.oblock_xcd = true;
+            }
+        }
         for (size_t k = 0; k < blocks.size(); ++k) {
             auto &t = blocks[k];
-            const InstDesc &d = P.desc[t[0]];
-            const int ring = d.G4 / t[4];              // blocks of the octet
-            const int first = (int)k - t[3] / t[4];    // its block at group 0
-            const int base = (int)tiles.size();        // blocks follow the tiles in the list
             t[5] = (int32_t)P.orec_words;
-            t[6] = base + first + (t[3] / t[4] + ring - 1) % ring;
-            t[7] = base + first + (t[3] / t[4] + 1) % ring;
-            P.orec_words += d.N;
+            t[6] = base + prev[k];
+            t[7] = base + next[k];
+            P.orec_words += P.desc[t[0]].N;
         }
         for (const auto &t : tiles) P.otiles.insert(P.otiles.end(), t.begin(), t.end());
         for (const auto &t : blocks) P.otiles.insert(P.otiles.end(), t.begin(), t.end());
@@ -562,8 +618,9 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
     P.o_otiles = take(P.otiles.size() * 4);
     P.o_orec = take((size_t)P.orec_words * 2 * 4);
     P.o_oprog = take((size_t)(P.n_otile + P.n_oblock) * 2 * 4);
-    P.o_oqueue = take(9 * 4);  // zero in the uploaded image
+    P.o_oqueue = take(18 * 4);  // zero in the uploaded image
     P.o_oqitems = take(P.oqitems.size() * 4);
+    P.o_oxq = take(P.oblock_xq.size() * 4);
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
     P.o_E = take((size_t)rep * 8);
@@ -673,6 +730,7 @@ struct pt_ctx {
     std::vector<std::pair<int, int>> journal;
     bool replaying = false, resident_off = false;
     int64_t recoveries = 0;
+    uint32_t last_device_error = 0;  // the device error word of the last failed synchronisation
     // whole octets from the device work queue; the exchange fused into the octet that
     // completes an instance (every instance of the batch in whole octets)
     bool oct_queue = false, oct_fuse = false;
@@ -1012,11 +1070,16 @@ int sync_and_check(pt_ctx *c)
     uint32_t err = 0;
     HIP_TRY(hipMemcpy(&err, c->ws + c->plan.o_err, 4, hipMemcpyDeviceToHost));
     if (err != 0) {
+        c->last_device_error = err;
         const uint32_t zero = 0;
         HIP_TRY(hipMemcpy(c->ws + c->plan.o_err, &zero, 4, hipMemcpyHostToDevice));
         if (err & kErrLdsBase)
             return fail(PT_ESTATE, "an octet kernel found its dynamic LDS away from address 0 "
                                    "and did not run; the state is inconsistent");
+        if ((err & kErrPlace) && c->shadow && !c->replaying) return recover(c);
+        if (err & kErrPlace)
+            return fail(PT_ESTATE, "a resident slice block took its work from another XCD's "
+                                   "list; the state is inconsistent");
         if (err & kErrQueue)
             return fail(PT_ESTATE, "a whole-octet workgroup found every work queue empty; the "
                                    "state is inconsistent");
@@ -1039,6 +1102,14 @@ hipError_t energies_from_spins(pt_ctx *c, int rep_first, int n)
 
 // Whole octets from the device work queue: as many workgroups as the compute units hold at
 // once for the current block size (at most one per octet).
+// Resident octet slice blocks pass their records through the L2 of the XCD that holds
+// their ring (the rings were placed one per XCD).
+bool oct_ring_xcd(const pt_ctx *c)
+{
+    return c->oct_resident && c->plan.oblock_xcd &&
+           !(c->opt.flags & PT_FLAG_DEVICE_SCOPE_RECORDS);
+}
+
 // Bit-packed encoding: n_sweeps sweeps as one launch per colour class (parity, colour) of
 // every instance, then E_cl and C of every replica.
 int enqueue_bp_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
@@ -1086,6 +1157,7 @@ int enqueue_bp_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
         if (c->oct_resident) {
             O.lds_bytes = P.oblock_res_lds;
             O.rec_words = (int32_t)P.orec_words;
+            O.xcd_local = oct_ring_xcd(c) ? 1 : 0;
             if (c->opt.flags & PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT) {
                 O.wait_polls = 16;
                 O.wait_extra = 1 << 30;
@@ -1538,6 +1610,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.oprog = (int32_t *)(w + P.o_oprog);
     st.oqueue = (int32_t *)(w + P.o_oqueue);
     st.oqitems = (const int32_t *)(w + P.o_oqitems);
+    st.oxq = (const int32_t *)(w + P.o_oxq);
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;
@@ -1569,6 +1642,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     put(P.o_otbl, P.otbl.data(), P.otbl.size() * 4);
     put(P.o_otiles, P.otiles.data(), P.otiles.size() * 4);
     put(P.o_oqitems, P.oqitems.data(), P.oqitems.size() * 4);
+    put(P.o_oxq, P.oblock_xq.data(), P.oblock_xq.size() * 4);
     for (int n = 0; n < n_inst; ++n) {
         const InstDesc &d = P.desc[n];
         for (int r = 0; r < d.R; ++r) {
@@ -1984,7 +2058,9 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->oct_resident = c->oct_resident ? 1 : 0;
     o->oct_queue = c->oct_queue ? 1 : 0;
     o->oct_fused = c->oct_fuse ? 1 : 0;
+    o->oct_ring_xcd = oct_ring_xcd(c) ? 1 : 0;
     o->recoveries = c->recoveries;
+    o->last_device_error = c->last_device_error;
     o->lane_words = c->lane_words;
     o->latency_path = latency_path(c, c->block_threads) ? 1 : 0;
     o->ent16_instances = 0;

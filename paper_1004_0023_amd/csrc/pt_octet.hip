@@ -589,28 +589,29 @@ __device__ __forceinline__ void oct_tile_item(const OctLaunch &L, char *lds, int
     if (ld32(flag)) exchange_instance<true>(st, n, L.swap_key0, L.swap_key1, L.t_add);
 }
 
-// The list position a workgroup of a work-queue launch sweeps: the next one of its XCD's
-// queue (the word groups were dealt to the XCDs' queues largest first, so that the octets
-// of a word group share one L2), else of the next XCD's queue that has one left.  The launch
-// has one workgroup per position, so each finds one.  The last workgroup to take its
-// position resets the counts for the next launch (every other has taken its own by then).
-// Returns -1 only if every queue was empty.
-__device__ __forceinline__ int oct_ticket(const DevState &st, int grid)
+// A list position for a workgroup of a launch that takes its work from per-XCD lists (q:
+// 9 offsets, then the lists; cnt: 8 counts taken and a count of workgroups done): the next
+// one of its own XCD's list, else of the next XCD's list that has one left (own = false).
+// The launch has one workgroup per position, so each finds one.  The last workgroup to take
+// its position resets the counts for the next launch (every other has taken its own by
+// then).  Returns -1 only if every list was empty.
+__device__ __forceinline__ int oct_take(const int32_t *q, int32_t *cnt, int grid, bool &own)
 {
     const int x0 = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7;  // XCC_ID (4 bits)
-    const int32_t *q = st.oqitems;
     int got = -1;
+    own = false;
     for (int j = 0; j < 8 && got < 0; ++j) {
         const int x = (x0 + j) & 7;
         const int len = q[x + 1] - q[x];
-        if (__hip_atomic_load(&st.oqueue[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len)
-            continue;
-        const int t = __hip_atomic_fetch_add(&st.oqueue[x], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (t < len) got = q[9 + q[x] + t];
+        if (__hip_atomic_load(&cnt[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len) continue;
+        const int t = __hip_atomic_fetch_add(&cnt[x], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t < len) {
+            got = q[9 + q[x] + t];
+            own = j == 0;
+        }
     }
-    if (__hip_atomic_fetch_add(&st.oqueue[8], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == grid - 1)
-        for (int x = 0; x < 9; ++x)
-            __hip_atomic_store(&st.oqueue[x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_fetch_add(&cnt[8], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == grid - 1)
+        for (int x = 0; x < 9; ++x) __hip_atomic_store(&cnt[x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return got;
 }
 
@@ -631,7 +632,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const uint32_t slot = (uint32_t)L.lds_bytes - (uint32_t)kOctQueueLds;
     int k = (int)blockIdx.x;
     if (L.queue) {
-        if (threadIdx.x == 0) st32(slot, (uint32_t)oct_ticket(st, (int)gridDim.x));
+        bool own;
+        if (threadIdx.x == 0) st32(slot, (uint32_t)oct_take(st.oqitems, st.oqueue, (int)gridDim.x, own));
         __syncthreads();
         // the same in every lane: scalar, so that everything derived from the octet's
         // record (its instance descriptor above all) stays in scalar registers
@@ -819,14 +821,24 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 // a reader issues its record loads only after it has seen the count.  (Publishing through
 // an agent-scope release and acquire instead, which write the whole XCD's L2 back and
 // invalidate it, made config 4's sweeps 1.4x slower.)
+//
+// When every ring of blocks sits on one XCD (LOCAL), a block's reader and writer share that
+// XCD's L2, and the stores need not go through to the coherence point: records and counts
+// are written with plain stores, which land in the L2, and read with the same
+// device-scope loads, which bypass the L1 and find the L2's line (measured between two
+// workgroups of one XCD: a round trip of 0.76 us against 2.8 us with device-scope stores).
 constexpr int kOctWaitPolls = 1 << 18;
 __device__ __forceinline__ uint32_t rec_ld(const uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+template <bool LOCAL>
 __device__ __forceinline__ void rec_st(uint32_t *p, uint32_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (LOCAL)
+        *p = v;
+    else
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Thread 0 polls *flag until it reaches need while the workgroup waits at a barrier.  The
@@ -852,11 +864,12 @@ __device__ __forceinline__ void oct_wait(const DevState &st, const int32_t *flag
 
 // After the workgroup's record stores: every wave waits for its own stores to complete
 // (a workgroup barrier does not wait for them), then thread 0 stores v.
+template <bool LOCAL>
 __device__ __forceinline__ void oct_publish(int32_t *flag, int v)
 {
     __builtin_amdgcn_s_waitcnt(kOctWaitVmcnt0);
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flag, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) rec_st<LOCAL>(reinterpret_cast<uint32_t *>(flag), (uint32_t)v);
 }
 
 // All sweeps of a call over one octet slice block, with every block of the launch resident.
@@ -886,7 +899,27 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) 
         if (threadIdx.x == 0) atomicOr(st.err, kErrLdsBase);
         return;
     }
-    const int b = L.tile0 + (int)blockIdx.x;
+    // with L.xcd_local, the block takes its position from its XCD's list, so that every
+    // ring of blocks runs on one XCD; a block that has to take one from another XCD's list
+    // fails the call (the host recovers), and still runs, its waits bounded, so that every
+    // block of the launch exits
+    int b = L.tile0 + (int)blockIdx.x;
+    if (L.xcd_local) {
+        const uint32_t slot = (uint32_t)L.lds_bytes - (uint32_t)kOctQueueLds;
+        if (threadIdx.x == 0) {
+            bool own;
+            const int k = oct_take(st.oxq, st.oqueue + 9, (int)gridDim.x, own);
+            if (!own) atomicOr(st.err, kErrPlace);
+            st32(slot, (uint32_t)k);
+        }
+        __syncthreads();
+        const int k = __builtin_amdgcn_readfirstlane((int)ld32(slot));
+        if (k < 0) {
+            if (threadIdx.x == 0) atomicOr(st.err, kErrQueue);
+            return;
+        }
+        b = L.tile0 + k;
+    }
     const int32_t *rec = st.otiles + (int64_t)b * kOctRec;
     const int n = rec[0], w = rec[1], oct = rec[2], g0 = rec[3], ng = rec[4];
     const int roff = rec[5], prev = rec[6], next = rec[7];
@@ -913,30 +946,39 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) 
     const int polls = L.wait_polls > 0 ? L.wait_polls : kOctWaitPolls;
     const OctPlanes pl0 = {P0, RS, P1, RS}, pl1 = {P1 + 4u, RS, P0, RS};
     const uint32_t halo1 = P1, halo0 = P0 + 4u * (uint32_t)ng;  // x = 0 of P1, x = ng of P0
-    oct_dispatch(d.D, L.split != 0, [&](auto dt, auto spl) {
-        constexpr int DT = decltype(dt)::value, SPL = decltype(spl)::value;
-        for (int sw = 0; sw < L.n_sweeps; ++sw) {
-            const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
-            if (sw > 0) {
-                oct_wait(st, prog + 2 * prev + 1, sw + L.wait_extra, polls);
-                for (int i = tid; i < N; i += nt) st32(halo1 + (uint32_t)i * RS, rec_ld(R1prev + i));
-                __syncthreads();
-            }
-            oct_block_sweep<DT, SPL>(L, d, o, pl0, 0, n, c0, nslots, g0, ng, tt);
-            for (int i = tid; i < N; i += nt) rec_st(R0 + i, ld32(P0 + (uint32_t)i * RS));
-            oct_publish(prog + 2 * b, sw + 1);
-            oct_wait(st, prog + 2 * next, sw + 1 + L.wait_extra, polls);
-            for (int i = tid; i < N; i += nt) st32(halo0 + (uint32_t)i * RS, rec_ld(R0next + i));
-            __syncthreads();
-            oct_block_sweep<DT, SPL>(L, d, o, pl1, 1, n, c0, nslots, g0, ng, tt);
-            if (sw + 1 < L.n_sweeps) {
+    auto sweeps = [&](auto local) __attribute__((always_inline)) {
+        constexpr bool LOCAL = decltype(local)::value != 0;
+        oct_dispatch(d.D, L.split != 0, [&](auto dt, auto spl) {
+            constexpr int DT = decltype(dt)::value, SPL = decltype(spl)::value;
+            for (int sw = 0; sw < L.n_sweeps; ++sw) {
+                const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
+                if (sw > 0) {
+                    oct_wait(st, prog + 2 * prev + 1, sw + L.wait_extra, polls);
+                    for (int i = tid; i < N; i += nt)
+                        st32(halo1 + (uint32_t)i * RS, rec_ld(R1prev + i));
+                    __syncthreads();
+                }
+                oct_block_sweep<DT, SPL>(L, d, o, pl0, 0, n, c0, nslots, g0, ng, tt);
+                for (int i = tid; i < N; i += nt) rec_st<LOCAL>(R0 + i, ld32(P0 + (uint32_t)i * RS));
+                oct_publish<LOCAL>(prog + 2 * b, sw + 1);
+                oct_wait(st, prog + 2 * next, sw + 1 + L.wait_extra, polls);
                 for (int i = tid; i < N; i += nt)
-                    rec_st(R1 + i, ld32(P1 + (uint32_t)i * RS + 4u * (uint32_t)ng));
-                oct_publish(prog + 2 * b + 1, sw + 1);
+                    st32(halo0 + (uint32_t)i * RS, rec_ld(R0next + i));
+                __syncthreads();
+                oct_block_sweep<DT, SPL>(L, d, o, pl1, 1, n, c0, nslots, g0, ng, tt);
+                if (sw + 1 < L.n_sweeps) {
+                    for (int i = tid; i < N; i += nt)
+                        rec_st<LOCAL>(R1 + i, ld32(P1 + (uint32_t)i * RS + 4u * (uint32_t)ng));
+                    oct_publish<LOCAL>(prog + 2 * b + 1, sw + 1);
+                }
             }
-        }
-        oct_block_energy<DT>(L, d, lds, o, pl1, ng);
-    });
+            oct_block_energy<DT>(L, d, lds, o, pl1, ng);
+        });
+    };
+    if (L.xcd_local)
+        sweeps(IC<1>{});
+    else
+        sweeps(IC<0>{});
     __syncthreads();
     oct_block_energy_out(st, d, lds, o, c0, nslots);
     for (int k = tid; k < (N << lgng); k += nt) {

@@ -26,6 +26,7 @@ PT_FLAG_TAU_CORR = 0x80
 PT_FLAG_WORK_QUEUE = 0x100
 PT_FLAG_TWO_WORD_LANES = 0x200
 PT_FLAG_NO_LATENCY_PATH = 0x400
+PT_FLAG_DEVICE_SCOPE_RECORDS = 0x800
 TAU_LAGS = 8  # PT_TAU_LAGS
 PT_FLAG_SLICE_BLOCKS = 0x8
 LABEL_NONE, LABEL_UP, LABEL_DOWN = 0, 1, 2
@@ -84,9 +85,10 @@ class _Info(C.Structure):
                 ("multi_cycles", C.c_int64), ("multi_ms", C.c_double),
                 ("oct_tiles", C.c_int32), ("oct_blocks", C.c_int32),
                 ("oct_tile_launches", C.c_int32), ("oct_resident", C.c_int32),
-                ("oct_queue", C.c_int32), ("oct_fused", C.c_int32), ("recoveries", C.c_int64),
+                ("oct_queue", C.c_int32), ("oct_fused", C.c_int32), ("oct_ring_xcd", C.c_int32),
+                ("recoveries", C.c_int64),
                 ("lane_words", C.c_int32), ("ent16_instances", C.c_int32),
-                ("latency_path", C.c_int32)]
+                ("last_device_error", C.c_uint32), ("latency_path", C.c_int32)]
 
 
 _lib = None
