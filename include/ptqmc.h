@@ -127,10 +127,11 @@ extern "C" {
                                           compute unit like any other instead of forming
                                           each thread's next item during the current one
                                           (same chain; a measurement and test hook)    */
-#define PT_FLAG_DEVICE_SCOPE_RECORDS 0x800u /* resident octet slice blocks: pass boundary
-                                          records with device-scope operations even
-                                          when every ring of blocks sits on one XCD (same
-                                          chain; a measurement and test hook)          */
+#define PT_FLAG_DEVICE_SCOPE_RECORDS 0x800u /* resident slice blocks (both encodings):
+                                          pass boundary records with device-scope
+                                          operations even when every ring of blocks
+                                          runs on one XCD, instead of through its L2
+                                          (same chain; a measurement and test hook)    */
 #define PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT 0x40u /* test hook: resident slice blocks wait for a
                                           progress count that never comes, under a tiny
                                           poll bound, so every wait gives up; the next
@@ -232,12 +233,14 @@ typedef struct {
     int32_t oct_fused;                /* 1: a PT cycle of the batch is one launch, the
                                          exchange step run by the octet that completes
                                          each instance                                  */
-    int32_t oct_ring_xcd;             /* 1: resident octet slice blocks take their work
-                                         from per-XCD lists, every ring of blocks on one
-                                         XCD, and pass boundary records through that
-                                         XCD's L2 (a block that has to take work from
-                                         another XCD's list fails the call, which then
-                                         recovers as after a wait that gave up)         */
+    int32_t oct_ring_xcd;             /* 1: every ring of resident octet slice blocks
+                                         runs on one XCD (workgroups b and b + 8 of a
+                                         launch share one) and passes boundary records
+                                         through its L2; a launch whose workgroups do
+                                         not keep to that fails, and the call recovers
+                                         as after a wait that gave up                   */
+    int32_t block_ring_xcd;           /* 1: the same for PT_INT8 resident slice blocks,
+                                         one ring of blocks per replica                 */
     int64_t recoveries;               /* synchronising calls that found a resident
                                          launch's wait given up, restored the state of
                                          the last clean synchronisation and replayed
@@ -254,8 +257,8 @@ typedef struct {
                                          synchronisation found (0: none): 1 a resident
                                          wait gave up, 2 an octet kernel found its LDS
                                          away from address 0, 4 a whole-octet workgroup
-                                         found the work queues empty, 8 a resident block
-                                         took its work from another XCD's list          */
+                                         found the work queues empty, 8 the workgroups
+                                         of a resident launch left round-robin XCDs     */
     int32_t latency_path;             /* 1: whole-replica tiles sweep on the latency path
                                          (at most one tile per compute unit; tiles whose
                                          colour classes fit one pass of the workgroup

@@ -237,13 +237,13 @@ struct DevState {
     const int32_t *otiles;
     uint32_t *orec;
     int32_t *oprog;
-    // per-XCD lists of octet work: oqueue holds, for the whole-octet work queues and then
-    // for the resident slice blocks' lists, the positions taken from each XCD's list (8
-    // counts) and the workgroups that have taken theirs (the last resets all nine for the
-    // next launch); oqitems and oxq: each set of lists as 9 offsets, then list positions
+    // whole octets from the device work queues: positions taken from each XCD's queue
+    // (8 counts) and workgroups that have taken theirs (the last resets all nine for the
+    // next launch); oqitems: the queues' 9 offsets, then their list positions
     int32_t *oqueue;
     const int32_t *oqitems;
-    const int32_t *oxq;
+    // resident slice blocks (octets, bytes): the XCD offsets their workgroups found
+    uint32_t *xseen;
     // mutable state
     uint8_t *spins;
     int64_t *E;       // per replica slot

@@ -78,10 +78,8 @@ struct Plan {
     // the whole-octet work queues: offsets of the 8 per-XCD queues (9 ints), then each
     // queue's list positions, largest octet first
     std::vector<int32_t> oqitems;
-    // resident octet slice blocks: every ring of blocks dealt whole to one XCD's list
-    // (offsets of the 8 lists, then their block positions)
+    // resident octet slice blocks: every ring of blocks in one run of the launch's map
     bool oblock_xcd = false;
-    std::vector<int32_t> oblock_xq;
     int32_t otile_lds = 0, oblock_lds = 0;     // their largest LDS need
     int32_t oblock_threads = 256;
     bool oblock_split = false;                 // slice blocks: two lanes per (site, group)
@@ -94,7 +92,7 @@ struct Plan {
     size_t o_inst, o_adj, o_off, o_h, o_ent, o_bias, o_csite, o_cls, o_tbl, o_db, o_dK, o_tiles,
         o_repinst, o_halo, o_itiles, o_icount, o_prog, o_err, o_bp_sblk, o_bp_eblk, o_bp_wg,
         o_bp_part, o_oent, o_ohinfo, o_otbl, o_otiles, o_orec, o_oprog, o_oqueue, o_oqitems,
-        o_oxq;
+        o_xseen;
     size_t o_state;  // start of the mutable region
     size_t o_spins, o_E, o_C, o_rung, o_label, o_rt, o_repof, o_sumE, o_sumC, o_sumE2,
         o_sumC2, o_nup, o_ndown, o_acc, o_att, o_ctr, o_sumCt;
@@ -185,6 +183,18 @@ constexpr int32_t kLdsPerWorkgroup = 163840;
 // passes over 64 positions at a time).
 constexpr int32_t kBpMaxChunks = 1024;
 constexpr int32_t kBpThreadsHost = 256;
+
+// Whether every ring of slice blocks ([first, end) positions, consecutive) lies within one
+// run of the launches' map from workgroups to tiles (runs of nb / 8 positions, each on one
+// XCD; the tail past 8 runs keeps its own indices and XCDs).
+bool rings_in_runs(const std::vector<std::pair<int, int>> &rings, int nb)
+{
+    const int q = nb / 8;
+    if (q == 0 || nb % 8 != 0) return false;
+    for (const auto &r : rings)
+        if (r.first / q != (r.second - 1) / q) return false;
+    return true;
+}
 
 int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t encoding, Plan &P)
 {
@@ -456,7 +466,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
                         // the list; neighbours and record offsets are filled in below
                         for (int g0 = 0; g0 < d.G4; g0 += ng) blocks.push_back({n, w, o, g0, ng, 0, 0, 0});
                         P.oblock_lds = std::max(P.oblock_lds, oct_lds_bytes(d, ng, kOctPhase));
-                        P.oblock_res_lds = std::max(P.oblock_res_lds, oct_lds_bytes(d, ng, kOctResident) + kOctQueueLds);
+                        P.oblock_res_lds = std::max(P.oblock_res_lds, oct_lds_bytes(d, ng, kOctResident));
                     }
                 }
         }
@@ -503,10 +513,9 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
             for (int x = 0; x < kXcds; ++x) P.oqitems.insert(P.oqitems.end(), pos[x].begin(), pos[x].end());
         }
         // Resident slice blocks pass boundary records to their ring neighbours twice per
-        // sweep.  When the rings can be dealt to the 8 XCDs whole, each XCD taking exactly an
-        // eighth of the blocks, every block of the resident launch takes its slice block from
-        // its own XCD's list as it starts, so each ring runs on one XCD and the records pass
-        // through that XCD's L2 instead of device-scope operations.
+        // sweep.  When every ring lies in one run of the resident launch's workgroup-to-block
+        // map (so on one XCD), the records pass through that XCD's L2 instead of
+        // device-scope operations.
         const int base = (int)tiles.size();  // blocks follow the tiles in the list
         std::vector<int32_t> prev(blocks.size()), next(blocks.size());
         for (size_t k = 0; k < blocks.size(); ++k) {
@@ -516,12 +525,9 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
             prev[k] = first + (t[3] / t[4] + ring - 1) % ring;
             next[k] = first + (t[3] / t[4] + 1) % ring;
         }
-        P.oblock_xcd = false;
-        P.oblock_xq.clear();
-        if (!blocks.empty() && blocks.size() % 8 == 0) {
-            constexpr int kXcds = 8;
-            const int nb = (int)blocks.size();
+        {
             std::vector<std::pair<int, int>> rings;  // [first, end) in blocks
+            const int nb = (int)blocks.size();
             for (int k = 0; k < nb;) {
                 int e = k + 1;
                 while (e < nb && blocks[e][0] == blocks[k][0] && blocks[e][1] == blocks[k][1] &&
@@ -530,32 +536,7 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
                 rings.emplace_back(k, e);
                 k = e;
             }
-            std::vector<int> cap(kXcds, nb / kXcds), order(rings.size());
-            for (size_t r = 0; r < rings.size(); ++r) order[r] = (int)r;
-            std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-                return rings[x].second - rings[x].first > rings[y].second - rings[y].first;
-            });
-            std::vector<std::vector<int32_t>> lists(kXcds);
-            bool ok = true;
-            for (int r : order) {
-                const int sz = rings[r].second - rings[r].first;
-                int best = -1;
-                for (int x = 0; x < kXcds; ++x)
-                    if (cap[x] >= sz && (best < 0 || cap[x] > cap[best])) best = x;
-                if (best < 0) {
-                    ok = false;
-                    break;
-                }
-                cap[best] -= sz;
-                for (int k = rings[r].first; k < rings[r].second; ++k) lists[best].push_back(k);
-            }
-            if (ok) {
-                P.oblock_xq.assign(kXcds + 1, 0);
-                for (int x = 0; x < kXcds; ++x) P.oblock_xq[x + 1] = P.oblock_xq[x] + (int32_t)lists[x].size();
-                for (int x = 0; x < kXcds; ++x)
-                    P.oblock_xq.insert(P.oblock_xq.end(), lists[x].begin(), lists[x].end());
-                P.oblock_xcd = true;
-            }
+            P.oblock_xcd = rings_in_runs(rings, nb);
         }
         for (size_t k = 0; k < blocks.size(); ++k) {
             auto &t = blocks[k];
@@ -618,9 +599,9 @@ int make_plan(const pt_instance *inst, int32_t n_inst, uint32_t flags, int32_t e
     P.o_otiles = take(P.otiles.size() * 4);
     P.o_orec = take((size_t)P.orec_words * 2 * 4);
     P.o_oprog = take((size_t)(P.n_otile + P.n_oblock) * 2 * 4);
-    P.o_oqueue = take(18 * 4);  // zero in the uploaded image
+    P.o_oqueue = take(9 * 4);  // zero in the uploaded image
     P.o_oqitems = take(P.oqitems.size() * 4);
-    P.o_oxq = take(P.oblock_xq.size() * 4);
+    P.o_xseen = take(2 * 4);
     P.o_state = o;
     P.o_spins = take((size_t)spinb);
     P.o_E = take((size_t)rep * 8);
@@ -721,6 +702,7 @@ struct pt_ctx {
     int resident_per_cu = 0;
     int block_persistent = 0;   // the last slice-block call ran as one resident launch
     int lane_words = 2;         // whole-replica tiles: four-slice words per lane
+    bool block_xcd = false;     // resident slice blocks: every replica's ring on one XCD
     bool lat = false;           // whole-replica tiles: the latency path
     bool oct_resident = false;  // octet slice blocks: one resident launch per call
     // Recovery when a resident launch's wait gave up: a device copy of the state region at
@@ -878,6 +860,21 @@ int build_tiles(pt_ctx *c, int force_P, int tile_bytes)
     if (hb > P.halo_words || hb > 0x7fffffff)
         return fail(PT_EINVAL, "slice blocks need more boundary records than were reserved "
                                "(the device's LDS is smaller than the library assumes)");
+    // Resident slice blocks pass boundary records to the neighbouring blocks of their
+    // replica every sweep: when every replica's ring of blocks lies in one run of the
+    // launches' workgroup-to-tile map (so on one XCD), the records pass through that XCD's
+    // L2 instead of device-scope operations.
+    {
+        std::vector<std::pair<int, int>> rings;
+        const int nb = (int)block.size();
+        for (int k = 0; k < nb;) {
+            int e = k + 1;
+            while (e < nb && block[e].inst == block[k].inst && block[e].c0 == block[k].c0) ++e;
+            rings.emplace_back(k, e);
+            k = e;
+        }
+        c->block_xcd = rings_in_runs(rings, nb);
+    }
     c->tiles = fast;
     c->tiles.insert(c->tiles.end(), generic.begin(), generic.end());
     c->tiles.insert(c->tiles.end(), block.begin(), block.end());
@@ -1078,8 +1075,8 @@ int sync_and_check(pt_ctx *c)
                                    "and did not run; the state is inconsistent");
         if ((err & kErrPlace) && c->shadow && !c->replaying) return recover(c);
         if (err & kErrPlace)
-            return fail(PT_ESTATE, "a resident slice block took its work from another XCD's "
-                                   "list; the state is inconsistent");
+            return fail(PT_ESTATE, "the workgroups of a resident slice-block launch did not keep "
+                                   "to round-robin XCDs; the state is inconsistent");
         if (err & kErrQueue)
             return fail(PT_ESTATE, "a whole-octet workgroup found every work queue empty; the "
                                    "state is inconsistent");
@@ -1102,6 +1099,14 @@ hipError_t energies_from_spins(pt_ctx *c, int rep_first, int n)
 
 // Whole octets from the device work queue: as many workgroups as the compute units hold at
 // once for the current block size (at most one per octet).
+// Resident byte slice blocks pass their records through the L2 of the XCD that holds their
+// replica's ring.
+bool block_ring_xcd(const pt_ctx *c)
+{
+    return c->block_xcd && c->n_block_tiles > 0 && !c->resident_off &&
+           !(c->opt.flags & (PT_FLAG_DEVICE_SCOPE_RECORDS | PT_FLAG_BLOCK_LAUNCH_PER_SWEEP));
+}
+
 // Resident octet slice blocks pass their records through the L2 of the XCD that holds
 // their ring (the rings were placed one per XCD).
 bool oct_ring_xcd(const pt_ctx *c)
@@ -1309,6 +1314,7 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange, int cycles =
                 c->block_persistent = resident ? 1 : 0;
                 if (e == hipSuccess && resident) {
                     L.persist = 1;
+                    L.xcd_local = block_ring_xcd(c) ? 1 : 0;
                     if (c->opt.flags & PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT) {
                         L.wait_polls = 16;
                         L.wait_extra = 1 << 30;
@@ -1610,7 +1616,7 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     st.oprog = (int32_t *)(w + P.o_oprog);
     st.oqueue = (int32_t *)(w + P.o_oqueue);
     st.oqitems = (const int32_t *)(w + P.o_oqitems);
-    st.oxq = (const int32_t *)(w + P.o_oxq);
+    st.xseen = (uint32_t *)(w + P.o_xseen);
 
     // one host image of the whole workspace, uploaded in a single copy
     std::vector<char> img;
@@ -1642,7 +1648,6 @@ int pt_init(pt_ctx **out, const pt_instance *inst, int32_t n_inst, const pt_opti
     put(P.o_otbl, P.otbl.data(), P.otbl.size() * 4);
     put(P.o_otiles, P.otiles.data(), P.otiles.size() * 4);
     put(P.o_oqitems, P.oqitems.data(), P.oqitems.size() * 4);
-    put(P.o_oxq, P.oblock_xq.data(), P.oblock_xq.size() * 4);
     for (int n = 0; n < n_inst; ++n) {
         const InstDesc &d = P.desc[n];
         for (int r = 0; r < d.R; ++r) {
@@ -2059,6 +2064,7 @@ int pt_get_info(pt_ctx *c, pt_info *o)
     o->oct_queue = c->oct_queue ? 1 : 0;
     o->oct_fused = c->oct_fuse ? 1 : 0;
     o->oct_ring_xcd = oct_ring_xcd(c) ? 1 : 0;
+    o->block_ring_xcd = block_ring_xcd(c) ? 1 : 0;
     o->recoveries = c->recoveries;
     o->last_device_error = c->last_device_error;
     o->lane_words = c->lane_words;

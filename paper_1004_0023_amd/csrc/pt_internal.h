@@ -29,6 +29,9 @@ struct SweepLaunch {
     // fused whole-replica launches whose tiles each hold a whole instance: PT cycles run by
     // the launch (0 or 1: one)
     int32_t cycles;
+    // resident slice blocks: every replica's ring of blocks lies in one run of the
+    // workgroup-to-tile map, so on one XCD, and records and counts pass through its L2
+    int32_t xcd_local;
     // fast tiles: the latency path (at most one tile per compute unit; tiles whose colour
     // classes do not fit one pass of the workgroup sweep as usual)
     int32_t lat;
@@ -73,8 +76,8 @@ struct OctLaunch {
     // resident: poll bound of a neighbour wait (0: the kernel's default) and an amount added
     // to every awaited progress count (0; a test hook sets it so that the waits give up)
     int32_t wait_polls, wait_extra;
-    // resident: every block takes its work from its XCD's list (DevState::oxq), so every
-    // ring of blocks is on one XCD, and records and progress counts pass through its L2
+    // resident: every ring of blocks lies in one run of the workgroup-to-block map, so on
+    // one XCD, and records and progress counts pass through its L2
     int32_t xcd_local;
 };
 constexpr int kOctRec = 8;  // ints per octet work item
@@ -85,7 +88,7 @@ enum OctMode { kOctTile = 0, kOctPhase = 1, kOctResident = 2 };
 constexpr uint32_t kErrWait = 1u;     // a resident slice block gave up waiting for a neighbour
 constexpr uint32_t kErrLdsBase = 2u;  // an octet kernel found its dynamic LDS away from address 0
 constexpr uint32_t kErrQueue = 4u;    // a whole-octet workgroup found every work queue empty
-constexpr uint32_t kErrPlace = 8u;    // a resident block took its work from another XCD's list
+constexpr uint32_t kErrPlace = 8u;    // a resident launch's workgroups left round-robin XCDs
 
 // Each returns the hipError_t of the launch itself (asynchronous execution errors
 // surface at the next synchronisation).

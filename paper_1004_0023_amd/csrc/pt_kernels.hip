@@ -19,6 +19,7 @@
 // class is an independent set, so its sites are updated in parallel and the result is
 // independent of the launch shape.
 #include "pt_exchange.h"
+#include "pt_xcd.h"
 #include "pt_internal.h"
 
 #pragma clang fp contract(off)
@@ -1204,18 +1205,9 @@ __device__ __forceinline__ void block_sweep_split(const BlockArgs &a, const Inst
     block_phase<DT, 1>(a, d, tile, t, w.s[3], w.l[3], w.nt, 1);
 }
 
-// Workgroups go to the XCDs (each with its own L2 cache) round robin by index.  The slice
-// blocks of one replica share every cache line of its spin rows (a block owns a few words
-// of each row), so consecutive tiles are kept on one XCD: index b runs tile
-// (b mod X) * q + b / X for b < X * q, q = n / X, and the tail keeps its index.  The map is
-// a bijection for any X; on a device with another XCD count only the locality is lost.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_tile(int b, int n)
-{
-    const int q = n / kXcds;
-    if (b >= kXcds * q) return b;
-    return (b % kXcds) * q + b / kXcds;
-}
+// The slice blocks of one replica share every cache line of its spin rows (a block owns a
+// few words of each row), so the launches map workgroups to tiles with xcd_tile: runs of
+// consecutive tiles share an XCD.
 
 // Before the first slice-block launch of a call: every block's boundary record of the
 // current spins into buffer (t mod 2), its progress count zeroed, and E_cl, C of its
@@ -1237,6 +1229,7 @@ __global__ void block_prepare_kernel(SweepLaunch L)
         rec[2 * N + i] = *reinterpret_cast<const uint32_t *>(r1 + 4 * (g0 + ng - 1));
     }
     if (threadIdx.x == 0) st.prog[xcd_tile(blockIdx.x, gridDim.x)] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st.xseen[1] = 0u;
     if (g0 == 0 && threadIdx.x == 0)
         for (int q = 0; q < tile.P; ++q) {
             st.E[d.rep_base + tile.c0 + q] = 0;
@@ -1249,14 +1242,19 @@ __global__ void block_prepare_kernel(SweepLaunch L)
 // written only with agent-scope atomic operations, which the hardware performs coherently
 // for the whole device, so no L2 write-back or invalidation is needed: every wave waits for
 // its record stores to complete before the barrier that precedes the count's store, and a
-// block issues its halo loads only after it has seen the counts.
+// block issues its halo loads only after it has seen the counts.  When every replica's
+// ring of blocks runs on one XCD (local), the stores are plain: they land in that XCD's L2,
+// where the same device-scope loads find them, without the trip to the coherence point.
 __device__ __forceinline__ uint32_t rec_ld(const uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void rec_st(uint32_t *p, uint32_t v)
+__device__ __forceinline__ void rec_st(uint32_t *p, uint32_t v, bool local)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (local)
+        *p = v;
+    else
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Stage a slice block into LDS: the owned groups of both planes from the spins (16-byte
@@ -1425,6 +1423,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
     extern __shared__ __align__(16) char lds[];
     const DevState &st = L.st;
     const int bt = xcd_tile(blockIdx.x, gridDim.x);
+    // resident blocks with L.xcd_local: every replica's ring of blocks lies in one run of
+    // xcd_tile, so it runs on one XCD; a launch whose workgroups did not keep to that fails
+    // the call (checked at the end; the host recovers), each block running to its end, its
+    // waits bounded
+    const bool local = PERSIST && L.xcd_local != 0;
     const Tile tile = st.tiles[L.tile0 + bt];
     const int n = tile.inst;
     const InstDesc d = st.inst[n];
@@ -1518,15 +1521,14 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
     auto store_records = [&](int sw) {
         uint32_t *rout = st.halo + (int64_t)((tsw + sw + 1) & 1) * st.halo_words + tile.hb;
         for (int i = tid; i < N; i += nt) {
-            rec_st(rout + N + i, sp32[block_at(a, 1, 0, i, 1) >> 2]);
-            rec_st(rout + 2 * N + i, sp32[block_at(a, 1, 0, i, ng) >> 2]);
+            rec_st(rout + N + i, sp32[block_at(a, 1, 0, i, 1) >> 2], local);
+            rec_st(rout + 2 * N + i, sp32[block_at(a, 1, 0, i, ng) >> 2], local);
         }
     };
     auto commit = [&](int sw) {
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
-        if (tid == 0)
-            __hip_atomic_store(&st.prog[bt], sw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) rec_st(reinterpret_cast<uint32_t *>(&st.prog[bt]), (uint32_t)(sw + 1), local);
     };
     auto publish = [&](int sw) {
         store_records(sw);
@@ -1644,6 +1646,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
             rec_out[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
         }
     }
+    if (local) xcd_check(st, st.xseen + 1, (int)blockIdx.x, kErrPlace);
     if constexpr (FUSE)
         if (L.last) finish_tile(L, st, n, t.red);
 }

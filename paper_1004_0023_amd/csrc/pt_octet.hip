@@ -26,6 +26,7 @@
 //              launch of a call adds each block's part of E_cl and C
 //   oct_clear  E_cl and C of the slice-block octets set to zero before a call
 #include "pt_exchange.h"
+#include "pt_xcd.h"
 #include "pt_internal.h"
 
 #pragma clang fp contract(off)
@@ -589,32 +590,6 @@ __device__ __forceinline__ void oct_tile_item(const OctLaunch &L, char *lds, int
     if (ld32(flag)) exchange_instance<true>(st, n, L.swap_key0, L.swap_key1, L.t_add);
 }
 
-// A list position for a workgroup of a launch that takes its work from per-XCD lists (q:
-// 9 offsets, then the lists; cnt: 8 counts taken and a count of workgroups done): the next
-// one of its own XCD's list, else of the next XCD's list that has one left (own = false).
-// The launch has one workgroup per position, so each finds one.  The last workgroup to take
-// its position resets the counts for the next launch (every other has taken its own by
-// then).  Returns -1 only if every list was empty.
-__device__ __forceinline__ int oct_take(const int32_t *q, int32_t *cnt, int grid, bool &own)
-{
-    const int x0 = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7;  // XCC_ID (4 bits)
-    int got = -1;
-    own = false;
-    for (int j = 0; j < 8 && got < 0; ++j) {
-        const int x = (x0 + j) & 7;
-        const int len = q[x + 1] - q[x];
-        if (__hip_atomic_load(&cnt[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len) continue;
-        const int t = __hip_atomic_fetch_add(&cnt[x], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (t < len) {
-            got = q[9 + q[x] + t];
-            own = j == 0;
-        }
-    }
-    if (__hip_atomic_fetch_add(&cnt[8], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == grid - 1)
-        for (int x = 0; x < 9; ++x) __hip_atomic_store(&cnt[x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return got;
-}
-
 // Whole octets, one workgroup each.  Workgroup b sweeps list position tile0 + b: the
 // hardware hands workgroups to each XCD in index order as its units free up, and the list
 // is dealt to the XCDs largest first, so that order already runs the largest octets first.
@@ -632,8 +607,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const uint32_t slot = (uint32_t)L.lds_bytes - (uint32_t)kOctQueueLds;
     int k = (int)blockIdx.x;
     if (L.queue) {
-        bool own;
-        if (threadIdx.x == 0) st32(slot, (uint32_t)oct_take(st.oqitems, st.oqueue, (int)gridDim.x, own));
+        if (threadIdx.x == 0) st32(slot, (uint32_t)xcd_take(st.oqitems, st.oqueue, (int)gridDim.x));
         __syncthreads();
         // the same in every lane: scalar, so that everything derived from the octet's
         // record (its instance descriptor above all) stays in scalar registers
@@ -899,27 +873,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) 
         if (threadIdx.x == 0) atomicOr(st.err, kErrLdsBase);
         return;
     }
-    // with L.xcd_local, the block takes its position from its XCD's list, so that every
-    // ring of blocks runs on one XCD; a block that has to take one from another XCD's list
-    // fails the call (the host recovers), and still runs, its waits bounded, so that every
-    // block of the launch exits
-    int b = L.tile0 + (int)blockIdx.x;
-    if (L.xcd_local) {
-        const uint32_t slot = (uint32_t)L.lds_bytes - (uint32_t)kOctQueueLds;
-        if (threadIdx.x == 0) {
-            bool own;
-            const int k = oct_take(st.oxq, st.oqueue + 9, (int)gridDim.x, own);
-            if (!own) atomicOr(st.err, kErrPlace);
-            st32(slot, (uint32_t)k);
-        }
-        __syncthreads();
-        const int k = __builtin_amdgcn_readfirstlane((int)ld32(slot));
-        if (k < 0) {
-            if (threadIdx.x == 0) atomicOr(st.err, kErrQueue);
-            return;
-        }
-        b = L.tile0 + k;
-    }
+    // runs of consecutive blocks share an XCD (xcd_tile); with L.xcd_local every ring of
+    // blocks lies in one run, and a launch whose workgroups did not keep to that fails the
+    // call (checked at the end; the host recovers), each block running to its end, its
+    // waits bounded
+    const int b = L.tile0 + xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int32_t *rec = st.otiles + (int64_t)b * kOctRec;
     const int n = rec[0], w = rec[1], oct = rec[2], g0 = rec[3], ng = rec[4];
     const int roff = rec[5], prev = rec[6], next = rec[7];
@@ -986,6 +944,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) 
         oct_store(oct_row(st, d, w, 0, i), g0 + x, oct, ld32(P0 + (uint32_t)i * RS + 4u * (uint32_t)x));
         oct_store(oct_row(st, d, w, 1, i), g0 + x, oct, ld32(P1 + (uint32_t)i * RS + 4u * (uint32_t)(x + 1)));
     }
+    if (L.xcd_local) xcd_check(st, st.xseen, (int)blockIdx.x, kErrPlace);
 }
 
 // E_cl and C of the slice-block octets set to zero (the block at group 0 clears its
@@ -996,6 +955,7 @@ __global__ void oct_clear_kernel(OctLaunch L)
     const int32_t *rec = L.st.otiles + (int64_t)b * kOctRec;
     const int r = threadIdx.x;
     if (r < 2) L.st.oprog[2 * b + r] = 0;
+    if (blockIdx.x == 0 && r == 0) L.st.xseen[0] = 0u;
     if (rec[3] != 0) return;
     const InstDesc d = L.st.inst[rec[0]];
     const int c0 = 32 * rec[1] + 8 * rec[2];

@@ -86,6 +86,7 @@ class _Info(C.Structure):
                 ("oct_tiles", C.c_int32), ("oct_blocks", C.c_int32),
                 ("oct_tile_launches", C.c_int32), ("oct_resident", C.c_int32),
                 ("oct_queue", C.c_int32), ("oct_fused", C.c_int32), ("oct_ring_xcd", C.c_int32),
+                ("block_ring_xcd", C.c_int32),
                 ("recoveries", C.c_int64),
                 ("lane_words", C.c_int32), ("ent16_instances", C.c_int32),
                 ("last_device_error", C.c_uint32), ("latency_path", C.c_int32)]

@@ -468,19 +468,22 @@ def test_config2_slice_blocks(ptqmc):
         assert_same(s, 0, ref, "config2 blocks")
 
 
-@pytest.mark.parametrize("mode", ["resident", "per_sweep", "bitpack", "bitpack_device_scope"])
+@pytest.mark.parametrize("mode", ["resident", "resident_device_scope", "per_sweep", "bitpack",
+                                  "bitpack_device_scope"])
 def test_config4_long_run_digest(ptqmc, mode):
     """The 8x8x16 lattice (N=1024, M=256, R=64) for 100 cycles of 10 sweeps (10^3
     sweeps): resident slice blocks, slice blocks launched once per sweep, and the
-    bit-packed encoding (its eight rings of 32 resident octet blocks one per XCD,
-    records through that XCD's L2, and through device-scope operations) all end in the
-    state whose digest the oracle stored, with no call recovered."""
+    bit-packed encoding all end in the state whose digest the oracle stored, with no call
+    recovered.  Resident blocks run with every ring of blocks on one XCD (a replica's 4
+    byte blocks, an octet's 32), records through that XCD's L2, and with records through
+    device-scope operations."""
     gold = golden.load_golden("config4")
     inst = W.config4()
     seed = W.sampler_seed(4)
     assert gold["seed"] == seed
-    flags = {"per_sweep": ptqmc.PT_FLAG_BLOCK_LAUNCH_PER_SWEEP,
-             "bitpack_device_scope": ptqmc.PT_FLAG_DEVICE_SCOPE_RECORDS}.get(mode, 0)
+    flags = ptqmc.PT_FLAG_BLOCK_LAUNCH_PER_SWEEP if mode == "per_sweep" else 0
+    if mode.endswith("device_scope"):
+        flags |= ptqmc.PT_FLAG_DEVICE_SCOPE_RECORDS
     enc = ptqmc.PT_BITPACK32 if mode.startswith("bitpack") else ptqmc.PT_INT8
     say(f"case: config 4, {gold['cycles']} cycles of 10 sweeps, {mode}, against the stored digest")
     with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, flags=flags, encoding=enc) as s:
@@ -491,6 +494,7 @@ def test_config4_long_run_digest(ptqmc, mode):
             assert info["oct_ring_xcd"] == (1 if mode == "bitpack" else 0)
         else:
             assert info["block_resident"] == (0 if mode == "per_sweep" else 1)
+            assert info["block_ring_xcd"] == (1 if mode == "resident" else 0)
         got = golden.state_digest(s.spins(0), s.observables(0))
         assert s.info()["recoveries"] == 0
     assert got == gold["digests"][0]
