@@ -132,6 +132,10 @@ extern "C" {
                                           operations even when every ring of blocks
                                           runs on one XCD, instead of through its L2
                                           (same chain; a measurement and test hook)    */
+#define PT_FLAG_TEST_XCD_MISMATCH 0x1000u /* test hook: resident slice blocks whose rings
+                                          share an XCD report the launch's XCDs as
+                                          mismatched, so the next synchronising call
+                                          recovers (pt_info.recoveries)                */
 #define PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT 0x40u /* test hook: resident slice blocks wait for a
                                           progress count that never comes, under a tiny
                                           poll bound, so every wait gives up; the next

@@ -1162,7 +1162,7 @@ int enqueue_bp_sweep(pt_ctx *c, int n_sweeps, bool fuse_exchange)
         if (c->oct_resident) {
             O.lds_bytes = P.oblock_res_lds;
             O.rec_words = (int32_t)P.orec_words;
-            O.xcd_local = oct_ring_xcd(c) ? 1 : 0;
+            O.xcd_local = !oct_ring_xcd(c) ? 0 : (c->opt.flags & PT_FLAG_TEST_XCD_MISMATCH) ? 2 : 1;
             if (c->opt.flags & PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT) {
                 O.wait_polls = 16;
                 O.wait_extra = 1 << 30;
@@ -1314,7 +1314,8 @@ int enqueue_sweep_once(pt_ctx *c, int n_sweeps, bool fuse_exchange, int cycles =
                 c->block_persistent = resident ? 1 : 0;
                 if (e == hipSuccess && resident) {
                     L.persist = 1;
-                    L.xcd_local = block_ring_xcd(c) ? 1 : 0;
+                    L.xcd_local = !block_ring_xcd(c) ? 0
+                                  : (c->opt.flags & PT_FLAG_TEST_XCD_MISMATCH) ? 2 : 1;
                     if (c->opt.flags & PT_FLAG_TEST_BLOCK_WAIT_TIMEOUT) {
                         L.wait_polls = 16;
                         L.wait_extra = 1 << 30;

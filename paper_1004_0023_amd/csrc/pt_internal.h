@@ -30,7 +30,8 @@ struct SweepLaunch {
     // the launch (0 or 1: one)
     int32_t cycles;
     // resident slice blocks: every replica's ring of blocks lies in one run of the
-    // workgroup-to-tile map, so on one XCD, and records and counts pass through its L2
+    // workgroup-to-tile map, so on one XCD, and records and counts pass through its L2 (2:
+    // the same, and the launch reports its XCDs as mismatched; a test hook)
     int32_t xcd_local;
     // fast tiles: the latency path (at most one tile per compute unit; tiles whose colour
     // classes do not fit one pass of the workgroup sweep as usual)
@@ -77,7 +78,8 @@ struct OctLaunch {
     // to every awaited progress count (0; a test hook sets it so that the waits give up)
     int32_t wait_polls, wait_extra;
     // resident: every ring of blocks lies in one run of the workgroup-to-block map, so on
-    // one XCD, and records and progress counts pass through its L2
+    // one XCD, and records and progress counts pass through its L2 (2: the same, and the
+    // launch reports its XCDs as mismatched; a test hook)
     int32_t xcd_local;
 };
 constexpr int kOctRec = 8;  // ints per octet work item

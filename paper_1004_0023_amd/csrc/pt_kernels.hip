@@ -1646,7 +1646,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(PERSI
             rec_out[2 * N + i] = sp32[block_at(a, 1, 0, i, ng) >> 2];
         }
     }
-    if (local) xcd_check(st, st.xseen + 1, (int)blockIdx.x, kErrPlace);
+    if (local) xcd_check(st, st.xseen + 1, (int)blockIdx.x, kErrPlace, L.xcd_local == 2);
     if constexpr (FUSE)
         if (L.last) finish_tile(L, st, n, t.red);
 }

@@ -944,7 +944,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) 
         oct_store(oct_row(st, d, w, 0, i), g0 + x, oct, ld32(P0 + (uint32_t)i * RS + 4u * (uint32_t)x));
         oct_store(oct_row(st, d, w, 1, i), g0 + x, oct, ld32(P1 + (uint32_t)i * RS + 4u * (uint32_t)(x + 1)));
     }
-    if (L.xcd_local) xcd_check(st, st.xseen, (int)blockIdx.x, kErrPlace);
+    if (L.xcd_local) xcd_check(st, st.xseen, (int)blockIdx.x, kErrPlace, L.xcd_local == 2);
 }
 
 // E_cl and C of the slice-block octets set to zero (the block at group 0 clears its

@@ -26,13 +26,15 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 
 // Workgroup b of a launch that relies on b and b + 8 sharing an XCD: records the XCD offset
 // (XCC_ID - b) mod 8 in *seen (zeroed before the launch) and sets the error word's bit
-// `err` if another workgroup of the launch found a different one.
-__device__ __forceinline__ void xcd_check(const DevState &st, uint32_t *seen, int b, uint32_t err)
+// `err` if another workgroup of the launch found a different one (or, with `force`, a test
+// hook, always from workgroup 0).
+__device__ __forceinline__ void xcd_check(const DevState &st, uint32_t *seen, int b, uint32_t err,
+                                          bool force)
 {
     if (threadIdx.x == 0) {
         const uint32_t bit = 1u << ((xcc_id() - b) & 7);
         const uint32_t old = atomicOr(seen, bit);
-        if ((old | bit) != bit) atomicOr(st.err, err);
+        if ((old | bit) != bit || (force && b == 0)) atomicOr(st.err, err);
     }
 }
 

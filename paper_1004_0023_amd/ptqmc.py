@@ -27,6 +27,7 @@ PT_FLAG_WORK_QUEUE = 0x100
 PT_FLAG_TWO_WORD_LANES = 0x200
 PT_FLAG_NO_LATENCY_PATH = 0x400
 PT_FLAG_DEVICE_SCOPE_RECORDS = 0x800
+PT_FLAG_TEST_XCD_MISMATCH = 0x1000
 TAU_LAGS = 8  # PT_TAU_LAGS
 PT_FLAG_SLICE_BLOCKS = 0x8
 LABEL_NONE, LABEL_UP, LABEL_DOWN = 0, 1, 2

@@ -179,6 +179,37 @@ def test_octet_resident_wait_timeout_recovers(ptqmc):
         assert s.info()["recoveries"] == 1
 
 
+@pytest.mark.parametrize("encoding", ["bitpack", "int8"])
+def test_xcd_mismatch_recovers(ptqmc, encoding):
+    """Resident slice blocks whose rings share an XCD pass their records through its L2,
+    which is only right while the launch's workgroups keep to round-robin XCDs.  A launch
+    that reports a mismatch (forced from the host) fails the call; the next synchronising
+    call restores the last clean state and replays the calls with per-sweep launches: the
+    state is the oracle's, one recovery is counted, and the error word named the cause."""
+    inst = W.config4()
+    seed = 11
+    enc = ptqmc.PT_BITPACK32 if encoding == "bitpack" else ptqmc.PT_INT8
+    say(f"case: forced XCD mismatch of resident slice blocks (config 4, {encoding}), recovery")
+    ref = oracle.OracleChain(inst, seed)
+    # the byte encoding at its tuned shape (4 resident blocks per replica), so that no
+    # tuner candidate runs first
+    shape = {} if encoding == "bitpack" else dict(tile_bytes=131072, block_threads=1024)
+    with ptqmc.Sampler([inst], seed, sweeps_per_exchange=10, encoding=enc,
+                       flags=ptqmc.PT_FLAG_TEST_XCD_MISMATCH, **shape) as s:
+        info = s.info()
+        assert (info["oct_ring_xcd"] if encoding == "bitpack" else info["block_ring_xcd"]) == 1
+        s.run(2)
+        s.sync()
+        ref.run(10, 2)
+        info = s.info()
+        assert info["recoveries"] == 1 and info["last_device_error"] & 8
+        assert_same(s, 0, ref, "recovered")
+        s.run(1)
+        ref.run(10, 1)
+        assert_same(s, 0, ref, "after recovery")
+        assert s.info()["recoveries"] == 1
+
+
 def octet_batch():
     """Instances the octet kernels take (+-1 couplings, |h| <= 1, one degree, M a
     power-of-two multiple of 8): the smallest M (8), degree 8 with fields (nine adder-tree
