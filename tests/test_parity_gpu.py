@@ -247,6 +247,29 @@ def test_latency_path_matches_oracle(ptqmc, batch, two_words, no_latency):
             assert_same(s, n, refs[n], "latency path")
 
 
+@pytest.mark.parametrize("encoding", ["int8", "bitpack"])
+def test_more_than_64_replicas(ptqmc, encoding):
+    """Instances of 65, 96 and 130 replicas: the exchange step of instances of at most 64
+    replicas runs in one wave, these take its general form (and the bit-packed encoding
+    a third, partly filled 32-slot word group).  Every cycle's state is the oracle's."""
+    rng = np.random.default_rng([1004, 28])
+    insts = [W.random_small_instance(rng, 6, 8, 65, d=2, jmax=1, hmax=1, t_min=0.2, t_max=4.0,
+                                     name="r65"),
+             W.random_small_instance(rng, 10, 16, 96, d=3, jmax=1, hmax=1, t_min=0.3, t_max=3.0,
+                                     name="r96"),
+             W.random_small_instance(rng, 4, 8, 130, d=2, jmax=1, hmax=0, t_min=0.1, t_max=5.0,
+                                     name="r130")]
+    seed = 0x65A
+    k, cycles = 2, 12
+    enc = ptqmc.PT_BITPACK32 if encoding == "bitpack" else ptqmc.PT_INT8
+    say(f"case: R = 65, 96, 130, {encoding}")
+    refs = oracle_batch(insts, seed, k, cycles)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, encoding=enc) as s:
+        s.run(cycles)
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], f"R={insts[n].R}")
+
+
 def test_sixteen_bit_entries_in_small_batch(ptqmc):
     """A lone large regular +-1 instance (N = 512, M = 128, degree 8: a replica of more
     than half a compute unit's LDS, so its neighbour entries are 16 bits) with two
