@@ -270,6 +270,42 @@ def test_more_than_64_replicas(ptqmc, encoding):
             assert_same(s, n, refs[n], f"R={insts[n].R}")
 
 
+def spread_colours(inst):
+    """The same instance with colour c renamed 2c: every odd colour class is empty."""
+    import dataclasses
+    return dataclasses.replace(inst, color=np.ascontiguousarray(2 * np.asarray(inst.color)),
+                               n_colors=2 * inst.n_colors, name=inst.name + "_spread")
+
+
+@pytest.mark.parametrize("mode", ["latency", "classes", "bitpack"])
+def test_empty_colour_classes(ptqmc, mode):
+    """Colourings with empty classes between the used ones (colour c renamed 2c): the
+    byte kernel's latency path (which pairs class k of parity 0 with class k - 1 of parity
+    1, here often an empty one), its class-by-class sweep, and the bit-packed encoding
+    follow the oracle."""
+    rng = np.random.default_rng([1004, 29])
+    if mode == "bitpack":
+        base = [W.random_small_instance(rng, 24, 16, 12, d=4, jmax=1, hmax=1, name="oct"),
+                W.random_small_instance(rng, 9, 8, 40, d=8, jmax=1, hmax=0, name="oct8")]
+    else:
+        base = fast_batch()[1:]
+    insts = [spread_colours(i) for i in base]
+    seed = 0xE3C
+    k, cycles = 3, 10
+    flags = ptqmc.PT_FLAG_NO_LATENCY_PATH if mode == "classes" else 0
+    enc = ptqmc.PT_BITPACK32 if mode == "bitpack" else ptqmc.PT_INT8
+    shape = {} if mode == "bitpack" else dict(tile_replicas=1, block_threads=1024)
+    say(f"case: empty colour classes, {mode}")
+    refs = oracle_batch(insts, seed, k, cycles)
+    with ptqmc.Sampler(insts, seed, sweeps_per_exchange=k, flags=flags, encoding=enc,
+                       **shape) as s:
+        if mode != "bitpack":
+            assert s.info()["latency_path"] == (1 if mode == "latency" else 0)
+        s.run(cycles)
+        for n in range(len(insts)):
+            assert_same(s, n, refs[n], f"{mode} {insts[n].name}")
+
+
 def test_sixteen_bit_entries_in_small_batch(ptqmc):
     """A lone large regular +-1 instance (N = 512, M = 128, degree 8: a replica of more
     than half a compute unit's LDS, so its neighbour entries are 16 bits) with two
