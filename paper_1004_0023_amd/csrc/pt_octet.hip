@@ -434,6 +434,61 @@ __device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDe
     const int N = d.N, G4 = d.G4, lgG4 = 31 - __clz(G4);
     constexpr int lgL = SPL == 8 ? 0 : 1;  // lanes per item
     const uint32_t plane = (uint32_t)N * (uint32_t)G4 * 4u;
+    const int nc = d.n_colors;
+    if (nc >= 2) {
+        // Class k of parity 0 and class k - 1 of parity 1 (mod nc; of the previous sweep
+        // when k = 0) touch disjoint words: each writes its own sites' words of its parity
+        // and reads the other parity only at those sites.  So they run as one step, every
+        // update reading what it reads in the plain order, and a sweep is nc steps.
+        int sw = 0, k = 0;
+        for (int step = 0; step <= nc * L.n_sweeps; ++step) {
+            const int kB = (k == 0 ? nc : k) - 1, swB = sw - (k == 0 ? 1 : 0);
+            const int a0 = (int)ld32(o.coff + 4u * (uint32_t)k);
+            const int b0 = (int)ld32(o.coff + 4u * (uint32_t)kB);
+            const int itemsA = sw < L.n_sweeps
+                                   ? ((int)ld32(o.coff + 4u * (uint32_t)(k + 1)) - a0) << (lgG4 + lgL)
+                                   : 0;
+            const int itemsB = swB >= 0 && swB < L.n_sweeps
+                                   ? ((int)ld32(o.coff + 4u * (uint32_t)(kB + 1)) - b0) << (lgG4 + lgL)
+                                   : 0;
+            for (int it = tid; it < itemsA + itemsB; it += nt) {
+                const bool inA = it < itemsA;
+                const int p = inA ? 0 : 1;
+                const int jt = inA ? it : it - itemsA;
+                const uint32_t tt = (uint32_t)(t0 + (uint64_t)(inA ? sw : swB));
+                const uint32_t pb = inA ? 0u : plane, ob = inA ? plane : 0u;
+                const int half = jt & ((1 << lgL) - 1);
+                const int gg = (jt >> lgL) & (G4 - 1);
+                const int i = (int)ld16(o.csite + 2u * (uint32_t)((inA ? a0 : b0) + (jt >> (lgG4 + lgL))));
+                const uint32_t rowi = (uint32_t)(i << lgG4) * 4u;
+                const uint32_t X = ld32(pb + rowi + 4u * (uint32_t)gg);
+                const uint32_t Wc = ld32(ob + rowi + 4u * (uint32_t)gg);
+                // the other parity's word before the item's (parity 0) or after it (parity 1)
+                const uint32_t Wx = ld32(ob + rowi + 4u * (uint32_t)((gg + (inA ? -1 : 1)) & (G4 - 1)));
+                const uint32_t Tlo = inA ? __builtin_amdgcn_alignbyte(Wc, Wx, 3) : Wc;
+                const uint32_t Thi = inA ? Wc : __builtin_amdgcn_alignbyte(Wx, Wc, 1);
+                uint32_t Y[DT], nm[DT];
+#pragma unroll
+                for (int e = 0; e < DT; ++e) {
+                    uint32_t j;
+                    oct_entry(o, i * DT + e, j, nm[e]);
+                    Y[e] = ld32(pb + ((j << lgG4) + (uint32_t)gg) * 4u);
+                }
+                const OctSite site = oct_site(o, i);
+                const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)gg;
+                const uint32_t nx = oct_update<DT, SPL>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
+                                                        (uint32_t)c0, (uint32_t)n, L.key0,
+                                                        L.key1, nslots, half);
+                if (half == 0) st32(pb + rowi + 4u * (uint32_t)gg, nx);
+            }
+            __syncthreads();
+            if (++k == nc) {
+                k = 0;
+                ++sw;
+            }
+        }
+        return;
+    }
     for (int sw = 0; sw < L.n_sweeps; ++sw) {
         const uint32_t tt = (uint32_t)(t0 + (uint64_t)sw);
         for (int p = 0; p < 2; ++p) {
