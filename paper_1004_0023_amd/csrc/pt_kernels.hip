@@ -493,12 +493,12 @@ __device__ __forceinline__ void fast_item(const FastArgs &a, const TileLds &t, i
     stsw<NW>(t.sp, own, out);
 }
 
-// All colour classes of parity PAR.  A class holds ns sites x P replicas x G4/NW lanes;
-// lanes run over slice groups fastest, so the lanes of a site read one neighbour row entry
-// (broadcast) and consecutive words of each neighbour row.
+// The items of colour class g of parity PAR, with no closing barrier.  A class holds
+// ns sites x P replicas x G4/NW lanes; lanes run over slice groups fastest, so the lanes of
+// a site read one neighbour row entry (broadcast) and consecutive words of each neighbour row.
 template <int DT, int NW, int PAR, int EM>
-__device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d, const TileLds &t,
-                                           int lgGW, int lgL)
+__device__ __forceinline__ void fast_class(const FastArgs &a, const InstDesc &d, const TileLds &t,
+                                           int lgGW, int lgL, int g)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int Lmask = (1 << lgL) - 1;
@@ -511,23 +511,28 @@ __device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d,
         const int g4 = NW * (r & ((1 << lgGW) - 1));
         const int sstep = nt >> lgL;
         const int s_first = (tid < (sstep << lgL)) ? (tid >> lgL) : (1 << 30);
-        for (int g = 0; g < d.n_colors; ++g) {
-            const int s1 = t.coff[g + 1];
-            for (int si = t.coff[g] + s_first; si < s1; si += sstep)
-                fast_item<DT, NW, PAR, EM>(a, t, D, t.csite[si], q, g4);
-            __syncthreads();
-        }
+        const int s1 = t.coff[g + 1];
+        for (int si = t.coff[g] + s_first; si < s1; si += sstep)
+            fast_item<DT, NW, PAR, EM>(a, t, D, t.csite[si], q, g4);
     } else {
-        for (int g = 0; g < d.n_colors; ++g) {
-            const int s0 = t.coff[g];
-            const int items = (t.coff[g + 1] - s0) << lgL;
-            for (int it = tid; it < items; it += nt) {
-                const int r = it & Lmask;
-                fast_item<DT, NW, PAR, EM>(a, t, D, t.csite[s0 + (it >> lgL)], r >> lgGW,
+        const int s0 = t.coff[g];
+        const int items = (t.coff[g + 1] - s0) << lgL;
+        for (int it = tid; it < items; it += nt) {
+            const int r = it & Lmask;
+            fast_item<DT, NW, PAR, EM>(a, t, D, t.csite[s0 + (it >> lgL)], r >> lgGW,
                                        NW * (r & ((1 << lgGW) - 1)));
-            }
-            __syncthreads();
         }
+    }
+}
+
+// All colour classes of parity PAR, one barrier after each.
+template <int DT, int NW, int PAR, int EM>
+__device__ __forceinline__ void fast_phase(const FastArgs &a, const InstDesc &d, const TileLds &t,
+                                           int lgGW, int lgL)
+{
+    for (int g = 0; g < d.n_colors; ++g) {
+        fast_class<DT, NW, PAR, EM>(a, d, t, lgGW, lgL, g);
+        __syncthreads();
     }
 }
 
@@ -726,10 +731,32 @@ __device__ __forceinline__ void fast_sweeps(const SweepLaunch &L, const InstDesc
                 return;
             }
         }
-        for (int sw = 0; sw < L.n_sweeps; ++sw) {
-            a.tt = (uint32_t)(t0 + (uint64_t)sw);
-            fast_phase<DT, NW, 0, EM>(a, d, t, lgGW, lgL);
-            fast_phase<DT, NW, 1, EM>(a, d, t, lgGW, lgL);
+        const int nc = d.n_colors;
+        if (nc < 2) {
+            for (int sw = 0; sw < L.n_sweeps; ++sw) {
+                a.tt = (uint32_t)(t0 + (uint64_t)sw);
+                fast_phase<DT, NW, 0, EM>(a, d, t, lgGW, lgL);
+                fast_phase<DT, NW, 1, EM>(a, d, t, lgGW, lgL);
+            }
+            return;
+        }
+        // class k of parity 0 with class k - 1 of parity 1 (from the previous sweep when
+        // k = 0; the order of the latency path below), one barrier per step; the step after
+        // the last sweep finishes its last parity-1 class
+        FastArgs b = a;
+        for (int sw = 0; sw <= L.n_sweeps; ++sw) {
+            const bool tail = sw == L.n_sweeps;
+            for (int k = 0; k < (tail ? 1 : nc); ++k) {
+                if (!tail) {
+                    a.tt = (uint32_t)(t0 + (uint64_t)sw);
+                    fast_class<DT, NW, 0, EM>(a, d, t, lgGW, lgL, k);
+                }
+                if (k > 0 || sw > 0) {
+                    b.tt = (uint32_t)(t0 + (uint64_t)(sw - (k == 0)));
+                    fast_class<DT, NW, 1, EM>(b, d, t, lgGW, lgL, k > 0 ? k - 1 : nc - 1);
+                }
+                __syncthreads();
+            }
         }
     };
     // 16-bit entries are only used with two words per lane and rows of at least four
