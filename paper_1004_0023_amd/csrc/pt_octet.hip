@@ -178,14 +178,18 @@ struct OctSite {
 // masks of its D neighbours.  ctr0: Philox counter word 0 of (site, parity, global group);
 // slot 8 o + r of word group w is replica cbase + r.  A lane takes SPL of the eight slots,
 // those from SPL * half on; with SPL = 4 the two lanes of an item are neighbours and join
-// their flips with one lane exchange (both must call).
-template <int DT, int SPL>
+// their flips with one lane exchange (both must call).  MASK = false: slots is the octet's
+// count nslots and each slot is tested against it.  MASK = true: every slot is drawn and
+// looked up (the tables of all eight slots lie in LDS) and slots is the lane's flip mask
+// (oct_slot_mask), which clears the flips of slots beyond the count: no per-slot test, more
+// registers live.
+template <int DT, int SPL, bool MASK>
 __device__ __forceinline__ uint32_t oct_update(uint32_t X, uint32_t Tlo,
                                                uint32_t Thi, const uint32_t (&Y)[DT],
                                                const uint32_t (&nm)[DT], const OctSite &site,
                                                uint32_t ctr0, uint32_t tt, uint32_t cbase,
                                                uint32_t n, uint32_t key0, uint32_t key1,
-                                               int nslots, int half)
+                                               uint32_t slots, int half)
 {
     uint32_t v[9];
 #pragma unroll
@@ -211,7 +215,7 @@ __device__ __forceinline__ uint32_t oct_update(uint32_t X, uint32_t Tlo,
     uint32_t flip = 0u;
 #pragma unroll
     for (int r = 0; r < SPL; ++r) {
-        if (sh + r < nslots) {
+        if (MASK || sh + r < (int)slots) {
             const uint32_t idx = offs[r];  // table byte offsets of slot sh + r's four slices
             const Words4 u = philox10_rk(ctr0, tt, cbase + (uint32_t)(sh + r), n, key0, key1);
 #pragma unroll
@@ -222,9 +226,19 @@ __device__ __forceinline__ uint32_t oct_update(uint32_t X, uint32_t Tlo,
             }
         }
     }
+    if constexpr (MASK) flip &= slots;
     flip <<= sh;
     if constexpr (SPL < 8) flip |= (uint32_t)__shfl_xor((int)flip, 1, kWave);
     return X ^ flip;
+}
+
+// The flip mask of oct_update for a lane of the given half: in every byte, the bits of the
+// lane's SPL slots that are among the octet's nslots in use.
+template <int SPL>
+__device__ __forceinline__ uint32_t oct_slot_mask(int nslots, int half)
+{
+    const int nv = min(max(nslots - SPL * half, 0), SPL);
+    return 0x01010101u * ((1u << nv) - 1u);
 }
 
 // count elements through load(k) -> store(k, value) with up to four loads in flight per
@@ -476,9 +490,9 @@ __device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDe
                 }
                 const OctSite site = oct_site(o, i);
                 const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)gg;
-                const uint32_t nx = oct_update<DT, SPL>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
-                                                        (uint32_t)c0, (uint32_t)n, L.key0,
-                                                        L.key1, nslots, half);
+                const uint32_t nx = oct_update<DT, SPL, false>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
+                                                               (uint32_t)c0, (uint32_t)n, L.key0,
+                                                               L.key1, (uint32_t)nslots, half);
                 if (half == 0) st32(pb + rowi + 4u * (uint32_t)gg, nx);
             }
             __syncthreads();
@@ -520,9 +534,9 @@ __device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDe
                     }
                     const OctSite site = oct_site(o, i);
                     const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)gg;
-                    const uint32_t nx = oct_update<DT, SPL>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
-                                                            (uint32_t)c0, (uint32_t)n, L.key0,
-                                                            L.key1, nslots, half);
+                    const uint32_t nx = oct_update<DT, SPL, false>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
+                                                                   (uint32_t)c0, (uint32_t)n, L.key0,
+                                                                   L.key1, (uint32_t)nslots, half);
                     if (half == 0) st32(pb + rowi + 4u * (uint32_t)gg, nx);
                 }
                 __syncthreads();
@@ -694,11 +708,13 @@ __device__ __forceinline__ void oct_block_sweep(const OctLaunch &L, const InstDe
     const int tid = threadIdx.x, nt = blockDim.x;
     const int G4 = d.G4, lgng = 31 - __clz(ng);
     constexpr int lgL = SPL == 8 ? 0 : 1;  // lanes per item
+    // items come in lane pairs and the block size is even, so a thread keeps its half
+    const int half = tid & ((1 << lgL) - 1);
+    const uint32_t vmask = oct_slot_mask<SPL>(nslots, half);
     for (int g = 0; g < d.n_colors; ++g) {
         const int s0 = (int)ld32(o.coff + 4u * (uint32_t)g);
         const int items = ((int)ld32(o.coff + 4u * (uint32_t)(g + 1)) - s0) << (lgng + lgL);
         for (int it = tid; it < items; it += nt) {
-            const int half = it & ((1 << lgL) - 1);
             const uint32_t gl4 = 4u * (uint32_t)((it >> lgL) & (ng - 1));
             const int i = (int)ld16(o.csite + 2u * (uint32_t)(s0 + (it >> (lgng + lgL))));
             const uint32_t own = pl.own + (uint32_t)i * pl.own_stride + gl4;
@@ -722,9 +738,9 @@ __device__ __forceinline__ void oct_block_sweep(const OctLaunch &L, const InstDe
             }
             const OctSite site = oct_site(o, i);
             const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)g0 + (gl4 >> 2);
-            const uint32_t nx = oct_update<DT, SPL>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
-                                                    (uint32_t)c0, (uint32_t)n, L.key0, L.key1,
-                                                    nslots, half);
+            const uint32_t nx = oct_update<DT, SPL, true>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
+                                                          (uint32_t)c0, (uint32_t)n, L.key0, L.key1,
+                                                          vmask, half);
             if (half == 0) st32(own, nx);
         }
         __syncthreads();
