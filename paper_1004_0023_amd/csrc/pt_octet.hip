@@ -178,8 +178,9 @@ struct OctSite {
 // masks of its D neighbours.  ctr0: Philox counter word 0 of (site, parity, global group);
 // slot 8 o + r of word group w is replica cbase + r.  A lane takes SPL of the eight slots,
 // those from SPL * half on; with SPL = 4 the two lanes of an item are neighbours and join
-// their flips with one lane exchange (both must call).  MASK = false: slots is the octet's
-// count nslots and each slot is tested against it.  MASK = true: every slot is drawn and
+// their flips with one lane exchange (both must call).  MASK = false: slots is the number of
+// the lane's slots in use, nslots - SPL * half (at most SPL counts), and each slot is
+// tested against it.  MASK = true: every slot is drawn and
 // looked up (the tables of all eight slots lie in LDS) and slots is the lane's flip mask
 // (oct_slot_mask), which clears the flips of slots beyond the count: no per-slot test, more
 // registers live.
@@ -215,7 +216,7 @@ __device__ __forceinline__ uint32_t oct_update(uint32_t X, uint32_t Tlo,
     uint32_t flip = 0u;
 #pragma unroll
     for (int r = 0; r < SPL; ++r) {
-        if (MASK || sh + r < (int)slots) {
+        if (MASK || r < (int)slots) {
             const uint32_t idx = offs[r];  // table byte offsets of slot sh + r's four slices
             const Words4 u = philox10_rk(ctr0, tt, cbase + (uint32_t)(sh + r), n, key0, key1);
 #pragma unroll
@@ -447,6 +448,9 @@ __device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDe
     const int tid = threadIdx.x, nt = blockDim.x;
     const int N = d.N, G4 = d.G4, lgG4 = 31 - __clz(G4);
     constexpr int lgL = SPL == 8 ? 0 : 1;  // lanes per item
+    // items come in lane pairs and the block size is even, so a thread keeps its half
+    const int half = tid & ((1 << lgL) - 1);
+    const uint32_t nv = (uint32_t)(nslots - SPL * half);  // this lane's slots in use (signed)
     const uint32_t plane = (uint32_t)N * (uint32_t)G4 * 4u;
     const int nc = d.n_colors;
     if (nc >= 2) {
@@ -471,7 +475,6 @@ __device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDe
                 const int jt = inA ? it : it - itemsA;
                 const uint32_t tt = (uint32_t)(t0 + (uint64_t)(inA ? sw : swB));
                 const uint32_t pb = inA ? 0u : plane, ob = inA ? plane : 0u;
-                const int half = jt & ((1 << lgL) - 1);
                 const int gg = (jt >> lgL) & (G4 - 1);
                 const int i = (int)ld16(o.csite + 2u * (uint32_t)((inA ? a0 : b0) + (jt >> (lgG4 + lgL))));
                 const uint32_t rowi = (uint32_t)(i << lgG4) * 4u;
@@ -492,7 +495,7 @@ __device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDe
                 const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)gg;
                 const uint32_t nx = oct_update<DT, SPL, false>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
                                                                (uint32_t)c0, (uint32_t)n, L.key0,
-                                                               L.key1, (uint32_t)nslots, half);
+                                                               L.key1, nv, half);
                 if (half == 0) st32(pb + rowi + 4u * (uint32_t)gg, nx);
             }
             __syncthreads();
@@ -511,7 +514,6 @@ __device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDe
                 const int s0 = (int)ld32(o.coff + 4u * (uint32_t)g);
                 const int items = ((int)ld32(o.coff + 4u * (uint32_t)(g + 1)) - s0) << (lgG4 + lgL);
                 for (int it = tid; it < items; it += nt) {
-                    const int half = it & ((1 << lgL) - 1);
                     const int gg = (it >> lgL) & (G4 - 1);
                     const int i = (int)ld16(o.csite + 2u * (uint32_t)(s0 + (it >> (lgG4 + lgL))));
                     const uint32_t rowi = (uint32_t)(i << lgG4) * 4u;
@@ -536,7 +538,7 @@ __device__ __forceinline__ void oct_tile_sweeps(const OctLaunch &L, const InstDe
                     const uint32_t ctr0 = (uint32_t)(2 * i + p) * (uint32_t)G4 + (uint32_t)gg;
                     const uint32_t nx = oct_update<DT, SPL, false>(X, Tlo, Thi, Y, nm, site, ctr0, tt,
                                                                    (uint32_t)c0, (uint32_t)n, L.key0,
-                                                                   L.key1, (uint32_t)nslots, half);
+                                                                   L.key1, nv, half);
                     if (half == 0) st32(pb + rowi + 4u * (uint32_t)gg, nx);
                 }
                 __syncthreads();
