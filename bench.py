@@ -186,8 +186,11 @@ def main():
     ap.add_argument("--no-latency-path", action="store_true",
                     help="byte tiles of small batches: sweep without forming next items ahead")
     ap.add_argument("--tau-corr", action="store_true",
-                    help="also accumulate imaginary-time correlations at every exchange step")
+                    help="also accumulate imaginary-time correlations at every exchange step "
+                         "(byte encoding only; the default encoding then is int8)")
     args = ap.parse_args()
+    if args.tau_corr and args.encoding == "bitpack":
+        ap.error("--tau-corr needs the byte encoding (--encoding int8)")
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
@@ -202,7 +205,7 @@ def main():
     from paper_1004_0023_amd import ptqmc
 
     if args.encoding is None:
-        args.encoding = DEFAULT_ENCODING.get(args.config, "int8")
+        args.encoding = "int8" if args.tau_corr else DEFAULT_ENCODING.get(args.config, "int8")
     torch.cuda.set_device(0)
     insts, desc = workload(args.config)
     k = W.sweeps_per_exchange(args.config)

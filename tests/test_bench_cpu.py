@@ -21,6 +21,14 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in p.stderr and p.stdout == ""
 
 
+def test_tau_corr_with_packed_spins_is_refused_with_a_message():
+    # the correlations are taken from byte spins; --tau-corr alone picks that encoding
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--tau-corr",
+                        "--encoding", "bitpack"], capture_output=True, text=True, timeout=60)
+    assert p.returncode == 2
+    assert "--encoding int8" in p.stderr and p.stdout == ""
+
+
 def test_work_model():
     # Philox share 10, field d/2, time field 0.5, index 1.25, decision 3, update 0.25
     assert bench.ops_per_flip(6) == pytest.approx(18.0)
