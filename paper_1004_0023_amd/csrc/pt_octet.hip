@@ -606,11 +606,12 @@ __device__ __forceinline__ void oct_tile_item(const OctLaunch &L, char *lds, int
     oct_stage_common(st, d, lds, o, c0, nslots);
     const uint64_t t0 = st.ctr[n].t;
     __syncthreads();
-    // two lanes per item when every colour class fits half the workgroup
+    // two lanes per item when every step's items fit half the workgroup (a step sweeps two
+    // classes when there are two or more)
     int most = 0;
     for (int g = 0; g < d.n_colors; ++g)
         most = max(most, (int)(ld32(o.coff + 4u * (uint32_t)(g + 1)) - ld32(o.coff + 4u * (uint32_t)g)));
-    const bool split = (2 * most) << lgG4 <= nt;
+    const bool split = ((d.n_colors >= 2 ? 4 : 2) * most) << lgG4 <= nt;
     oct_dispatch(d.D, split, [&](auto dt, auto spl) {
         constexpr int DT = decltype(dt)::value, SPL = decltype(spl)::value;
         oct_tile_sweeps<DT, SPL>(L, d, o, n, c0, nslots, t0);
